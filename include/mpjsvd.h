@@ -1,0 +1,200 @@
+/*
+ * mpjsvd — mixed-precision one-sided Jacobi SVD for AMD Instinct MI355X (gfx950).
+ *
+ * Computes A = U diag(S) V^T for a dense FP64 matrix A (m x n, m >= n) to high
+ * relative accuracy, following Gao, Ma and Shao, "A mixed precision Jacobi SVD
+ * algorithm" (arXiv 2209.04626):
+ *   svd_plain  — Algorithm 2 + Algorithm 1: QR with column pivoting, an LQ
+ *                step, FP64 one-sided Jacobi sweeps with accumulated V.
+ *   svd_mixed  — Algorithm 4: the same QR preconditioning with pivots chosen in
+ *                FP32 (Algorithm 5), the branch tests of Section 3.5, an FP32
+ *                one-sided Jacobi SVD without V (Section 3.2), the switch
+ *                Q = qr(X^T U_low), Y = X Q (Section 3.3), and FP64 one-sided
+ *                Jacobi refinement on Y (Section 3.4).
+ *   svd_batched — the mixed path over many small matrices of uneven size in
+ *                one persistent-kernel launch.
+ *   svd_backward — the adjoint of the SVD (not in the paper): gA from U, S, V
+ *                and cotangents gU, gS, gV.
+ *
+ * Conventions shared by every entry point:
+ *   - Matrices are FP64, column-major, with a leading dimension (ld >= rows).
+ *   - All matrix/vector pointers are DEVICE pointers owned by the caller.  The
+ *     library never allocates device memory inside these calls: scratch space
+ *     is the caller's `work` buffer, sized by the matching *_workspace_size
+ *     query.  A is never modified.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued on that stream.  svd_plain / svd_mixed read convergence
+ *     and branch flags back to the host between sweeps, so they return only
+ *     when the result is complete; svd_batched and svd_backward are fully
+ *     asynchronous (stream-ordered).
+ *   - The return value checks arguments only, LAPACK style: 0 on success,
+ *     -k when argument k is invalid (k counts from 1), -100 on a HIP runtime
+ *     error.  The numerical outcome is in svd_info.status.
+ *   - Calls on different streams with different workspaces may run
+ *     concurrently; the library keeps no mutable global state.
+ */
+#ifndef MPJSVD_H
+#define MPJSVD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* svd_info.status values */
+#define SVD_OK 0
+#define SVD_WARN_NOCONV 1        /* a Jacobi phase hit its sweep cap        */
+#define SVD_ERR_NONFINITE 2      /* A holds NaN or Inf; outputs undefined   */
+#define SVD_WARN_RANK_DEFICIENT 3 /* some sigma_i == 0; U(:, i) set to zero */
+
+/* svd_opts.branch / svd_info.branch_taken (Algorithm 4's special cases) */
+#define SVD_BRANCH_AUTO 0
+#define SVD_BRANCH_LOW 1         /* run the FP32 stage and the switch       */
+#define SVD_BRANCH_SKIP 2        /* Q = I: go straight to FP64 sweeps       */
+
+#define SVD_ERR_HIP (-100)
+
+typedef struct {
+    /* Section 7.1 parameters.  tol_alg is recorded only: the low-precision
+       SVD is always the FP32 one-sided Jacobi method. */
+    double tol_alg;        /* 1e-2 */
+    double tol_orth;       /* 1e-5: skip the FP32 stage when
+                              max|X_t^T X_t - I| <= tol_orth (Section 3.5) */
+    double tol_cond_coef;  /* 1.5: skip when max|r_ii|/min|r_ii| <=
+                              tol_cond_coef * n^(1/4) (Section 3.5) */
+    double small_col_rel;  /* a column of X is "small" when its norm is
+                              <= small_col_rel * max column norm; 2^-53 */
+    double small_col_frac; /* skip when at least ceil(frac * n) trailing
+                              columns of X are small; 0.25 */
+    double eps_work;       /* FP64 rotation threshold; 0 -> sqrt(n) 2^-53 */
+    double eps_low;        /* FP32 rotation threshold; 0 -> sqrt(n) 2^-24 */
+    int maxsweep_low;      /* FP32 sweep cap (30) */
+    int maxsweep_work;     /* FP64 sweep cap (30) */
+    int want_u;            /* 1: form U (m x n) */
+    int want_v;            /* 1: form V (n x n); 0 skips V accumulation */
+    int branch;            /* SVD_BRANCH_AUTO / _LOW / _SKIP */
+    int switch_method;     /* 1: Q = qr(X^T U_low) (Section 3.3, default) */
+    int pivot_precision;   /* 32 (Algorithm 5) or 64 (plain xGEQP3) */
+    int sign_normalize;    /* 1: make the largest |V(k, i)| of each column
+                              positive (first k on ties), negating U(:, i)
+                              with it */
+    int block_cols;        /* Jacobi block width b (16 or 32); 0 = auto */
+    int inner_sweeps;      /* cap on the Jacobi sweeps run on each 2b x 2b
+                              Gram block per block pair; 0 = auto (2) */
+} svd_opts;
+
+typedef struct {
+    int status;            /* SVD_OK / SVD_WARN_* / SVD_ERR_* */
+    int branch_taken;      /* SVD_BRANCH_LOW or SVD_BRANCH_SKIP */
+    int sweeps_low;        /* FP32 sweeps executed */
+    int sweeps_work;       /* FP64 sweeps executed */
+    int n_small;           /* trailing small columns of X */
+    double orth;           /* max|X_t^T X_t - I| (FP32), -1 if not computed */
+    double cond_r;         /* max|r_ii| / min|r_ii| of the pivoted R */
+    float stage_ms[8];     /* ingest+tall QR, pivots, QR, LQ, tests,
+                              FP32 sweeps, switch, FP64 sweeps+finalise */
+} svd_info;
+
+/* Fill *o with the defaults above; mixed = 1 selects pivot_precision 32,
+   mixed = 0 selects 64. */
+void svd_default_opts(svd_opts *o, int mixed);
+
+/* Bytes of device workspace svd_plain / svd_mixed need for an m x n problem
+   with options o (NULL = defaults).  Returns 0 for invalid sizes. */
+size_t svd_workspace_size(int m, int n, const svd_opts *o);
+
+/*
+ * svd_plain: Algorithm 2 (preconditioned one-sided Jacobi) in FP64:
+ *   A = Q0 R1 if m > n (Algorithm 4, first lines), A1 P = Q1 R with FP64
+ *   Businger-Golub pivots, R = L Q2, FP64 Jacobi sweeps on X = L with V_X = I,
+ *   U = Q0 Q1 U_X, V = P Q2^T V_X.
+ * Arguments:
+ *   1 m, 2 n        sizes, m >= n >= 0
+ *   3 A, 4 lda      input, lda >= max(1, m); not modified
+ *   5 S             output, n singular values, descending, >= 0
+ *   6 U, 7 ldu      output m x n (ignored when want_u = 0; may be NULL then)
+ *   8 V, 9 ldv      output n x n (ignored when want_v = 0; may be NULL then)
+ *   10 work, 11 work_bytes  device scratch, >= svd_workspace_size(m, n, o)
+ *   12 o            options (NULL = svd_default_opts(.., 0))
+ *   13 info         HOST pointer, filled before return (may be NULL)
+ *   14 stream       hipStream_t
+ */
+int svd_plain(int m, int n, const double *A, int lda, double *S,
+              double *U, int ldu, double *V, int ldv,
+              void *work, size_t work_bytes, const svd_opts *o,
+              svd_info *info, void *stream);
+
+/*
+ * svd_mixed: Algorithm 4 with Algorithm 5 pivots.  Same arguments as
+ * svd_plain (NULL options = svd_default_opts(.., 1)).  Section 4 (Proposition
+ * 1) makes the result as accurate as svd_plain's whatever the FP32 stage
+ * delivers; the FP32 stage changes only the number of FP64 sweeps.
+ */
+int svd_mixed(int m, int n, const double *A, int lda, double *S,
+              double *U, int ldu, double *V, int ldv,
+              void *work, size_t work_bytes, const svd_opts *o,
+              svd_info *info, void *stream);
+
+/* Per-matrix result of svd_batched, written on the device. */
+typedef struct {
+    int status;
+    int branch_taken;
+    int sweeps_low;
+    int sweeps_work;
+} svd_batch_info;
+
+/*
+ * Ragged batch, packed layout: matrix j is m_j x n_j (16 <= ... ; any
+ * 1 <= n_j <= m_j <= 256 is accepted), stored column-major with ld = m_j at
+ *   A_base + offA[j],  offA[j] = sum_{i<j} m_i n_i   (same offsets for U)
+ *   S_base + offS[j],  offS[j] = sum_{i<j} n_i
+ *   V_base + offV[j],  offV[j] = sum_{i<j} n_i^2       (ld = n_j)
+ * svd_batched_plan_create (host only) validates the sizes, orders the work
+ * longest-first, picks per-size kernel parameters and reports the workspace
+ * size.  svd_batched enqueues one persistent kernel that runs the whole mixed
+ * path for every matrix (U and V are always formed).  info: device array of
+ * `batch` svd_batch_info.  The plan is immutable after creation and may be
+ * shared between streams.
+ * Returns -k for a bad argument k, as above.
+ */
+int svd_batched_plan_create(int batch, const int *h_m, const int *h_n,
+                            const svd_opts *o, void **plan, size_t *work_bytes);
+int svd_batched(void *plan, const double *A_base, double *S_base,
+                double *U_base, double *V_base, void *work, size_t work_bytes,
+                svd_batch_info *info, void *stream);
+void svd_batched_plan_destroy(void *plan);
+
+/*
+ * svd_backward: the SVD adjoint for a strided batch of equal shapes (not in
+ * the paper; the standard result for distinct singular values):
+ *   gA = U [ (F o (J - J^T)) S + diag(gS) + S (F o (K - K^T)) ] V^T
+ *        + (I - U U^T) gU S^-1 V^T,
+ *   J = U^T gU, K = V^T gV, F_ij = d / (d^2 + eta^2), d = S_j^2 - S_i^2,
+ *   eta = eps_deg * S_1^2, F_ii = 0.
+ * U (m x n, ld m) at U + b*sU, S at S + b*sS, V (n x n, ld n) at V + b*sV,
+ * gU / gV with the strides of U / V, gS with the stride of S, gA (m x n,
+ * ld m) at gA + b*sA.  Any of gU, gS, gV may be NULL (zero).  eps_deg <= 0
+ * selects 1e-12.  work >= svd_backward_workspace_size(batch, m, n) bytes.
+ * Requires m >= n >= 1; if m > n and some S_i == 0 the S^-1 term is undefined
+ * (those columns are left at zero contribution).
+ */
+size_t svd_backward_workspace_size(int batch, int m, int n);
+int svd_backward(int batch, int m, int n,
+                 const double *U, long long sU, const double *S, long long sS,
+                 const double *V, long long sV,
+                 const double *gU, const double *gS, const double *gV,
+                 double *gA, long long sA, double eps_deg,
+                 void *work, size_t work_bytes, void *stream);
+
+/* Human-readable name of a status or return code. */
+const char *svd_status_string(int code);
+
+/* Description of the HIP failure behind the last SVD_ERR_HIP return of a
+   call made on this thread ("" if none). */
+const char *svd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPJSVD_H */

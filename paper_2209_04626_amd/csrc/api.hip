@@ -1,0 +1,364 @@
+// Host orchestration of svd_plain (Algorithm 2 + Algorithm 1) and svd_mixed
+// (Algorithm 4 with the pivots of Algorithm 5), and the C ABI.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "../../include/mpjsvd.h"
+#include "common.hpp"
+#include "internal.hpp"
+
+using namespace mpj;
+
+namespace mpj {
+static thread_local char g_last_error[256] = "";
+void note_hip_error(hipError_t e, const char *where) {
+    snprintf(g_last_error, sizeof(g_last_error), "%s: %s", where, hipGetErrorString(e));
+}
+} // namespace mpj
+
+extern "C" const char *svd_last_error(void) { return mpj::g_last_error; }
+
+extern "C" void svd_default_opts(svd_opts *o, int mixed) {
+    memset(o, 0, sizeof(*o));
+    o->tol_alg = 1e-2;
+    o->tol_orth = 1e-5;
+    o->tol_cond_coef = 1.5;
+    o->small_col_rel = ldexp(1.0, -53);
+    o->small_col_frac = 0.25;
+    o->eps_work = 0.0;
+    o->eps_low = 0.0;
+    o->maxsweep_low = 30;
+    o->maxsweep_work = 30;
+    o->want_u = 1;
+    o->want_v = 1;
+    o->branch = SVD_BRANCH_AUTO;
+    o->switch_method = 1;
+    o->pivot_precision = mixed ? 32 : 64;
+    o->sign_normalize = 1;
+    o->block_cols = 0;
+    o->inner_sweeps = 0;
+}
+
+namespace {
+
+inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    int m, n, N, b;
+    size_t off_atall, off_tau0, off_t0, off_a1, off_wp, off_nrm2, off_piv, off_a1p, off_tau1,
+        off_t1, off_rt, off_tau2, off_t2, off_x, off_y, off_vacc, off_y32, off_xt, off_ulow, off_bm,
+        off_tau3, off_t3, off_ux, off_vx, off_sig, off_rank, off_nrmx, off_small, off_qr, off_jac,
+        total;
+};
+
+int pick_b(int n, const svd_opts &o) {
+    if (o.block_cols == 16 || o.block_cols == 32) return o.block_cols;
+    return n >= 256 ? 32 : 16;
+}
+
+Layout layout(int m, int n, const svd_opts &o) {
+    Layout L;
+    L.m = m; L.n = n;
+    L.N = ((n + 63) / 64) * 64;
+    if (L.N == 0) L.N = 64;
+    L.b = pick_b(n, o);
+    const size_t d = sizeof(double), f = sizeof(float);
+    const size_t nn = (size_t)n * n, NN = (size_t)L.N * L.N;
+    const size_t nblk = (size_t)cdiv(n, QR_NB) * QR_NB * QR_NB;
+    size_t p = 0;
+    auto take = [&](size_t bytes) { size_t o_ = p; p += al256(bytes); return o_; };
+    L.off_atall = take(m > n ? (size_t)m * n * d : 0);
+    L.off_tau0 = take((size_t)n * d);
+    L.off_t0 = take(nblk * d);
+    L.off_a1 = take(nn * d);
+    L.off_wp = take(nn * d);
+    L.off_nrm2 = take((size_t)2 * n * d);
+    L.off_piv = take((size_t)n * sizeof(int));
+    L.off_a1p = take(nn * d);
+    L.off_tau1 = take((size_t)n * d);
+    L.off_t1 = take(nblk * d);
+    L.off_rt = take(nn * d);
+    L.off_tau2 = take((size_t)n * d);
+    L.off_t2 = take(nblk * d);
+    L.off_x = take(NN * d);
+    L.off_y = take(NN * d);
+    L.off_vacc = take(NN * d);
+    L.off_y32 = take(NN * f);
+    L.off_xt = take(nn * f);
+    L.off_ulow = take(NN * d);
+    L.off_bm = take(nn * d);
+    L.off_tau3 = take((size_t)n * d);
+    L.off_t3 = take(nblk * d);
+    L.off_ux = take(nn * d);
+    L.off_vx = take(nn * d);
+    L.off_sig = take((size_t)n * d);
+    L.off_rank = take((size_t)n * sizeof(int));
+    L.off_nrmx = take((size_t)n * d);
+    L.off_small = take(4096);
+    L.off_qr = take(qr_scratch_doubles(m > n ? m : n, n, nullptr) * d);
+    L.off_jac = take(jacobi_scratch_bytes(L.N, L.b, (int)d));
+    L.total = p;
+    return L;
+}
+
+// layout of the small-scalar block
+struct Small {
+    int nonfinite, nzero, nsmall, pad0;
+    double cond;
+    float orth;
+    int pad1;
+};
+
+struct Timer {
+    hipEvent_t ev[9];
+    bool ok = false;
+    hipStream_t s;
+    int last = 0;
+    explicit Timer(hipStream_t st) : s(st) {
+        ok = true;
+        for (int i = 0; i < 9; ++i)
+            if (hipEventCreate(&ev[i]) != hipSuccess) ok = false;
+        if (ok) hipEventRecord(ev[0], s);
+    }
+    void mark(int stage) {  // end of stage `stage` (0..7); skipped stages get 0 ms
+        if (!ok) return;
+        for (int k = last + 1; k <= stage + 1; ++k) hipEventRecord(ev[k], s);
+        last = stage + 1;
+    }
+    void fill(svd_info *info) {
+        if (!ok) return;
+        mark(7);
+        hipEventSynchronize(ev[8]);
+        for (int i = 0; i < 8; ++i) {
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+            if (info) info->stage_ms[i] = ms;
+        }
+    }
+    ~Timer() {
+        if (ok)
+            for (int i = 0; i < 9; ++i) hipEventDestroy(ev[i]);
+    }
+};
+
+int read_back(hipStream_t s, void *host, const void *dev, size_t bytes) {
+    hipError_t e = hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        note_hip_error(e, "read_back");
+        return -1;
+    }
+    return 0;
+}
+
+int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, double *U, int ldu,
+            double *V, int ldv, void *work, size_t work_bytes, const svd_opts *op, svd_info *info,
+            void *stream) {
+    svd_opts o;
+    if (op) o = *op; else svd_default_opts(&o, mixed ? 1 : 0);
+    if (m < 0) return -1;
+    if (n < 0 || n > m) return -2;
+    if (n > 0 && !A) return -3;
+    if (lda < (m > 1 ? m : 1)) return -4;
+    if (n > 0 && !S) return -5;
+    if (o.want_u && n > 0 && !U) return -6;
+    if (o.want_u && ldu < (m > 1 ? m : 1)) return -7;
+    if (o.want_v && n > 0 && !V) return -8;
+    if (o.want_v && ldv < (n > 1 ? n : 1)) return -9;
+    if (n > 8192) return -2;
+    if (o.pivot_precision != 32 && o.pivot_precision != 64) return -12;
+    if (info) {
+        memset(info, 0, sizeof(*info));
+        info->orth = -1.0;
+    }
+    if (n == 0) return 0;
+    mpj::g_last_error[0] = 0;
+    (void)hipGetLastError();  // drop a stale error left by an earlier, unrelated call
+    const Layout L = layout(m, n, o);
+    if (!work) return -10;
+    if (work_bytes < L.total) return -11;
+
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)work;
+    auto D = [&](size_t off) { return (double *)(w + off); };
+    double *Atall = D(L.off_atall), *tau0 = D(L.off_tau0), *T0 = D(L.off_t0);
+    double *A1 = D(L.off_a1), *A1P = D(L.off_a1p), *tau1 = D(L.off_tau1), *T1 = D(L.off_t1);
+    double *Rt = D(L.off_rt), *tau2 = D(L.off_tau2), *T2 = D(L.off_t2);
+    double *X = D(L.off_x), *Y = D(L.off_y), *Vacc = D(L.off_vacc);
+    float *Y32 = (float *)(w + L.off_y32), *Xt = (float *)(w + L.off_xt);
+    double *Ulow = D(L.off_ulow), *Bm = D(L.off_bm), *tau3 = D(L.off_tau3), *T3 = D(L.off_t3);
+    double *UX = D(L.off_ux), *VX = D(L.off_vx), *sig = D(L.off_sig), *nrmX = D(L.off_nrmx);
+    int *piv = (int *)(w + L.off_piv), *rank = (int *)(w + L.off_rank);
+    Small *sm = (Small *)(w + L.off_small);
+    const int N = L.N, b = L.b;
+    const int inner = o.inner_sweeps > 0 ? o.inner_sweeps : 2;
+
+    QRScratch q;
+    qr_scratch_carve(q, D(L.off_qr), m > n ? m : n, n);
+    JacobiWork jw;
+    jacobi_carve(jw, w + L.off_jac, N, b, (int)sizeof(double));
+    int hflag = 0;
+    jw.hflag = &hflag;
+
+    Timer tm(s);
+    Small hs;
+    MPJ_CHECK(hipMemsetAsync(sm, 0, sizeof(Small), s));
+
+    // a0: ingest (A is const) and non-finite scan
+    double *Ain = (m > n) ? Atall : A1;
+    const int ldin = (m > n) ? m : n;
+    copy_scan(s, m, n, A, lda, Ain, ldin, &sm->nonfinite);
+    MPJ_CHECK(hipGetLastError());
+    if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
+    if (hs.nonfinite) {
+        if (info) info->status = SVD_ERR_NONFINITE;
+        return 0;
+    }
+    // a1: tall reduction A = Q0 R1
+    if (m > n) {
+        qr_factor(s, m, n, Atall, m, tau0, T0, q);
+        copy_upper(s, n, Atall, m, A1, n);
+    }
+    tm.mark(0);
+    // a2: pivots (Algorithm 5 in FP32, or FP64)
+    if (o.pivot_precision == 32)
+        qrcp_pivots<float>(s, n, A1, n, (float *)D(L.off_wp), (float *)D(L.off_nrm2), piv);
+    else
+        qrcp_pivots<double>(s, n, A1, n, D(L.off_wp), D(L.off_nrm2), piv);
+    tm.mark(1);
+    // a3: FP64 QR of A1 P
+    gather_cols(s, n, n, A1, n, piv, A1P, n);
+    qr_factor(s, n, n, A1P, n, tau1, T1, q);
+    tm.mark(2);
+    // a4: R = L Q2 via the QR of R^T; X = L (zero padded to N x N)
+    transpose_upper_to_lower(s, n, A1P, n, Rt, n, n);
+    qr_factor(s, n, n, Rt, n, tau2, T2, q);
+    transpose_upper_to_lower(s, n, Rt, n, X, N, N);
+    tm.mark(3);
+    MPJ_CHECK(hipGetLastError());
+
+    // a5: special cases of Section 3.5
+    int branch = SVD_BRANCH_SKIP;
+    double cond = 0.0, orth = -1.0;
+    int nsmall = 0;
+    if (mixed) {
+        diag_cond(s, n, A1P, n, &sm->cond);
+        col_norms(s, n, n, X, N, nrmX);
+        count_small(s, n, nrmX, o.small_col_rel, &sm->nsmall);
+        if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
+        cond = hs.cond;
+        nsmall = hs.nsmall;
+        const bool small_cond = cond <= o.tol_cond_coef * pow((double)n, 0.25);
+        const bool many_small = nsmall >= (int)ceil(o.small_col_frac * n);
+        bool skip = small_cond || many_small;
+        if (!skip || o.branch != SVD_BRANCH_AUTO) {
+            make_xt32(s, n, X, N, Xt, n);
+            gemm_orth_maxdev(s, n, Xt, n, &sm->orth);
+            if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
+            orth = hs.orth;
+            if (orth <= o.tol_orth) skip = true;
+        }
+        if (o.branch == SVD_BRANCH_LOW) skip = false;
+        if (o.branch == SVD_BRANCH_SKIP) skip = true;
+        branch = skip ? SVD_BRANCH_SKIP : SVD_BRANCH_LOW;
+    }
+    tm.mark(4);
+
+    const double eps_low = o.eps_low > 0 ? o.eps_low : sqrt((double)n) * ldexp(1.0, -24);
+    const double eps_work = o.eps_work > 0 ? o.eps_work : sqrt((double)n) * ldexp(1.0, -53);
+    int sweeps_low = 0, conv_low = 1;
+    if (branch == SVD_BRANCH_LOW) {
+        // a6: FP32 one-sided Jacobi on low(X), no V (Section 3.2)
+        convert_f64_f32(s, N, N, X, N, Y32, N);
+        sweeps_low = jacobi_sweeps<float>(s, N, b, Y32, nullptr, eps_low, o.maxsweep_low, inner, jw,
+                                          &conv_low);
+        if (sweeps_low < 0) return SVD_ERR_HIP;
+        normalize_f32_to_f64(s, N, N, Y32, N, Ulow, N);
+        tm.mark(5);
+        // a7: switch (Section 3.3, method of Algorithm 4): X^T U_low = Q R2, Y = X Q
+        gemm<double>(s, true, false, n, n, n, 1.0, X, N, Ulow, N, 0.0, Bm, n, q.split,
+                     q.split_elems);
+        qr_factor(s, n, n, Bm, n, tau3, T3, q);
+        set_identity(s, N, Vacc, N);
+        qr_apply_left(s, false, n, n, Bm, n, T3, n, Vacc, N, q);
+        zero_pad_fill(s, N, N, Y, N);
+        gemm<double>(s, false, false, n, n, n, 1.0, X, N, Vacc, N, 0.0, Y, N, q.split,
+                     q.split_elems);
+        tm.mark(6);
+    } else {
+        MPJ_CHECK(hipMemcpyAsync(Y, X, (size_t)N * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        set_identity(s, N, Vacc, N);
+        tm.mark(6);
+    }
+    MPJ_CHECK(hipGetLastError());
+
+    // a8: FP64 one-sided Jacobi (Algorithm 1) with V accumulated from Q
+    int conv_work = 0;
+    const int sweeps_work = jacobi_sweeps<double>(s, N, b, Y, o.want_v ? Vacc : nullptr, eps_work,
+                                                  o.maxsweep_work, inner, jw, &conv_work);
+    if (sweeps_work < 0) return SVD_ERR_HIP;
+
+    // a9: sigma, U_X, V_X sorted; U = Q0 Q1 U_X, V = P Q2^T V_X
+    finalize_sort(s, n, N, Y, Vacc, sig, rank, UX, VX, S, &sm->nzero, o.want_v != 0);
+    if (o.want_u) {
+        qr_apply_left(s, false, n, n, A1P, n, T1, n, UX, n, q);
+        place_u(s, m, n, UX, n, U, ldu);
+        if (m > n) qr_apply_left(s, false, m, n, Atall, m, T0, n, U, ldu, q);
+    }
+    if (o.want_v) {
+        qr_apply_left(s, false, n, n, Rt, n, T2, n, VX, n, q);
+        permute_rows_v(s, n, VX, n, piv, V, ldv);
+        if (o.sign_normalize) sign_normalize(s, m, n, U, ldu, o.want_u != 0, V, ldv);
+    }
+    MPJ_CHECK(hipGetLastError());
+    tm.mark(7);
+    if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
+    if (info) {
+        tm.fill(info);
+        info->branch_taken = branch;
+        info->sweeps_low = sweeps_low;
+        info->sweeps_work = sweeps_work;
+        info->n_small = nsmall;
+        info->orth = orth;
+        info->cond_r = mixed ? cond : 0.0;
+        int st = SVD_OK;
+        if (!conv_work || (branch == SVD_BRANCH_LOW && !conv_low)) st = SVD_WARN_NOCONV;
+        if (hs.nzero) st = SVD_WARN_RANK_DEFICIENT;
+        info->status = st;
+    }
+    return 0;
+}
+
+} // namespace
+
+extern "C" size_t svd_workspace_size(int m, int n, const svd_opts *op) {
+    if (m < 0 || n < 0 || n > m) return 0;
+    svd_opts o;
+    if (op) o = *op; else svd_default_opts(&o, 1);
+    if (n == 0) return 256;
+    return layout(m, n, o).total;
+}
+
+extern "C" int svd_plain(int m, int n, const double *A, int lda, double *S, double *U, int ldu,
+                         double *V, int ldv, void *work, size_t work_bytes, const svd_opts *o,
+                         svd_info *info, void *stream) {
+    return run_svd(false, m, n, A, lda, S, U, ldu, V, ldv, work, work_bytes, o, info, stream);
+}
+
+extern "C" int svd_mixed(int m, int n, const double *A, int lda, double *S, double *U, int ldu,
+                         double *V, int ldv, void *work, size_t work_bytes, const svd_opts *o,
+                         svd_info *info, void *stream) {
+    return run_svd(true, m, n, A, lda, S, U, ldu, V, ldv, work, work_bytes, o, info, stream);
+}
+
+extern "C" const char *svd_status_string(int code) {
+    switch (code) {
+    case SVD_OK: return "ok";
+    case SVD_WARN_NOCONV: return "warning: a Jacobi phase reached its sweep cap";
+    case SVD_ERR_NONFINITE: return "error: input holds NaN or Inf";
+    case SVD_WARN_RANK_DEFICIENT: return "warning: zero singular value(s)";
+    case SVD_ERR_HIP: return "error: HIP runtime failure";
+    default: return code < 0 ? "error: invalid argument" : "unknown status";
+    }
+}

@@ -1,0 +1,165 @@
+// Adjoint of the SVD for a strided batch of equal shapes (not part of the
+// paper's method; the standard result for distinct singular values).
+//
+// With J = U^T gU, K = V^T gV and F_ij = d / (d^2 + eta^2), d = s_j^2 - s_i^2
+// (F_ii = 0), the cotangent of A is
+//   gA = (U M + gU S^-1) V^T,
+//   M  = (F o (J - J^T)) S + diag(gS) + S (F o (K - K^T)) - J S^-1 [m > n],
+// where the last term and gU S^-1 together are (I - U U^T) gU S^-1 V^T.
+// One workgroup per matrix; the products run on the FP64 matrix cores with
+// 64 x 64 output tiles staged through LDS; J, K, M, Z live in the workspace.
+#include "../../include/mpjsvd.h"
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace mpj {
+
+constexpr int BW_NT = 256;
+
+// C (M x N) = op(A) op(B) (+ C when accumulate), whole workgroup, tile by tile.
+template <bool TA, bool TB>
+__device__ void wg_gemm(int M, int N, int K, const double *A, int lda, const double *B, int ldb,
+                        double *C, int ldc, bool accumulate, double (*As)[65], double (*Bs)[65]) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    for (int i0 = 0; i0 < M; i0 += 64)
+        for (int j0 = 0; j0 < N; j0 += 64) {
+            dbl4 acc[2][2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0, 0, 0, 0};
+            for (int k0 = 0; k0 < K; k0 += 16) {
+                for (int e = tid; e < 64 * 16; e += BW_NT) {
+                    int i, k;
+                    if (!TA) { i = e % 64; k = e / 64; } else { k = e % 16; i = e / 16; }
+                    const int gi = i0 + i, gk = k0 + k;
+                    double v = 0.0;
+                    if (gi < M && gk < K) v = TA ? A[(size_t)gi * lda + gk] : A[(size_t)gk * lda + gi];
+                    As[k][i] = v;
+                }
+                for (int e = tid; e < 64 * 16; e += BW_NT) {
+                    int j, k;
+                    if (!TB) { k = e % 16; j = e / 16; } else { j = e % 64; k = e / 64; }
+                    const int gj = j0 + j, gk = k0 + k;
+                    double v = 0.0;
+                    if (gj < N && gk < K) v = TB ? B[(size_t)gk * ldb + gj] : B[(size_t)gj * ldb + gk];
+                    Bs[k][j] = v;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int kk = 0; kk < 16; kk += 4) {
+                    double a[2], b[2];
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        a[t] = As[kk + lane / 16][wm * 32 + t * 16 + lane % 16];
+                        b[t] = Bs[kk + lane / 16][wn * 32 + t * 16 + lane % 16];
+                    }
+#pragma unroll
+                    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                        for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = mfma16(a[ti], b[tj], acc[ti][tj]);
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int gi = i0 + wm * 32 + ti * 16 + mfma_row<double>(lane, r);
+                        const int gj = j0 + wn * 32 + tj * 16 + lane % 16;
+                        if (gi < M && gj < N) {
+                            double *c = C + (size_t)gj * ldc + gi;
+                            *c = accumulate ? *c + acc[ti][tj][r] : acc[ti][tj][r];
+                        }
+                    }
+        }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(BW_NT) void k_svd_backward(
+    int m, int n, const double *U, long long sU, const double *S, long long sS, const double *V,
+    long long sV, const double *gU, const double *gS, const double *gV, double *gA, long long sA,
+    double eps_deg, double *work) {
+    __shared__ double As[16][65];
+    __shared__ double Bs[16][65];
+    const int bidx = blockIdx.x, tid = threadIdx.x;
+    const double *u = U + bidx * sU, *s = S + bidx * sS, *v = V + bidx * sV;
+    const double *gu = gU ? gU + bidx * sU : nullptr;
+    const double *gs = gS ? gS + bidx * sS : nullptr;
+    const double *gv = gV ? gV + bidx * sV : nullptr;
+    double *ga = gA + bidx * sA;
+    const size_t nn = (size_t)n * n;
+    double *Jw = work + (size_t)bidx * (3 * nn + (size_t)m * n);
+    double *Kw = Jw + nn, *Mw = Kw + nn, *Zw = Mw + nn;
+
+    if (gu) wg_gemm<true, false>(n, n, m, u, m, gu, m, Jw, n, false, As, Bs);
+    if (gv) wg_gemm<true, false>(n, n, n, v, n, gv, n, Kw, n, false, As, Bs);
+    double s1 = 0.0;
+    for (int i = 0; i < n; ++i) s1 = fmax(s1, s[i]);
+    const double eta = eps_deg * s1 * s1;
+    for (size_t e = tid; e < nn; e += BW_NT) {
+        const int i = (int)(e % n), j = (int)(e / n);
+        double mij = 0.0;
+        if (i == j) {
+            if (gs) mij = gs[i];
+        } else {
+            const double d = s[j] * s[j] - s[i] * s[i];
+            const double den = d * d + eta * eta;
+            const double f = den > 0.0 ? d / den : 0.0;
+            if (gu) mij += f * (Jw[(size_t)j * n + i] - Jw[(size_t)i * n + j]) * s[j];
+            if (gv) mij += s[i] * f * (Kw[(size_t)j * n + i] - Kw[(size_t)i * n + j]);
+        }
+        if (gu && m > n) mij -= s[j] > 0.0 ? Jw[(size_t)j * n + i] / s[j] : 0.0;
+        Mw[e] = mij;
+    }
+    __syncthreads();
+    // Z = U M (+ gU S^-1 when m > n)
+    if (gu && m > n) {
+        for (size_t e = tid; e < (size_t)m * n; e += BW_NT) {
+            const int j = (int)(e / m);
+            Zw[e] = s[j] > 0.0 ? gu[e] / s[j] : 0.0;
+        }
+        __syncthreads();
+        wg_gemm<false, false>(m, n, n, u, m, Mw, n, Zw, m, true, As, Bs);
+    } else {
+        wg_gemm<false, false>(m, n, n, u, m, Mw, n, Zw, m, false, As, Bs);
+    }
+    // gA = Z V^T
+    wg_gemm<false, true>(m, n, n, Zw, m, v, n, ga, m, false, As, Bs);
+}
+
+} // namespace mpj
+
+using namespace mpj;
+
+extern "C" size_t svd_backward_workspace_size(int batch, int m, int n) {
+    if (batch < 0 || m < n || n < 1) return 0;
+    return (size_t)batch * (3 * (size_t)n * n + (size_t)m * n) * sizeof(double) + 256;
+}
+
+extern "C" int svd_backward(int batch, int m, int n, const double *U, long long sU, const double *S,
+                            long long sS, const double *V, long long sV, const double *gU,
+                            const double *gS, const double *gV, double *gA, long long sA,
+                            double eps_deg, void *work, size_t work_bytes, void *stream) {
+    if (batch < 0) return -1;
+    if (m < 1 || m < n) return -2;
+    if (n < 1) return -3;
+    if (!U) return -4;
+    if (sU < (long long)m * n && batch > 1) return -5;
+    if (!S) return -6;
+    if (sS < n && batch > 1) return -7;
+    if (!V) return -8;
+    if (sV < (long long)n * n && batch > 1) return -9;
+    if (!gA) return -13;
+    if (sA < (long long)m * n && batch > 1) return -14;
+    if (batch == 0) return 0;
+    if (!work) return -16;
+    if (work_bytes < svd_backward_workspace_size(batch, m, n)) return -17;
+    if (!(eps_deg > 0.0)) eps_deg = 1e-12;
+    hipLaunchKernelGGL(k_svd_backward, dim3(batch), dim3(BW_NT), 0, (hipStream_t)stream, m, n, U, sU,
+                       S, sS, V, sV, gU, gS, gV, gA, sA, eps_deg, (double *)work);
+    return hipGetLastError() == hipSuccess ? 0 : SVD_ERR_HIP;
+}

@@ -1,0 +1,111 @@
+// Device helpers shared by the gfx950 kernels: wavefront reductions, MFMA
+// wrappers and small numeric traits.  Wavefront size is 64 throughout.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+#define MPJ_WAVE 64
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// Butterfly sum over the 64 lanes of a wavefront; every lane gets the total.
+// The summation tree is fixed, so results are bitwise reproducible.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, MPJ_WAVE);
+    return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, MPJ_WAVE);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, MPJ_WAVE));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, MPJ_WAVE));
+    return v;
+}
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, MPJ_WAVE);
+    return v;
+}
+
+// Sum over a whole workgroup of NT threads (NT a multiple of 64).  `red`
+// must hold NT/64 entries of T in LDS.  All threads receive the result.
+template <int NT, typename T>
+__device__ __forceinline__ T block_sum(T v, T *red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / MPJ_WAVE, l = threadIdx.x % MPJ_WAVE;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < NT / MPJ_WAVE; ++i) s += red[i];
+    return s;
+}
+
+template <int NT>
+__device__ __forceinline__ int block_or(int v, int *red) {
+    v = wave_or(v);
+    const int w = threadIdx.x / MPJ_WAVE, l = threadIdx.x % MPJ_WAVE;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < NT / MPJ_WAVE; ++i) s |= red[i];
+    return s;
+}
+
+// 16x16x4 MFMA, FP64 and FP32.  Operand layout for lane l of the wavefront:
+//   A (16 x 4):  A[l % 16][l / 16]
+//   B (4 x 16):  B[l / 16][l % 16]
+//   D (16 x 16): column l % 16; accumulator element r holds row
+//                mfma_row<T>(l, r): 4 (l / 16) + r for FP32, but
+//                l / 16 + 4 r for FP64 (rows interleaved across lane groups).
+// (Both checked on gfx950 with a one-wavefront probe.)
+__device__ __forceinline__ dbl4 mfma16(double a, double b, dbl4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ flt4 mfma16(float a, float b, flt4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T> __device__ __forceinline__ int mfma_row(int lane, int r);
+template <> __device__ __forceinline__ int mfma_row<double>(int lane, int r) { return lane / 16 + 4 * r; }
+template <> __device__ __forceinline__ int mfma_row<float>(int lane, int r) { return 4 * (lane / 16) + r; }
+
+template <typename T> struct acc4;
+template <> struct acc4<double> { typedef dbl4 type; };
+template <> struct acc4<float> { typedef flt4 type; };
+
+template <typename T> __device__ __forceinline__ T tsqrt(T x);
+template <> __device__ __forceinline__ double tsqrt<double>(double x) { return sqrt(x); }
+template <> __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
+
+__host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+__host__ __device__ inline long long cdivl(long long a, long long b) { return (a + b - 1) / b; }
+
+// Round-robin (circle method) tournament on nb players: in round r
+// (0 <= r < nb - 1, nb even) slot 0 pairs r with nb - 1 and slot k pairs
+// (r + k) mod (nb - 1) with (r - k) mod (nb - 1).  Returns lo < hi.
+__host__ __device__ inline void rr_slot(int nb, int r, int k, int *lo, int *hi) {
+    int a, b;
+    if (k == 0) { a = r; b = nb - 1; }
+    else {
+        const int M = nb - 1;
+        a = (r + k) % M;
+        b = ((r - k) % M + M) % M;
+    }
+    *lo = a < b ? a : b;
+    *hi = a < b ? b : a;
+}

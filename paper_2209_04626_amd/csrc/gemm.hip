@@ -1,0 +1,189 @@
+// Dense GEMM on the matrix cores (MFMA 16x16x4, FP64 or FP32), used for the
+// dense contractions of the path: blocked Householder updates (Section 3.1),
+// the switch products X^T U_low and X Q (Section 3.3), the back-transforms
+// U = Q0 Q1 U_X, V = P Q2^T V_X, and the FP32 orthogonality test
+// max|X_t^T X_t - I| of Section 3.5.
+//
+// Tiling: 64 x 64 output tile per 256-thread workgroup, 4 wavefronts in a
+// 2 x 2 arrangement, each owning 32 x 32 = 2 x 2 MFMA tiles; K staged through
+// LDS in slices of 16.  Split-K writes partial products to scratch and a
+// second kernel sums them in a fixed order (deterministic).
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace mpj {
+
+constexpr int GBM = 64, GBN = 64, GBK = 16;
+
+enum { EPI_STORE = 0, EPI_PART = 1, EPI_MAXDEV = 2 };
+
+template <typename T, bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void gemm_kernel(
+    int M, int N, int K, T alpha, const T *__restrict__ A, int lda,
+    const T *__restrict__ B, int ldb, T beta, T *C, int ldc, int kchunk,
+    T *part, float *maxdev) {
+    __shared__ T As[GBK][GBM + 1];
+    __shared__ T Bs[GBK][GBN + 1];
+    __shared__ float red[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    const int i0 = blockIdx.x * GBM, j0 = blockIdx.y * GBN;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    typedef typename acc4<T>::type V4;
+    V4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = V4{0, 0, 0, 0};
+
+    for (int k0 = kbeg; k0 < kend; k0 += GBK) {
+#pragma unroll
+        for (int rep = 0; rep < 4; ++rep) {
+            const int e = tid + 256 * rep;
+            int i, k;
+            if (!TA) { i = e % GBM; k = e / GBM; } else { k = e % GBK; i = e / GBK; }
+            const int gi = i0 + i, gk = k0 + k;
+            T v = 0;
+            if (gi < M && gk < kend)
+                v = TA ? A[(size_t)gi * lda + gk] : A[(size_t)gk * lda + gi];
+            As[k][i] = v;
+        }
+#pragma unroll
+        for (int rep = 0; rep < 4; ++rep) {
+            const int e = tid + 256 * rep;
+            int j, k;
+            if (!TB) { k = e % GBK; j = e / GBK; } else { j = e % GBN; k = e / GBN; }
+            const int gj = j0 + j, gk = k0 + k;
+            T v = 0;
+            if (gj < N && gk < kend)
+                v = TB ? B[(size_t)gk * ldb + gj] : B[(size_t)gj * ldb + gk];
+            Bs[k][j] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GBK; kk += 4) {
+            T a[2], b[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                a[t] = As[kk + lane / 16][wm * 32 + t * 16 + lane % 16];
+                b[t] = Bs[kk + lane / 16][wn * 32 + t * 16 + lane % 16];
+            }
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = mfma16(a[ti], b[tj], acc[ti][tj]);
+        }
+        __syncthreads();
+    }
+
+    float dmax = 0.f;
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = i0 + wm * 32 + ti * 16 + mfma_row<T>(lane, r);
+                const int gj = j0 + wn * 32 + tj * 16 + lane % 16;
+                if (gi < M && gj < N) {
+                    const T v = alpha * acc[ti][tj][r];
+                    if (EPI == EPI_STORE) {
+                        T *c = C + (size_t)gj * ldc + gi;
+                        *c = (beta == T(0)) ? v : v + beta * (*c);
+                    } else if (EPI == EPI_PART) {
+                        part[(size_t)blockIdx.z * M * N + (size_t)gj * M + gi] = v;
+                    } else {
+                        const float d = fabsf((float)v - (gi == gj ? 1.f : 0.f));
+                        dmax = fmaxf(dmax, d);
+                    }
+                }
+            }
+    if (EPI == EPI_MAXDEV) {
+        dmax = wave_max(dmax);
+        if (lane == 0) red[w] = dmax;
+        __syncthreads();
+        if (tid == 0) {
+            const float m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+            atomicMax((unsigned int *)maxdev, __float_as_uint(m));
+        }
+    }
+}
+
+// C = sum_z part[z] + beta C, summed in z order.
+template <typename T>
+__global__ __launch_bounds__(256) void splitk_reduce(int M, int N, int nz,
+                                                     const T *__restrict__ part, T beta,
+                                                     T *C, int ldc) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t MN = (size_t)M * N;
+    if (e >= MN) return;
+    const int i = (int)(e % M), j = (int)(e / M);
+    T s = 0;
+    for (int z = 0; z < nz; ++z) s += part[z * MN + e];
+    T *c = C + (size_t)j * ldc + i;
+    *c = (beta == T(0)) ? s : s + beta * (*c);
+}
+
+template <typename T, bool TA, bool TB>
+static void gemm_launch(hipStream_t s, int M, int N, int K, T alpha, const T *A, int lda,
+                        const T *B, int ldb, T beta, T *C, int ldc, T *split,
+                        size_t split_elems) {
+    if (M <= 0 || N <= 0) return;
+    const int tm = cdiv(M, GBM), tn = cdiv(N, GBN);
+    const int tiles = tm * tn;
+    int nz = 1;
+    if (K <= 0) {
+        // C = beta C
+        if (split) {
+            hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_STORE>), dim3(tm, tn, 1), dim3(256), 0, s,
+                               M, N, 0, alpha, A, lda, B, ldb, beta, C, ldc, 16, (T *)nullptr, (float *)nullptr);
+        } else {
+            hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_STORE>), dim3(tm, tn, 1), dim3(256), 0, s,
+                               M, N, 0, alpha, A, lda, B, ldb, beta, C, ldc, 16, (T *)nullptr, (float *)nullptr);
+        }
+        return;
+    }
+    if (split && tiles < 512 && K >= 512) {
+        nz = min(cdiv(K, 256), cdiv(1024, tiles));
+        const size_t cap = split_elems / ((size_t)M * N);
+        if ((size_t)nz > cap) nz = (int)cap;
+        if (nz < 2) nz = 1;
+    }
+    int kchunk = cdiv(cdiv(K, nz), GBK) * GBK;
+    nz = cdiv(K, kchunk);
+    if (nz == 1) {
+        hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_STORE>), dim3(tm, tn, 1), dim3(256), 0, s,
+                           M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, (T *)nullptr, (float *)nullptr);
+    } else {
+        hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_PART>), dim3(tm, tn, nz), dim3(256), 0, s,
+                           M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, split, (float *)nullptr);
+        const size_t MN = (size_t)M * N;
+        hipLaunchKernelGGL((splitk_reduce<T>), dim3((unsigned)cdivl((long long)MN, 256)), dim3(256), 0, s,
+                           M, N, nz, split, beta, C, ldc);
+    }
+}
+
+template <typename T>
+void gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, T alpha, const T *A, int lda,
+          const T *B, int ldb, T beta, T *C, int ldc, T *split, size_t split_elems) {
+    if (!ta && !tb) gemm_launch<T, false, false>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, split, split_elems);
+    else if (ta && !tb) gemm_launch<T, true, false>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, split, split_elems);
+    else if (!ta && tb) gemm_launch<T, false, true>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, split, split_elems);
+    else gemm_launch<T, true, true>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, split, split_elems);
+}
+
+template void gemm<double>(hipStream_t, bool, bool, int, int, int, double, const double *, int,
+                           const double *, int, double, double *, int, double *, size_t);
+template void gemm<float>(hipStream_t, bool, bool, int, int, int, float, const float *, int,
+                          const float *, int, float, float *, int, float *, size_t);
+
+void gemm_orth_maxdev(hipStream_t s, int n, const float *X, int ldx, float *maxdev) {
+    if (n <= 0) return;
+    const int t = cdiv(n, GBM);
+    hipLaunchKernelGGL((gemm_kernel<float, true, false, EPI_MAXDEV>), dim3(t, t, 1), dim3(256), 0, s,
+                       n, n, n, 1.0f, X, ldx, X, ldx, 0.0f, (float *)nullptr, n, cdiv(n, GBK) * GBK,
+                       (float *)nullptr, maxdev);
+}
+
+} // namespace mpj

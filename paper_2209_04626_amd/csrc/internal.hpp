@@ -1,0 +1,113 @@
+// Host-side declarations shared by the translation units of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace mpj {
+
+// ---------------------------------------------------------------- GEMM
+// C (M x N, column-major, ldc) = alpha op(A) op(B) + beta C, op = transpose
+// when ta / tb.  `split` (may be NULL) is scratch for split-K partial
+// products: split_elems doubles (or floats); without it no split is used.
+template <typename T>
+void gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, T alpha,
+          const T *A, int lda, const T *B, int ldb, T beta, T *C, int ldc,
+          T *split, size_t split_elems);
+
+// maxdev = max_{i,j < n} |(X^T X)_ij - delta_ij| for the n x n FP32 matrix
+// X (ld ldx), accumulated into *maxdev (float bits, caller zeroes it).
+void gemm_orth_maxdev(hipStream_t s, int n, const float *X, int ldx, float *maxdev);
+
+// ---------------------------------------------------------------- QR
+constexpr int QR_NB = 32;    // panel width of the blocked Householder QR
+constexpr int QR_RC = 256;   // rows per workgroup in the panel kernels
+
+struct QRScratch {
+    double *part;   // 2 * max_groups * QR_NB
+    double *head;   // 2 * QR_NB
+    double *vtv;    // max_groups * QR_NB * QR_NB
+    double *vb;     // m * QR_NB     (explicit unit-lower block of reflectors)
+    double *w1;     // QR_NB * ncols_max
+    double *w2;     // QR_NB * ncols_max
+    double *split;  // split-K scratch
+    size_t split_elems;
+};
+size_t qr_scratch_doubles(int m, int ncols_max, size_t *split_elems);
+void qr_scratch_carve(QRScratch &q, double *base, int m, int ncols_max);
+
+// Householder QR of the m x n matrix A (m >= n): R in the upper triangle,
+// reflectors below, tau[n], block factors T (ceil(n/QR_NB) blocks of
+// QR_NB x QR_NB, ld QR_NB) in Tall.
+void qr_factor(hipStream_t s, int m, int n, double *A, int lda, double *tau,
+               double *Tall, QRScratch &q);
+// C (m x ncol) <- Q C (trans = false) or Q^T C (trans = true), Q from
+// qr_factor of an m x k matrix.
+void qr_apply_left(hipStream_t s, bool trans, int m, int k, const double *Qf,
+                   int ldq, const double *Tall, int ncol, double *C, int ldc,
+                   QRScratch &q);
+
+// ---------------------------------------------------------------- QRCP
+// Businger-Golub pivot selection on a working copy of the n x n matrix A1:
+// piv[k] = column chosen at step k.  W holds n*n elements of T.
+template <typename T>
+void qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W,
+                 T *norms2, int *piv);
+
+// ---------------------------------------------------------------- Jacobi
+struct JacobiWork {
+    void *gram;      // partial Gram blocks
+    void *wmat;      // per-pair rotation blocks
+    int *skip;       // per-pair "nothing to rotate" flags
+    int *flag;       // device: any rotation this sweep
+    int *hflag;      // pinned host mirror of flag
+};
+size_t jacobi_scratch_bytes(int N, int b, int elem);
+void jacobi_carve(JacobiWork &j, char *base, int N, int b, int elem);
+// One-sided block-Jacobi sweeps on Y (N x N padded, ld N) with optional V
+// accumulation (V: N x N, ld N).  Returns the number of sweeps run; *conv set
+// to 1 if the last sweep rotated nothing.
+template <typename T>
+int jacobi_sweeps(hipStream_t s, int N, int b, T *Y, T *V, double eps,
+                  int maxsweep, int max_inner, JacobiWork &jw, int *conv);
+
+// ---------------------------------------------------------------- misc
+void copy_scan(hipStream_t s, int m, int n, const double *A, int lda,
+               double *D, int ldd, int *nonfinite);
+void copy_upper(hipStream_t s, int n, const double *R, int ldr, double *D, int ldd);
+void gather_cols(hipStream_t s, int rows, int n, const double *A, int lda,
+                 const int *piv, double *D, int ldd);
+void transpose_upper_to_lower(hipStream_t s, int n, const double *R, int ldr,
+                              double *L, int ldl, int Npad);
+void set_identity(hipStream_t s, int N, double *V, int ldv);
+void zero_pad_fill(hipStream_t s, int rows, int cols, double *D, int ldd);
+void diag_cond(hipStream_t s, int n, const double *R, int ldr, double *out);
+void col_norms(hipStream_t s, int rows, int n, const double *X, int ldx, double *nrm);
+void count_small(hipStream_t s, int n, const double *nrm, double rel, int *out);
+void make_xt32(hipStream_t s, int n, const double *X, int ldx, float *Xt, int ldt);
+void convert_f64_f32(hipStream_t s, int rows, int cols, const double *X, int ldx, float *Y, int ldy);
+void normalize_f32_to_f64(hipStream_t s, int rows, int cols, const float *Y, int ldy, double *U, int ldu);
+void finalize_sort(hipStream_t s, int n, int N, const double *Y, const double *V,
+                   double *sig, int *rank, double *UX, double *VX, double *S, int *nzero,
+                   bool want_v);
+void place_u(hipStream_t s, int m, int n, const double *W, int ldw, double *U, int ldu);
+void permute_rows_v(hipStream_t s, int n, const double *T, int ldt, const int *piv,
+                    double *V, int ldv);
+void sign_normalize(hipStream_t s, int m, int n, double *U, int ldu, bool have_u,
+                    double *V, int ldv);
+
+} // namespace mpj
+
+namespace mpj {
+// Records the first HIP failure of the current call (thread-local) so that
+// svd_last_error() can report it.
+void note_hip_error(hipError_t e, const char *where);
+}
+
+#define MPJ_CHECK(x)                                                        \
+    do {                                                                    \
+        hipError_t e_ = (x);                                                \
+        if (e_ != hipSuccess) {                                             \
+            mpj::note_hip_error(e_, #x);                                    \
+            return SVD_ERR_HIP;                                             \
+        }                                                                   \
+    } while (0)

@@ -1,0 +1,351 @@
+// One-sided Jacobi sweeps (Algorithm 1) as block-Jacobi rounds on gfx950.
+//
+// The n columns are split into blocks of b columns; each sweep runs the
+// nb - 1 rounds of a round-robin tournament over the nb blocks, so every
+// column pair (p, q) of the matrix meets in exactly one block pair per sweep
+// (pairs inside a block meet in every round).  For each block pair (I, J) of
+// a round:
+//   1. gram:   G = [Y_I Y_J]^T [Y_I Y_J] (2b x 2b) from MFMA over row chunks;
+//              FP32 data accumulates in FP32, FP64 in FP64.
+//   2. inner:  in FP64, test every column pair of the block with the rule of
+//              Algorithm 1 (|g_pq| > eps sqrt(g_pp g_qq)); if none needs it the
+//              pair is skipped.  Otherwise run cyclic Jacobi rounds on G
+//              (the rotations of Section 2.1 computed from g_pp, g_qq, g_pq
+//              exactly as from the column dot products) and accumulate the
+//              2b x 2b orthogonal product W of the rotations.
+//   3. update: [Y_I Y_J] <- [Y_I Y_J] W and [V_I V_J] <- [V_I V_J] W (MFMA).
+// Applying any orthogonal W keeps the computation rowwise backward stable
+// (the argument of Section 4), and convergence is declared only after a sweep
+// in which no block pair needed a rotation on a freshly computed Gram block.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace mpj {
+
+constexpr int JR_NT = 256;   // threads per workgroup
+constexpr int JR_RG = 256;   // rows per workgroup in gram / update
+constexpr int JR_SLAB = 32;  // rows staged in LDS at a time
+
+__device__ __forceinline__ int blk_col(int c, int b, int I, int J) {
+    return c < b ? I * b + c : J * b + (c - b);
+}
+
+template <typename T, int B2>
+__global__ __launch_bounds__(JR_NT) void jac_gram(int N, int nblk, int r, const T *__restrict__ Y,
+                                                  int ldy, T *__restrict__ Gp, int nchunk) {
+    constexpr int b = B2 / 2;
+    constexpr int NTT = B2 / 16;           // tiles per dimension
+    constexpr int TPW = (NTT * NTT + 3) / 4;
+    __shared__ T Ps[B2][JR_SLAB + 1];
+    const int pair = blockIdx.x, chunk = blockIdx.y;
+    int I, J;
+    rr_slot(nblk, r, pair, &I, &J);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    typedef typename acc4<T>::type V4;
+    V4 acc[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) acc[q] = V4{0, 0, 0, 0};
+    const int rbeg = chunk * JR_RG, rend = min(N, rbeg + JR_RG);
+    for (int r0 = rbeg; r0 < rend; r0 += JR_SLAB) {
+#pragma unroll
+        for (int e = tid; e < B2 * JR_SLAB; e += JR_NT) {
+            const int c = e / JR_SLAB, rr = e % JR_SLAB;
+            const int gi = r0 + rr;
+            Ps[c][rr] = gi < N ? Y[(size_t)blk_col(c, b, I, J) * ldy + gi] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < JR_SLAB; kk += 4) {
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                const int tile = w + 4 * q;
+                if (tile < NTT * NTT) {
+                    const int ti = tile % NTT, tj = tile / NTT;
+                    const T a = Ps[16 * ti + lane % 16][kk + lane / 16];
+                    const T bb = Ps[16 * tj + lane % 16][kk + lane / 16];
+                    acc[q] = mfma16(a, bb, acc[q]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    T *out = Gp + ((size_t)pair * nchunk + chunk) * B2 * B2;
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        const int tile = w + 4 * q;
+        if (tile < NTT * NTT) {
+            const int ti = tile % NTT, tj = tile / NTT;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = 16 * ti + mfma_row<T>(lane, e), j = 16 * tj + lane % 16;
+                out[i + j * B2] = acc[q][e];
+            }
+        }
+    }
+}
+
+// The Jacobi rotation of Section 2.1 for (alpha, beta, gamma): the root
+// closest to the identity, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+// zeta = (beta - alpha) / (2 gamma), sign(0) = +1.
+__device__ __forceinline__ void jac_rot(double al, double be, double ga, double *c, double *s,
+                                        double *t) {
+    const double zeta = (be - al) / (2.0 * ga);
+    const double sg = zeta >= 0.0 ? 1.0 : -1.0;
+    const double tt = sg / (fabs(zeta) + hypot(1.0, zeta));
+    const double cc = 1.0 / sqrt(1.0 + tt * tt);
+    *c = cc; *s = tt * cc; *t = tt;
+}
+
+template <typename T, int B2>
+__global__ __launch_bounds__(JR_NT) void jac_inner(int nchunk, const T *__restrict__ Gp,
+                                                   T *__restrict__ Wm, int *skip, int *flag,
+                                                   double eps, int max_inner) {
+    constexpr int LD = B2 + 1;
+    constexpr int H = B2 / 2;
+    __shared__ double G[B2 * LD];
+    __shared__ double W[B2 * LD];
+    __shared__ double ca[B2], cb[B2];
+    __shared__ int par[B2];
+    __shared__ double tt[H];
+    __shared__ int pp[H], qq[H];
+    __shared__ int ired[JR_NT / 64];
+    __shared__ int any_rot;
+    const int pair = blockIdx.x, tid = threadIdx.x;
+
+    // 1. reduce the partial Gram blocks (fixed order), keep the upper triangle
+    const T *gp = Gp + (size_t)pair * nchunk * B2 * B2;
+    for (int e = tid; e < B2 * B2; e += JR_NT) {
+        const int i = e % B2, j = e / B2;
+        if (i <= j) {
+            double s = 0.0;
+            for (int c = 0; c < nchunk; ++c) s += (double)gp[(size_t)c * B2 * B2 + e];
+            G[i * LD + j] = s;
+            G[j * LD + i] = s;
+        }
+        W[i * LD + j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+
+    // 2. does any pair of the block need a rotation?
+    int need = 0;
+    for (int e = tid; e < B2 * B2; e += JR_NT) {
+        const int p = e % B2, q = e / B2;
+        if (p < q) {
+            const double g = G[p * LD + q];
+            if (fabs(g) > eps * sqrt(G[p * LD + p]) * sqrt(G[q * LD + q])) need = 1;
+        }
+    }
+    need = block_or<JR_NT>(need, ired);
+    if (!need) {
+        if (tid == 0) skip[pair] = 1;
+        return;
+    }
+    if (tid == 0) { skip[pair] = 0; *flag = 1; }
+
+    // 3. cyclic rounds of disjoint rotations on G, accumulating W = prod J
+    for (int sw = 0; sw < max_inner; ++sw) {
+        __syncthreads();  // every thread has read any_rot of the last sweep
+        if (tid == 0) any_rot = 0;
+        __syncthreads();
+        for (int rd = 0; rd < B2 - 1; ++rd) {
+            if (tid < H) {
+                int p, q;
+                rr_slot(B2, rd, tid, &p, &q);
+                const double al = G[p * LD + p], be = G[q * LD + q], ga = G[p * LD + q];
+                double c = 1.0, s = 0.0, t = 0.0;
+                if (fabs(ga) > eps * sqrt(al) * sqrt(be)) {
+                    jac_rot(al, be, ga, &c, &s, &t);
+                    any_rot = 1;
+                }
+                ca[p] = c; cb[p] = -s; par[p] = q;
+                ca[q] = c; cb[q] = s;  par[q] = p;
+                tt[tid] = t; pp[tid] = p; qq[tid] = q;
+            }
+            __syncthreads();
+            // G <- J^T G J on 2x2 groups {p_a, q_a} x {p_b, q_b}, a <= b
+            for (int e = tid; e < H * H; e += JR_NT) {
+                const int a = e % H, bq = e / H;
+                if (a > bq) continue;
+                const int pa = pp[a], qa = qq[a];
+                if (a == bq) {
+                    const double t = tt[a];
+                    if (t != 0.0) {
+                        const double ga = G[pa * LD + qa];
+                        G[pa * LD + pa] -= t * ga;
+                        G[qa * LD + qa] += t * ga;
+                        G[pa * LD + qa] = 0.0;
+                        G[qa * LD + pa] = 0.0;
+                    }
+                    continue;
+                }
+                const int pb = pp[bq], qb = qq[bq];
+                const int ii[2] = {pa, qa}, jj[2] = {pb, qb};
+                double g[2][2], o[2][2];
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) g[x][y] = G[ii[x] * LD + jj[y]];
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) {
+                        const int i = ii[x], j = jj[y];
+                        o[x][y] = ca[i] * ca[j] * g[x][y] + ca[i] * cb[j] * g[x][1 - y] +
+                                  cb[i] * ca[j] * g[1 - x][y] + cb[i] * cb[j] * g[1 - x][1 - y];
+                    }
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) {
+                        G[ii[x] * LD + jj[y]] = o[x][y];
+                        G[jj[y] * LD + ii[x]] = o[x][y];
+                    }
+            }
+            // W <- W J
+            for (int e = tid; e < B2 * H; e += JR_NT) {
+                const int row = e % B2, a = e / B2;
+                const int p = pp[a], q = qq[a];
+                const double wp = W[row * LD + p], wq = W[row * LD + q];
+                W[row * LD + p] = ca[p] * wp + cb[p] * wq;
+                W[row * LD + q] = cb[q] * wp + ca[q] * wq;
+            }
+            __syncthreads();
+        }
+        const int ar = any_rot;
+        if (!ar) break;
+    }
+
+    // 4. write W (column-major, element type T)
+    T *wo = Wm + (size_t)pair * B2 * B2;
+    for (int e = tid; e < B2 * B2; e += JR_NT) {
+        const int i = e % B2, j = e / B2;
+        wo[e] = (T)W[i * LD + j];
+    }
+}
+
+template <typename T, int B2>
+__global__ __launch_bounds__(JR_NT) void jac_update(int N, int nblk, int r, T *__restrict__ Y,
+                                                    int ldy, T *__restrict__ V, int ldv,
+                                                    int nchY, const T *__restrict__ Wm,
+                                                    const int *__restrict__ skip) {
+    constexpr int b = B2 / 2;
+    constexpr int NTJ = B2 / 16;                 // column tiles
+    constexpr int NT = 2 * NTJ;                  // 2 row tiles (32 rows) x NTJ
+    constexpr int TPW = NT / 4;
+    __shared__ T Ws[B2][B2 + 1];
+    __shared__ T Ps[B2][JR_SLAB + 1];
+    const int pair = blockIdx.x;
+    if (skip[pair]) return;
+    int I, J;
+    rr_slot(nblk, r, pair, &I, &J);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const T *wsrc = Wm + (size_t)pair * B2 * B2;
+    for (int e = tid; e < B2 * B2; e += JR_NT) Ws[e % B2][e / B2] = wsrc[e];
+    T *M;
+    int ld, chunk;
+    if ((int)blockIdx.y < nchY) { M = Y; ld = ldy; chunk = blockIdx.y; }
+    else { M = V; ld = ldv; chunk = blockIdx.y - nchY; }
+    const int rbeg = chunk * JR_RG, rend = min(N, rbeg + JR_RG);
+    typedef typename acc4<T>::type V4;
+    for (int r0 = rbeg; r0 < rend; r0 += JR_SLAB) {
+        for (int e = tid; e < B2 * JR_SLAB; e += JR_NT) {
+            const int c = e / JR_SLAB, rr = e % JR_SLAB;
+            const int gi = r0 + rr;
+            Ps[c][rr] = gi < N ? M[(size_t)blk_col(c, b, I, J) * ld + gi] : T(0);
+        }
+        __syncthreads();
+        V4 acc[TPW];
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) acc[q] = V4{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < B2; kk += 4) {
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                const int tile = w + 4 * q;
+                const int ti = tile % 2, tj = tile / 2;
+                const T a = Ps[kk + lane / 16][16 * ti + lane % 16];
+                const T bb = Ws[kk + lane / 16][16 * tj + lane % 16];
+                acc[q] = mfma16(a, bb, acc[q]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int tile = w + 4 * q;
+            const int ti = tile % 2, tj = tile / 2;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = 16 * ti + mfma_row<T>(lane, e);
+                const int j = 16 * tj + lane % 16;
+                const int gi = r0 + i;
+                if (gi < N) M[(size_t)blk_col(j, b, I, J) * ld + gi] = acc[q][e];
+            }
+        }
+    }
+}
+
+size_t jacobi_scratch_bytes(int N, int b, int elem) {
+    const int B2 = 2 * b;
+    const int npairs = N / B2;
+    const int nch = cdiv(N, JR_RG);
+    size_t bytes = (size_t)npairs * nch * B2 * B2 * elem;   // gram partials
+    bytes += (size_t)npairs * B2 * B2 * elem;                // W blocks
+    bytes += (size_t)npairs * sizeof(int) + 256;             // skip flags
+    bytes += 256;                                             // flag
+    return bytes + 1024;
+}
+
+void jacobi_carve(JacobiWork &jw, char *base, int N, int b, int elem) {
+    const int B2 = 2 * b;
+    const int npairs = N / B2;
+    const int nch = cdiv(N, JR_RG);
+    char *p = base;
+    jw.gram = p; p += (size_t)npairs * nch * B2 * B2 * elem;
+    jw.wmat = p; p += (size_t)npairs * B2 * B2 * elem;
+    jw.skip = (int *)p; p += (size_t)npairs * sizeof(int) + 256;
+    jw.flag = (int *)p;
+}
+
+template <typename T, int B2>
+static int sweeps_impl(hipStream_t s, int N, T *Y, T *V, double eps, int maxsweep, int max_inner,
+                       JacobiWork &jw, int *conv) {
+    constexpr int b = B2 / 2;
+    const int nblk = N / b;
+    const int npairs = nblk / 2;
+    const int nch = cdiv(N, JR_RG);
+    const int nchV = V ? nch : 0;
+    *conv = 0;
+    int sw = 0;
+    for (; sw < maxsweep; ++sw) {
+        hipError_t e = hipMemsetAsync(jw.flag, 0, sizeof(int), s);
+        if (e != hipSuccess) { note_hip_error(e, "jacobi flag reset"); return -1; }
+        for (int r = 0; r < nblk - 1; ++r) {
+            hipLaunchKernelGGL((jac_gram<T, B2>), dim3(npairs, nch), dim3(JR_NT), 0, s, N, nblk, r, Y,
+                               N, (T *)jw.gram, nch);
+            hipLaunchKernelGGL((jac_inner<T, B2>), dim3(npairs), dim3(JR_NT), 0, s, nch,
+                               (const T *)jw.gram, (T *)jw.wmat, jw.skip, jw.flag, eps, max_inner);
+            hipLaunchKernelGGL((jac_update<T, B2>), dim3(npairs, nch + nchV), dim3(JR_NT), 0, s, N,
+                               nblk, r, Y, N, V, N, nch, (const T *)jw.wmat, jw.skip);
+        }
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(jw.hflag, jw.flag, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { note_hip_error(e, "jacobi sweep"); return -1; }
+        if (*jw.hflag == 0) { *conv = 1; ++sw; break; }
+    }
+    return sw;
+}
+
+template <typename T>
+int jacobi_sweeps(hipStream_t s, int N, int b, T *Y, T *V, double eps, int maxsweep, int max_inner,
+                  JacobiWork &jw, int *conv) {
+    if (b == 16) return sweeps_impl<T, 32>(s, N, Y, V, eps, maxsweep, max_inner, jw, conv);
+    return sweeps_impl<T, 64>(s, N, Y, V, eps, maxsweep, max_inner, jw, conv);
+}
+
+template int jacobi_sweeps<float>(hipStream_t, int, int, float *, float *, double, int, int,
+                                  JacobiWork &, int *);
+template int jacobi_sweeps<double>(hipStream_t, int, int, double *, double *, double, int, int,
+                                   JacobiWork &, int *);
+
+} // namespace mpj

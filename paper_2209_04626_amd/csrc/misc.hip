@@ -1,0 +1,301 @@
+// Memory-bound helpers of the path: ingest with the non-finite scan, layout
+// moves (gather by the pivots, transposes for the LQ step, padding), the
+// branch tests of Section 3.5 (cond_R, trailing small columns, the scaled FP32
+// copy X_t), precision conversions around the FP32 stage, and the final step
+// of Algorithm 1 (norms, stable descending sort, normalisation) plus the sign
+// rule for the singular vectors.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace mpj {
+
+static inline dim3 grid1(size_t n, int bs = 256) { return dim3((unsigned)cdivl((long long)n, bs)); }
+
+__global__ void k_copy_scan(int m, int n, const double *A, int lda, double *D, int ldd, int *nf) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)m * n) return;
+    const int i = (int)(e % m), j = (int)(e / m);
+    const double v = A[(size_t)j * lda + i];
+    D[(size_t)j * ldd + i] = v;
+    if (!isfinite(v)) *nf = 1;
+}
+void copy_scan(hipStream_t s, int m, int n, const double *A, int lda, double *D, int ldd, int *nf) {
+    if ((size_t)m * n == 0) return;
+    hipLaunchKernelGGL(k_copy_scan, grid1((size_t)m * n), dim3(256), 0, s, m, n, A, lda, D, ldd, nf);
+}
+
+__global__ void k_copy_upper(int n, const double *R, int ldr, double *D, int ldd) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)n * n) return;
+    const int i = (int)(e % n), j = (int)(e / n);
+    D[(size_t)j * ldd + i] = (i <= j) ? R[(size_t)j * ldr + i] : 0.0;
+}
+void copy_upper(hipStream_t s, int n, const double *R, int ldr, double *D, int ldd) {
+    hipLaunchKernelGGL(k_copy_upper, grid1((size_t)n * n), dim3(256), 0, s, n, R, ldr, D, ldd);
+}
+
+__global__ void k_gather_cols(int rows, int n, const double *A, int lda, const int *piv, double *D,
+                              int ldd) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)rows * n) return;
+    const int i = (int)(e % rows), k = (int)(e / rows);
+    D[(size_t)k * ldd + i] = A[(size_t)piv[k] * lda + i];
+}
+void gather_cols(hipStream_t s, int rows, int n, const double *A, int lda, const int *piv, double *D,
+                 int ldd) {
+    hipLaunchKernelGGL(k_gather_cols, grid1((size_t)rows * n), dim3(256), 0, s, rows, n, A, lda, piv,
+                       D, ldd);
+}
+
+// L (Npad x Npad, ld ldl) = [R^T 0; 0 0] for the n x n upper triangle of R.
+__global__ void k_t_upper_lower(int n, const double *R, int ldr, double *L, int ldl, int Np) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)Np * Np) return;
+    const int i = (int)(e % Np), j = (int)(e / Np);
+    double v = 0.0;
+    if (i < n && j < n && i >= j) v = R[(size_t)i * ldr + j];
+    L[(size_t)j * ldl + i] = v;
+}
+void transpose_upper_to_lower(hipStream_t s, int n, const double *R, int ldr, double *L, int ldl,
+                              int Npad) {
+    hipLaunchKernelGGL(k_t_upper_lower, grid1((size_t)Npad * Npad), dim3(256), 0, s, n, R, ldr, L, ldl,
+                       Npad);
+}
+
+__global__ void k_identity(int N, double *V, int ldv) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)N * N) return;
+    const int i = (int)(e % N), j = (int)(e / N);
+    V[(size_t)j * ldv + i] = (i == j) ? 1.0 : 0.0;
+}
+void set_identity(hipStream_t s, int N, double *V, int ldv) {
+    hipLaunchKernelGGL(k_identity, grid1((size_t)N * N), dim3(256), 0, s, N, V, ldv);
+}
+
+__global__ void k_zero(int rows, int cols, double *D, int ldd) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)rows * cols) return;
+    const int i = (int)(e % rows), j = (int)(e / rows);
+    D[(size_t)j * ldd + i] = 0.0;
+}
+void zero_pad_fill(hipStream_t s, int rows, int cols, double *D, int ldd) {
+    if ((size_t)rows * cols == 0) return;
+    hipLaunchKernelGGL(k_zero, grid1((size_t)rows * cols), dim3(256), 0, s, rows, cols, D, ldd);
+}
+
+// out[0] = max|r_ii| / min|r_ii|  (cond_R of Algorithm 4, Section 3.5)
+__global__ __launch_bounds__(256) void k_diag_cond(int n, const double *R, int ldr, double *out) {
+    __shared__ double mx[4], mn[4];
+    double a = 0.0, b = INFINITY;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double v = fabs(R[(size_t)i * ldr + i]);
+        a = fmax(a, v);
+        b = fmin(b, v);
+    }
+    a = wave_max(a);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) b = fmin(b, __shfl_xor(b, o, 64));
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { mx[w] = a; mn[w] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double A = fmax(fmax(mx[0], mx[1]), fmax(mx[2], mx[3]));
+        double B = fmin(fmin(mn[0], mn[1]), fmin(mn[2], mn[3]));
+        out[0] = (B > 0.0) ? A / B : INFINITY;
+    }
+}
+void diag_cond(hipStream_t s, int n, const double *R, int ldr, double *out) {
+    hipLaunchKernelGGL(k_diag_cond, dim3(1), dim3(256), 0, s, n, R, ldr, out);
+}
+
+__global__ __launch_bounds__(256) void k_col_norms(int rows, int n, const double *X, int ldx,
+                                                   double *nrm) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= n) return;
+    double s = 0.0;
+    for (int i = lane; i < rows; i += 64) {
+        const double v = X[(size_t)j * ldx + i];
+        s += v * v;
+    }
+    s = wave_sum(s);
+    if (lane == 0) nrm[j] = sqrt(s);
+}
+void col_norms(hipStream_t s, int rows, int n, const double *X, int ldx, double *nrm) {
+    hipLaunchKernelGGL(k_col_norms, dim3(cdiv(n, 4)), dim3(256), 0, s, rows, n, X, ldx, nrm);
+}
+
+// out[0] = length of the run of trailing columns with norm <= rel * max norm.
+__global__ __launch_bounds__(256) void k_count_small(int n, const double *nrm, double rel, int *out) {
+    __shared__ double mx[4];
+    __shared__ int first_big[4];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) a = fmax(a, nrm[i]);
+    a = wave_max(a);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) mx[w] = a;
+    __syncthreads();
+    const double thr = rel * fmax(fmax(mx[0], mx[1]), fmax(mx[2], mx[3]));
+    int last = -1;  // largest index with a norm above the threshold
+    for (int i = threadIdx.x; i < n; i += 256)
+        if (nrm[i] > thr) last = max(last, i);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) last = max(last, __shfl_xor(last, o, 64));
+    if ((threadIdx.x & 63) == 0) first_big[w] = last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int L = max(max(first_big[0], first_big[1]), max(first_big[2], first_big[3]));
+        out[0] = n - 1 - L;
+    }
+}
+void count_small(hipStream_t s, int n, const double *nrm, double rel, int *out) {
+    hipLaunchKernelGGL(k_count_small, dim3(1), dim3(256), 0, s, n, nrm, rel, out);
+}
+
+// X_t = low(X) D^-1, D_jj = FP32 2-norm of low(X)(:, j)  (Algorithm 4, Section 3.5)
+__global__ __launch_bounds__(256) void k_make_xt32(int n, const double *X, int ldx, float *Xt,
+                                                   int ldt) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= n) return;
+    float s = 0.f;
+    for (int i = lane; i < n; i += 64) {
+        const float v = (float)X[(size_t)j * ldx + i];
+        s += v * v;
+    }
+    s = wave_sum(s);
+    const float d = sqrtf(s);
+    const float inv = d > 0.f ? 1.f / d : 0.f;
+    for (int i = lane; i < n; i += 64) Xt[(size_t)j * ldt + i] = (float)X[(size_t)j * ldx + i] * inv;
+}
+void make_xt32(hipStream_t s, int n, const double *X, int ldx, float *Xt, int ldt) {
+    hipLaunchKernelGGL(k_make_xt32, dim3(cdiv(n, 4)), dim3(256), 0, s, n, X, ldx, Xt, ldt);
+}
+
+__global__ void k_f64_f32(int rows, int cols, const double *X, int ldx, float *Y, int ldy) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)rows * cols) return;
+    const int i = (int)(e % rows), j = (int)(e / rows);
+    Y[(size_t)j * ldy + i] = (float)X[(size_t)j * ldx + i];
+}
+void convert_f64_f32(hipStream_t s, int rows, int cols, const double *X, int ldx, float *Y, int ldy) {
+    hipLaunchKernelGGL(k_f64_f32, grid1((size_t)rows * cols), dim3(256), 0, s, rows, cols, X, ldx, Y,
+                       ldy);
+}
+
+// U(:, j) = double(Y(:, j) / ||Y(:, j)||), the FP32 left vectors U_low lifted to FP64.
+__global__ __launch_bounds__(256) void k_norm_f32_f64(int rows, int cols, const float *Y, int ldy,
+                                                      double *U, int ldu) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= cols) return;
+    float s = 0.f;
+    for (int i = lane; i < rows; i += 64) {
+        const float v = Y[(size_t)j * ldy + i];
+        s += v * v;
+    }
+    s = wave_sum(s);
+    const float d = sqrtf(s);
+    for (int i = lane; i < rows; i += 64) {
+        const float v = Y[(size_t)j * ldy + i];
+        U[(size_t)j * ldu + i] = d > 0.f ? (double)(v / d) : 0.0;
+    }
+}
+void normalize_f32_to_f64(hipStream_t s, int rows, int cols, const float *Y, int ldy, double *U,
+                          int ldu) {
+    hipLaunchKernelGGL(k_norm_f32_f64, dim3(cdiv(cols, 4)), dim3(256), 0, s, rows, cols, Y, ldy, U,
+                       ldu);
+}
+
+// rank_j = #{i : s_i > s_j} + #{i < j : s_i == s_j}: a stable descending order.
+__global__ void k_rank(int n, const double *sig, int *rank) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const double sj = sig[j];
+    int r = 0;
+    for (int i = 0; i < n; ++i) {
+        const double si = sig[i];
+        r += (si > sj) || (si == sj && i < j);
+    }
+    rank[j] = r;
+}
+
+// Column j of Y / V goes to column rank_j of U_X / V_X (n x n, ld n).
+__global__ __launch_bounds__(256) void k_scatter(int n, int N, const double *Y, const double *V,
+                                                 const double *sig, const int *rank, double *UX,
+                                                 double *VX, double *S, int *nzero) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= n) return;
+    const int d = rank[j];
+    const double sj = sig[j];
+    const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
+    for (int i = lane; i < n; i += 64) {
+        UX[(size_t)d * n + i] = sj > 0.0 ? Y[(size_t)j * N + i] * inv : 0.0;
+        if (V) VX[(size_t)d * n + i] = V[(size_t)j * N + i];
+    }
+    if (lane == 0) {
+        S[d] = sj;
+        if (sj == 0.0) atomicAdd(nzero, 1);
+    }
+}
+
+void finalize_sort(hipStream_t s, int n, int N, const double *Y, const double *V, double *sig,
+                   int *rank, double *UX, double *VX, double *S, int *nzero, bool want_v) {
+    col_norms(s, N, n, Y, N, sig);
+    hipLaunchKernelGGL(k_rank, dim3(cdiv(n, 256)), dim3(256), 0, s, n, sig, rank);
+    hipLaunchKernelGGL(k_scatter, dim3(cdiv(n, 4)), dim3(256), 0, s, n, N, Y, want_v ? V : nullptr,
+                       sig, rank, UX, VX, S, nzero);
+}
+
+__global__ void k_place_u(int m, int n, const double *W, int ldw, double *U, int ldu) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)m * n) return;
+    const int i = (int)(e % m), j = (int)(e / m);
+    U[(size_t)j * ldu + i] = (i < n) ? W[(size_t)j * ldw + i] : 0.0;
+}
+void place_u(hipStream_t s, int m, int n, const double *W, int ldw, double *U, int ldu) {
+    hipLaunchKernelGGL(k_place_u, grid1((size_t)m * n), dim3(256), 0, s, m, n, W, ldw, U, ldu);
+}
+
+// V(piv[k], :) = T(k, :)   (V = P T)
+__global__ void k_perm_rows(int n, const double *T, int ldt, const int *piv, double *V, int ldv) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)n * n) return;
+    const int k = (int)(e % n), j = (int)(e / n);
+    V[(size_t)j * ldv + piv[k]] = T[(size_t)j * ldt + k];
+}
+void permute_rows_v(hipStream_t s, int n, const double *T, int ldt, const int *piv, double *V,
+                    int ldv) {
+    hipLaunchKernelGGL(k_perm_rows, grid1((size_t)n * n), dim3(256), 0, s, n, T, ldt, piv, V, ldv);
+}
+
+// For column i: k = first index of max |V(k, i)|; if V(k, i) < 0 negate V(:, i), U(:, i).
+__global__ __launch_bounds__(256) void k_sign(int m, int n, double *U, int ldu, int have_u, double *V,
+                                              int ldv) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    double best = -1.0;
+    int bk = n;
+    for (int k = lane; k < n; k += 64) {
+        const double a = fabs(V[(size_t)i * ldv + k]);
+        if (a > best) { best = a; bk = k; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int okk = __shfl_xor(bk, o, 64);
+        if (ob > best || (ob == best && okk < bk)) { best = ob; bk = okk; }
+    }
+    if (V[(size_t)i * ldv + bk] < 0.0) {
+        for (int k = lane; k < n; k += 64) V[(size_t)i * ldv + k] = -V[(size_t)i * ldv + k];
+        if (have_u)
+            for (int k = lane; k < m; k += 64) U[(size_t)i * ldu + k] = -U[(size_t)i * ldu + k];
+    }
+}
+void sign_normalize(hipStream_t s, int m, int n, double *U, int ldu, bool have_u, double *V, int ldv) {
+    hipLaunchKernelGGL(k_sign, dim3(cdiv(n, 4)), dim3(256), 0, s, m, n, U, ldu, (int)have_u, V, ldv);
+}
+
+} // namespace mpj

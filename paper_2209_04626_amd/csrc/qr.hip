@@ -1,0 +1,268 @@
+// Blocked Householder QR in FP64 (the QR factorizations of Sections 2.2 and
+// 3.1: the tall reduction A = Q0 R1, the QR of A1 P after the pivots of
+// Algorithm 5, the LQ step through the QR of R^T, and the QR of X^T U_low in
+// the switch of Section 3.3).
+//
+// Panel (QR_NB columns): one launch per column.  Each workgroup owns QR_RC
+// consecutive rows of the panel, stages them in LDS, applies the reflector
+// of the current column and emits partial dot products for the next one
+// (rows below the next diagonal), so the norm and the projections of a
+// column are a single cross-workgroup reduction, read by every workgroup at
+// the start of the next launch.  The row of the next diagonal element (the
+// reflector's head) is passed through a separate buffer so no workgroup reads
+// a value another one is writing.
+// Trailing matrix: compact WY form H_0..H_{nb-1} = I - V T V^T with the LAPACK
+// xLARFT recurrence for T, applied with MFMA GEMMs.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace mpj {
+
+static_assert(QR_RC == 256, "panel kernels use one thread per row");
+constexpr int LROW = QR_RC;  // LDS column stride (all accesses are row-contiguous)
+
+// Load rows [g*RC, g*RC+RC) x columns [c0, nb) of the panel into L[k][r].
+__device__ __forceinline__ void panel_load(double *L, const double *P, int ld, int mp, int g,
+                                           int c0, int nb) {
+    const int r = threadIdx.x;
+    const int i = g * QR_RC + r;
+    for (int k = c0; k < nb; ++k) L[k * LROW + r] = (i < mp) ? P[(size_t)k * ld + i] : 0.0;
+}
+
+__device__ __forceinline__ void panel_store(const double *L, double *P, int ld, int mp, int g,
+                                            int c0, int nb) {
+    const int r = threadIdx.x;
+    const int i = g * QR_RC + r;
+    if (i < mp)
+        for (int k = c0; k < nb; ++k) P[(size_t)k * ld + i] = L[k * LROW + r];
+}
+
+// Partial dots for the reflector of column jn: over local rows i > jn,
+// part[k] = sum x_i P(i, k) for k = jn..nb-1 (k = jn gives the squared norm of
+// the part below the diagonal).  Wavefront w takes columns jn + w + 4c; its
+// lanes stride the rows.  Head row jn goes to head[k].
+__device__ void panel_partials(const double *L, int mp, int g, int jn, int nb,
+                               double *part, double *head) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    for (int k = jn + w; k < nb; k += 4) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < QR_RC / 64; ++q) {
+            const int r = lane + 64 * q;
+            const int i = g * QR_RC + r;
+            if (i > jn && i < mp) s += L[jn * LROW + r] * L[k * LROW + r];
+        }
+        s = wave_sum(s);
+        if (lane == 0) part[(size_t)g * QR_NB + k] = s;
+    }
+    const int rj = jn - g * QR_RC;
+    if (rj >= 0 && rj < QR_RC && t >= jn && t < nb) head[t] = L[t * LROW + rj];
+}
+
+__global__ __launch_bounds__(QR_RC) void qr_panel_init(int mp, int nb, const double *P, int ld,
+                                                      double *part, double *head) {
+    __shared__ double L[QR_NB * LROW];
+    const int g = blockIdx.x;
+    panel_load(L, P, ld, mp, g, 0, nb);
+    __syncthreads();
+    panel_partials(L, mp, g, 0, nb, part, head);
+}
+
+__global__ __launch_bounds__(QR_RC) void qr_panel_step(int j, int mp, int nb, int ngroups,
+                                                      double *P, int ld, double *part,
+                                                      double *head, double *tau) {
+    __shared__ double L[QR_NB * LROW];
+    __shared__ double wsh[QR_NB];
+    __shared__ double dsum[QR_NB];
+    __shared__ double prm[3];  // beta, tau, scale
+    const int g = blockIdx.x, t = threadIdx.x;
+    const double *pin = part + (size_t)(j & 1) * ngroups * QR_NB;
+    const double *hin = head + (j & 1) * QR_NB;
+    double *pout = part + (size_t)((j + 1) & 1) * ngroups * QR_NB;
+    double *hout = head + ((j + 1) & 1) * QR_NB;
+
+    // 1. cross-workgroup sums (fixed order) and the reflector of column j
+    if (t >= j && t < nb) {
+        double a = 0.0;
+        for (int q = 0; q < ngroups; ++q) a += pin[(size_t)q * QR_NB + t];
+        dsum[t] = a;
+    }
+    panel_load(L, P, ld, mp, g, j, nb);
+    __syncthreads();
+    if (t == 0) {
+        const double x0 = hin[j];
+        const double xnorm = sqrt(dsum[j]);
+        double beta = x0, tv = 0.0, scale = 0.0;
+        if (xnorm != 0.0) {
+            beta = -copysign(hypot(x0, xnorm), x0);
+            tv = (beta - x0) / beta;
+            scale = 1.0 / (x0 - beta);
+        }
+        prm[0] = beta; prm[1] = tv; prm[2] = scale;
+        if (g == 0) tau[j] = tv;
+    }
+    __syncthreads();
+    if (t > j && t < nb) wsh[t] = prm[1] * (hin[t] + prm[2] * dsum[t]);
+    __syncthreads();
+
+    // 2. apply H_j to this workgroup's rows
+    {
+        const int i = g * QR_RC + t;
+        if (i == j) {
+            L[j * LROW + t] = prm[0];
+            for (int k = j + 1; k < nb; ++k) L[k * LROW + t] -= wsh[k];
+        } else if (i > j && i < mp) {
+            const double v = L[j * LROW + t] * prm[2];
+            L[j * LROW + t] = v;
+            for (int k = j + 1; k < nb; ++k) L[k * LROW + t] -= wsh[k] * v;
+        }
+    }
+    __syncthreads();
+
+    // 3. partials for column j + 1
+    if (j + 1 < nb) panel_partials(L, mp, g, j + 1, nb, pout, hout);
+    __syncthreads();
+    panel_store(L, P, ld, mp, g, j, nb);
+}
+
+// Partial V^T V over this workgroup's rows; V unit lower trapezoidal.
+__global__ __launch_bounds__(QR_RC) void qr_vtv_partial(int mp, int nb, const double *P, int ld,
+                                                       double *vtv) {
+    __shared__ double L[QR_NB * LROW];
+    const int g = blockIdx.x, t = threadIdx.x;
+    {
+        const int i = g * QR_RC + t;
+        for (int k = 0; k < nb; ++k) {
+            double v = 0.0;
+            if (i < mp) v = (i < k) ? 0.0 : (i == k ? 1.0 : P[(size_t)k * ld + i]);
+            L[k * LROW + t] = v;
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < QR_NB * QR_NB; e += QR_RC) {
+        const int a = e % QR_NB, b = e / QR_NB;
+        double s = 0.0;
+        if (a < nb && b < nb && a <= b)
+            for (int r = 0; r < QR_RC; ++r) s += L[a * LROW + r] * L[b * LROW + r];
+        vtv[(size_t)g * QR_NB * QR_NB + e] = s;
+    }
+}
+
+// T (nb x nb upper, ld QR_NB): T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) V(:, 0:j)^T v_j.
+__global__ __launch_bounds__(256) void qr_build_t(int nb, int ngroups, const double *vtv,
+                                                  const double *tau, double *T) {
+    __shared__ double G[QR_NB * QR_NB];
+    __shared__ double Ts[QR_NB * QR_NB];
+    __shared__ double z[QR_NB];
+    const int t = threadIdx.x;
+    for (int e = t; e < QR_NB * QR_NB; e += 256) {
+        double s = 0.0;
+        for (int q = 0; q < ngroups; ++q) s += vtv[(size_t)q * QR_NB * QR_NB + e];
+        G[e] = s;
+        Ts[e] = 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        if (t < j) z[t] = -tau[j] * G[j * QR_NB + t];  // G(t, j), t < j
+        __syncthreads();
+        if (t < j) {
+            double s = 0.0;
+            for (int l = t; l < j; ++l) s += Ts[l * QR_NB + t] * z[l];
+            Ts[j * QR_NB + t] = s;
+        }
+        if (t == j) Ts[j * QR_NB + j] = tau[j];
+        __syncthreads();
+    }
+    for (int e = t; e < QR_NB * QR_NB; e += 256) T[e] = Ts[e];
+}
+
+// Vb (mp x nb, ld ldv) = explicit unit lower trapezoidal V of the panel.
+__global__ __launch_bounds__(256) void qr_extract_v(int mp, int nb, const double *P, int ld,
+                                                    double *Vb, int ldv) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)mp * nb) return;
+    const int i = (int)(e % mp), k = (int)(e / mp);
+    const double v = (i < k) ? 0.0 : (i == k ? 1.0 : P[(size_t)k * ld + i]);
+    Vb[(size_t)k * ldv + i] = v;
+}
+
+size_t qr_scratch_doubles(int m, int ncols_max, size_t *split_elems) {
+    const int G = cdiv(m, QR_RC);
+    const size_t se = (size_t)8 * QR_NB * (size_t)ncols_max;
+    if (split_elems) *split_elems = se;
+    return (size_t)2 * G * QR_NB + 2 * QR_NB + (size_t)G * QR_NB * QR_NB + (size_t)m * QR_NB +
+           2 * (size_t)QR_NB * ncols_max + se + 64;
+}
+
+void qr_scratch_carve(QRScratch &q, double *base, int m, int ncols_max) {
+    const int G = cdiv(m, QR_RC);
+    size_t se;
+    qr_scratch_doubles(m, ncols_max, &se);
+    double *p = base;
+    q.part = p; p += (size_t)2 * G * QR_NB;
+    q.head = p; p += 2 * QR_NB;
+    q.vtv = p; p += (size_t)G * QR_NB * QR_NB;
+    q.vb = p; p += (size_t)m * QR_NB;
+    q.w1 = p; p += (size_t)QR_NB * ncols_max;
+    q.w2 = p; p += (size_t)QR_NB * ncols_max;
+    q.split = p;
+    q.split_elems = se;
+}
+
+// Factor one panel (mp x nb at P) and build its T; leaves Vb filled.
+static void panel_factor(hipStream_t s, int mp, int nb, double *P, int ld, double *tau,
+                         double *T, QRScratch &q) {
+    const int G = cdiv(mp, QR_RC);
+    hipLaunchKernelGGL(qr_panel_init, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.part, q.head);
+    for (int j = 0; j < nb; ++j)
+        hipLaunchKernelGGL(qr_panel_step, dim3(G), dim3(QR_RC), 0, s, j, mp, nb, G, P, ld,
+                           q.part, q.head, tau);
+    hipLaunchKernelGGL(qr_vtv_partial, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.vtv);
+    hipLaunchKernelGGL(qr_build_t, dim3(1), dim3(256), 0, s, nb, G, q.vtv, tau, T);
+}
+
+static void extract_v(hipStream_t s, int mp, int nb, const double *P, int ld, QRScratch &q) {
+    const size_t tot = (size_t)mp * nb;
+    hipLaunchKernelGGL(qr_extract_v, dim3((unsigned)cdivl((long long)tot, 256)), dim3(256), 0, s,
+                       mp, nb, P, ld, q.vb, mp);
+}
+
+// C (mp x ncol) <- (I - V T' V^T) C with T' = T (trans = false) or T^T.
+static void apply_block(hipStream_t s, bool transT, int mp, int nb, const double *T, int ncol,
+                        double *C, int ldc, QRScratch &q) {
+    gemm<double>(s, true, false, nb, ncol, mp, 1.0, q.vb, mp, C, ldc, 0.0, q.w1, nb, q.split,
+                 q.split_elems);
+    gemm<double>(s, transT, false, nb, ncol, nb, 1.0, T, QR_NB, q.w1, nb, 0.0, q.w2, nb, nullptr, 0);
+    gemm<double>(s, false, false, mp, ncol, nb, -1.0, q.vb, mp, q.w2, nb, 1.0, C, ldc, nullptr, 0);
+}
+
+void qr_factor(hipStream_t s, int m, int n, double *A, int lda, double *tau, double *Tall,
+               QRScratch &q) {
+    for (int c0 = 0, blk = 0; c0 < n; c0 += QR_NB, ++blk) {
+        const int nb = min(QR_NB, n - c0);
+        const int mp = m - c0;
+        double *P = A + (size_t)c0 * lda + c0;
+        double *T = Tall + (size_t)blk * QR_NB * QR_NB;
+        panel_factor(s, mp, nb, P, lda, tau + c0, T, q);
+        const int nt = n - c0 - nb;
+        if (nt > 0) {
+            extract_v(s, mp, nb, P, lda, q);
+            apply_block(s, true, mp, nb, T, nt, P + (size_t)nb * lda, lda, q);
+        }
+    }
+}
+
+void qr_apply_left(hipStream_t s, bool trans, int m, int k, const double *Qf, int ldq,
+                   const double *Tall, int ncol, double *C, int ldc, QRScratch &q) {
+    const int nblk = cdiv(k, QR_NB);
+    for (int t = 0; t < nblk; ++t) {
+        const int blk = trans ? t : nblk - 1 - t;
+        const int c0 = blk * QR_NB;
+        const int nb = min(QR_NB, k - c0);
+        const int mp = m - c0;
+        extract_v(s, mp, nb, Qf + (size_t)c0 * ldq + c0, ldq, q);
+        apply_block(s, trans, mp, nb, Tall + (size_t)blk * QR_NB * QR_NB, ncol, C + c0, ldc, q);
+    }
+}
+
+} // namespace mpj
