@@ -81,7 +81,7 @@ typedef struct {
                               with it */
     int block_cols;        /* Jacobi block width b (16 or 32); 0 = auto */
     int inner_sweeps;      /* cap on the Jacobi sweeps run on each 2b x 2b
-                              Gram block per block pair; 0 = auto (2) */
+                              Gram block per block pair; 0 = auto (1) */
 } svd_opts;
 
 typedef struct {

@@ -54,7 +54,7 @@ struct Layout {
 
 int pick_b(int n, const svd_opts &o) {
     if (o.block_cols == 16 || o.block_cols == 32) return o.block_cols;
-    return n >= 256 ? 32 : 16;
+    return 16;
 }
 
 Layout layout(int m, int n, const svd_opts &o) {
@@ -192,7 +192,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     int *piv = (int *)(w + L.off_piv), *rank = (int *)(w + L.off_rank);
     Small *sm = (Small *)(w + L.off_small);
     const int N = L.N, b = L.b;
-    const int inner = o.inner_sweeps > 0 ? o.inner_sweeps : 2;
+    const int inner = o.inner_sweeps > 0 ? o.inner_sweeps : 1;
 
     QRScratch q;
     qr_scratch_carve(q, D(L.off_qr), m > n ? m : n, n);

@@ -48,7 +48,8 @@ void qr_apply_left(hipStream_t s, bool trans, int m, int k, const double *Qf,
 
 // ---------------------------------------------------------------- QRCP
 // Businger-Golub pivot selection on a working copy of the n x n matrix A1:
-// piv[k] = column chosen at step k.  W holds n*n elements of T.
+// piv[k] = column chosen at step k.  W holds n*n elements of T; norms2 holds
+// 2n elements of T.
 template <typename T>
 void qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W,
                  T *norms2, int *piv);

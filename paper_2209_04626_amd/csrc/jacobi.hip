@@ -23,7 +23,8 @@
 namespace mpj {
 
 constexpr int JR_NT = 256;   // threads per workgroup
-constexpr int JR_RG = 256;   // rows per workgroup in gram / update
+constexpr int JR_RG = 256;   // rows per workgroup in update
+constexpr int JR_RGG = 1024; // rows per workgroup in gram
 constexpr int JR_SLAB = 32;  // rows staged in LDS at a time
 
 __device__ __forceinline__ int blk_col(int c, int b, int I, int J) {
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(JR_NT) void jac_gram(int N, int nblk, int r, const 
     V4 acc[TPW];
 #pragma unroll
     for (int q = 0; q < TPW; ++q) acc[q] = V4{0, 0, 0, 0};
-    const int rbeg = chunk * JR_RG, rend = min(N, rbeg + JR_RG);
+    const int rbeg = chunk * JR_RGG, rend = min(N, rbeg + JR_RGG);
     for (int r0 = rbeg; r0 < rend; r0 += JR_SLAB) {
 #pragma unroll
         for (int e = tid; e < B2 * JR_SLAB; e += JR_NT) {
@@ -91,51 +92,72 @@ __device__ __forceinline__ void jac_rot(double al, double be, double ga, double 
                                         double *t) {
     const double zeta = (be - al) / (2.0 * ga);
     const double sg = zeta >= 0.0 ? 1.0 : -1.0;
-    const double tt = sg / (fabs(zeta) + hypot(1.0, zeta));
+    const double az = fabs(zeta);
+    // sqrt(1 + zeta^2) without overflow: for |zeta| > 1e150 it is |zeta|
+    const double root = az > 1e150 ? az : sqrt(1.0 + az * az);
+    const double tt = sg / (az + root);
     const double cc = 1.0 / sqrt(1.0 + tt * tt);
     *c = cc; *s = tt * cc; *t = tt;
 }
 
-template <typename T, int B2>
-__global__ __launch_bounds__(JR_NT) void jac_inner(int nchunk, const T *__restrict__ Gp,
-                                                   T *__restrict__ Wm, int *skip, int *flag,
-                                                   double eps, int max_inner) {
+// Inner solve of one block pair.  G and the accumulated W are held in the
+// stage's precision T (FP32 in the FP32 stage, FP64 in the FP64 stage); every
+// rotation angle and threshold test is evaluated in FP64.  The rotation test
+// |g_pq| > eps sqrt(g_pp g_qq) is evaluated squared (no square roots).  Each
+// round loads all of a thread's 2x2 groups of G and W entries first, then
+// updates and stores them, so the LDS latency is paid once per round.
+template <typename T, int B2, int NT>
+__global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict__ Gp,
+                                                T *__restrict__ Wm, int *skip, int *flag,
+                                                double eps, int max_inner) {
     constexpr int LD = B2 + 1;
     constexpr int H = B2 / 2;
-    __shared__ double G[B2 * LD];
-    __shared__ double W[B2 * LD];
-    __shared__ double ca[B2], cb[B2];
-    __shared__ int par[B2];
-    __shared__ double tt[H];
-    __shared__ int pp[H], qq[H];
-    __shared__ int ired[JR_NT / 64];
+    constexpr int TG = (H * H) / NT;      // 2x2 groups of G per thread
+    constexpr int TW = (B2 * H) / NT;     // W column-pair entries per thread
+    constexpr int TE = (B2 * B2) / NT;    // Gram entries per thread
+    static_assert(TG * NT == H * H && TW * NT == B2 * H && TE * NT == B2 * B2, "tiling");
+    __shared__ T G[B2 * LD];
+    __shared__ T W[B2 * LD];
+    __shared__ T ca[B2], cb[B2];
+    __shared__ T tt[H];
+    __shared__ int ired[NT / 64 > 0 ? NT / 64 : 1];
     __shared__ int any_rot;
     const int pair = blockIdx.x, tid = threadIdx.x;
+    const double eps2 = eps * eps;
 
-    // 1. reduce the partial Gram blocks (fixed order), keep the upper triangle
-    const T *gp = Gp + (size_t)pair * nchunk * B2 * B2;
-    for (int e = tid; e < B2 * B2; e += JR_NT) {
-        const int i = e % B2, j = e / B2;
-        if (i <= j) {
-            double s = 0.0;
-            for (int c = 0; c < nchunk; ++c) s += (double)gp[(size_t)c * B2 * B2 + e];
-            G[i * LD + j] = s;
-            G[j * LD + i] = s;
+    // 1. reduce the partial Gram blocks (fixed chunk order, FP64 sums)
+    {
+        const T *gp = Gp + (size_t)pair * nchunk * B2 * B2;
+        double acc[TE];
+#pragma unroll
+        for (int k = 0; k < TE; ++k) acc[k] = 0.0;
+        for (int c = 0; c < nchunk; ++c) {
+            T v[TE];
+#pragma unroll
+            for (int k = 0; k < TE; ++k) v[k] = gp[(size_t)c * B2 * B2 + tid + k * NT];
+#pragma unroll
+            for (int k = 0; k < TE; ++k) acc[k] += (double)v[k];
         }
-        W[i * LD + j] = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < TE; ++k) {
+            const int e = tid + k * NT, i = e % B2, j = e / B2;
+            if (i <= j) { G[i * LD + j] = (T)acc[k]; G[j * LD + i] = (T)acc[k]; }
+            W[i * LD + j] = (i == j) ? T(1) : T(0);
+        }
     }
     __syncthreads();
 
     // 2. does any pair of the block need a rotation?
     int need = 0;
-    for (int e = tid; e < B2 * B2; e += JR_NT) {
-        const int p = e % B2, q = e / B2;
+#pragma unroll
+    for (int k = 0; k < TE; ++k) {
+        const int e = tid + k * NT, p = e % B2, q = e / B2;
         if (p < q) {
-            const double g = G[p * LD + q];
-            if (fabs(g) > eps * sqrt(G[p * LD + p]) * sqrt(G[q * LD + q])) need = 1;
+            const double g = (double)G[p * LD + q];
+            if (g * g > eps2 * (double)G[p * LD + p] * (double)G[q * LD + q]) need = 1;
         }
     }
-    need = block_or<JR_NT>(need, ired);
+    need = block_or<NT>(need, ired);
     if (!need) {
         if (tid == 0) skip[pair] = 1;
         return;
@@ -144,70 +166,87 @@ __global__ __launch_bounds__(JR_NT) void jac_inner(int nchunk, const T *__restri
 
     // 3. cyclic rounds of disjoint rotations on G, accumulating W = prod J
     for (int sw = 0; sw < max_inner; ++sw) {
-        __syncthreads();  // every thread has read any_rot of the last sweep
+        __syncthreads();
         if (tid == 0) any_rot = 0;
         __syncthreads();
         for (int rd = 0; rd < B2 - 1; ++rd) {
             if (tid < H) {
                 int p, q;
                 rr_slot(B2, rd, tid, &p, &q);
-                const double al = G[p * LD + p], be = G[q * LD + q], ga = G[p * LD + q];
+                const double al = (double)G[p * LD + p], be = (double)G[q * LD + q];
+                const double ga = (double)G[p * LD + q];
                 double c = 1.0, s = 0.0, t = 0.0;
-                if (fabs(ga) > eps * sqrt(al) * sqrt(be)) {
+                if (ga * ga > eps2 * al * be) {
                     jac_rot(al, be, ga, &c, &s, &t);
                     any_rot = 1;
                 }
-                ca[p] = c; cb[p] = -s; par[p] = q;
-                ca[q] = c; cb[q] = s;  par[q] = p;
-                tt[tid] = t; pp[tid] = p; qq[tid] = q;
+                ca[p] = (T)c; cb[p] = (T)(-s);
+                ca[q] = (T)c; cb[q] = (T)s;
+                tt[tid] = (T)t;
             }
             __syncthreads();
-            // G <- J^T G J on 2x2 groups {p_a, q_a} x {p_b, q_b}, a <= b
-            for (int e = tid; e < H * H; e += JR_NT) {
-                const int a = e % H, bq = e / H;
-                if (a > bq) continue;
-                const int pa = pp[a], qa = qq[a];
-                if (a == bq) {
-                    const double t = tt[a];
-                    if (t != 0.0) {
-                        const double ga = G[pa * LD + qa];
-                        G[pa * LD + pa] -= t * ga;
-                        G[qa * LD + qa] += t * ga;
-                        G[pa * LD + qa] = 0.0;
-                        G[qa * LD + pa] = 0.0;
+            // G <- J^T G J on the 2x2 groups {p_a, q_a} x {p_b, q_b}, a <= b
+            int gi[TG][2], gj[TG][2];
+            T g[TG][2][2], ci[TG][2], si[TG][2], cj[TG][2], sj[TG][2];
+            bool act[TG], diag[TG];
+#pragma unroll
+            for (int k = 0; k < TG; ++k) {
+                const int e = tid + k * NT, a = e % H, bq = e / H;
+                act[k] = a <= bq;
+                diag[k] = a == bq;
+                rr_slot(B2, rd, a, &gi[k][0], &gi[k][1]);
+                rr_slot(B2, rd, bq, &gj[k][0], &gj[k][1]);
+#pragma unroll
+                for (int x = 0; x < 2; ++x) {
+                    ci[k][x] = ca[gi[k][x]]; si[k][x] = cb[gi[k][x]];
+                    cj[k][x] = ca[gj[k][x]]; sj[k][x] = cb[gj[k][x]];
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) g[k][x][y] = G[gi[k][x] * LD + gj[k][y]];
+                }
+            }
+            // W column pairs
+            int wr[TW], wp[TW], wq[TW];
+            T w0[TW], w1[TW], cp[TW], sp[TW], cq[TW], sq[TW];
+#pragma unroll
+            for (int k = 0; k < TW; ++k) {
+                const int e = tid + k * NT;
+                wr[k] = e % B2;
+                rr_slot(B2, rd, e / B2, &wp[k], &wq[k]);
+                w0[k] = W[wr[k] * LD + wp[k]]; w1[k] = W[wr[k] * LD + wq[k]];
+                cp[k] = ca[wp[k]]; sp[k] = cb[wp[k]]; cq[k] = ca[wq[k]]; sq[k] = cb[wq[k]];
+            }
+            T tdiag[TG];
+#pragma unroll
+            for (int k = 0; k < TG; ++k) tdiag[k] = diag[k] ? tt[(tid + k * NT) % H] : T(0);
+            // each G / W entry is read and written by the same thread within a
+            // round, so no barrier is needed between the loads and the stores
+#pragma unroll
+            for (int k = 0; k < TG; ++k) {
+                if (!act[k]) continue;
+                if (diag[k]) {
+                    const T t = tdiag[k], gpq = g[k][0][1];
+                    if (t != T(0)) {
+                        G[gi[k][0] * LD + gi[k][0]] = g[k][0][0] - t * gpq;
+                        G[gi[k][1] * LD + gi[k][1]] = g[k][1][1] + t * gpq;
+                        G[gi[k][0] * LD + gi[k][1]] = T(0);
+                        G[gi[k][1] * LD + gi[k][0]] = T(0);
                     }
                     continue;
                 }
-                const int pb = pp[bq], qb = qq[bq];
-                const int ii[2] = {pa, qa}, jj[2] = {pb, qb};
-                double g[2][2], o[2][2];
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) g[x][y] = G[ii[x] * LD + jj[y]];
 #pragma unroll
                 for (int x = 0; x < 2; ++x)
 #pragma unroll
                     for (int y = 0; y < 2; ++y) {
-                        const int i = ii[x], j = jj[y];
-                        o[x][y] = ca[i] * ca[j] * g[x][y] + ca[i] * cb[j] * g[x][1 - y] +
-                                  cb[i] * ca[j] * g[1 - x][y] + cb[i] * cb[j] * g[1 - x][1 - y];
-                    }
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) {
-                        G[ii[x] * LD + jj[y]] = o[x][y];
-                        G[jj[y] * LD + ii[x]] = o[x][y];
+                        const T o = ci[k][x] * cj[k][y] * g[k][x][y] + ci[k][x] * sj[k][y] * g[k][x][1 - y] +
+                                    si[k][x] * cj[k][y] * g[k][1 - x][y] + si[k][x] * sj[k][y] * g[k][1 - x][1 - y];
+                        G[gi[k][x] * LD + gj[k][y]] = o;
+                        G[gj[k][y] * LD + gi[k][x]] = o;
                     }
             }
-            // W <- W J
-            for (int e = tid; e < B2 * H; e += JR_NT) {
-                const int row = e % B2, a = e / B2;
-                const int p = pp[a], q = qq[a];
-                const double wp = W[row * LD + p], wq = W[row * LD + q];
-                W[row * LD + p] = ca[p] * wp + cb[p] * wq;
-                W[row * LD + q] = cb[q] * wp + ca[q] * wq;
+#pragma unroll
+            for (int k = 0; k < TW; ++k) {
+                W[wr[k] * LD + wp[k]] = cp[k] * w0[k] + sp[k] * w1[k];
+                W[wr[k] * LD + wq[k]] = sq[k] * w0[k] + cq[k] * w1[k];
             }
             __syncthreads();
         }
@@ -215,11 +254,12 @@ __global__ __launch_bounds__(JR_NT) void jac_inner(int nchunk, const T *__restri
         if (!ar) break;
     }
 
-    // 4. write W (column-major, element type T)
+    // 4. write W (column-major)
     T *wo = Wm + (size_t)pair * B2 * B2;
-    for (int e = tid; e < B2 * B2; e += JR_NT) {
-        const int i = e % B2, j = e / B2;
-        wo[e] = (T)W[i * LD + j];
+#pragma unroll
+    for (int k = 0; k < TE; ++k) {
+        const int e = tid + k * NT, i = e % B2, j = e / B2;
+        wo[e] = W[i * LD + j];
     }
 }
 
@@ -287,7 +327,7 @@ __global__ __launch_bounds__(JR_NT) void jac_update(int N, int nblk, int r, T *_
 size_t jacobi_scratch_bytes(int N, int b, int elem) {
     const int B2 = 2 * b;
     const int npairs = N / B2;
-    const int nch = cdiv(N, JR_RG);
+    const int nch = cdiv(N, JR_RGG);
     size_t bytes = (size_t)npairs * nch * B2 * B2 * elem;   // gram partials
     bytes += (size_t)npairs * B2 * B2 * elem;                // W blocks
     bytes += (size_t)npairs * sizeof(int) + 256;             // skip flags
@@ -298,7 +338,7 @@ size_t jacobi_scratch_bytes(int N, int b, int elem) {
 void jacobi_carve(JacobiWork &jw, char *base, int N, int b, int elem) {
     const int B2 = 2 * b;
     const int npairs = N / B2;
-    const int nch = cdiv(N, JR_RG);
+    const int nch = cdiv(N, JR_RGG);
     char *p = base;
     jw.gram = p; p += (size_t)npairs * nch * B2 * B2 * elem;
     jw.wmat = p; p += (size_t)npairs * B2 * B2 * elem;
@@ -306,13 +346,14 @@ void jacobi_carve(JacobiWork &jw, char *base, int N, int b, int elem) {
     jw.flag = (int *)p;
 }
 
-template <typename T, int B2>
+template <typename T, int B2, int INNER_NT>
 static int sweeps_impl(hipStream_t s, int N, T *Y, T *V, double eps, int maxsweep, int max_inner,
                        JacobiWork &jw, int *conv) {
     constexpr int b = B2 / 2;
     const int nblk = N / b;
     const int npairs = nblk / 2;
     const int nch = cdiv(N, JR_RG);
+    const int nchG = cdiv(N, JR_RGG);
     const int nchV = V ? nch : 0;
     *conv = 0;
     int sw = 0;
@@ -320,9 +361,9 @@ static int sweeps_impl(hipStream_t s, int N, T *Y, T *V, double eps, int maxswee
         hipError_t e = hipMemsetAsync(jw.flag, 0, sizeof(int), s);
         if (e != hipSuccess) { note_hip_error(e, "jacobi flag reset"); return -1; }
         for (int r = 0; r < nblk - 1; ++r) {
-            hipLaunchKernelGGL((jac_gram<T, B2>), dim3(npairs, nch), dim3(JR_NT), 0, s, N, nblk, r, Y,
-                               N, (T *)jw.gram, nch);
-            hipLaunchKernelGGL((jac_inner<T, B2>), dim3(npairs), dim3(JR_NT), 0, s, nch,
+            hipLaunchKernelGGL((jac_gram<T, B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, N, nblk, r, Y,
+                               N, (T *)jw.gram, nchG);
+            hipLaunchKernelGGL((jac_inner<T, B2, INNER_NT>), dim3(npairs), dim3(INNER_NT), 0, s, nchG,
                                (const T *)jw.gram, (T *)jw.wmat, jw.skip, jw.flag, eps, max_inner);
             hipLaunchKernelGGL((jac_update<T, B2>), dim3(npairs, nch + nchV), dim3(JR_NT), 0, s, N,
                                nblk, r, Y, N, V, N, nch, (const T *)jw.wmat, jw.skip);
@@ -339,8 +380,8 @@ static int sweeps_impl(hipStream_t s, int N, T *Y, T *V, double eps, int maxswee
 template <typename T>
 int jacobi_sweeps(hipStream_t s, int N, int b, T *Y, T *V, double eps, int maxsweep, int max_inner,
                   JacobiWork &jw, int *conv) {
-    if (b == 16) return sweeps_impl<T, 32>(s, N, Y, V, eps, maxsweep, max_inner, jw, conv);
-    return sweeps_impl<T, 64>(s, N, Y, V, eps, maxsweep, max_inner, jw, conv);
+    if (b == 16) return sweeps_impl<T, 32, 256>(s, N, Y, V, eps, maxsweep, max_inner, jw, conv);
+    return sweeps_impl<T, 64, 1024>(s, N, Y, V, eps, maxsweep, max_inner, jw, conv);
 }
 
 template int jacobi_sweeps<float>(hipStream_t, int, int, float *, float *, double, int, int,

@@ -22,19 +22,29 @@ static_assert(QR_RC == 256, "panel kernels use one thread per row");
 constexpr int LROW = QR_RC;  // LDS column stride (all accesses are row-contiguous)
 
 // Load rows [g*RC, g*RC+RC) x columns [c0, nb) of the panel into L[k][r].
+// (unrolled over the panel width so that all loads of a thread are in flight)
 __device__ __forceinline__ void panel_load(double *L, const double *P, int ld, int mp, int g,
                                            int c0, int nb) {
     const int r = threadIdx.x;
     const int i = g * QR_RC + r;
-    for (int k = c0; k < nb; ++k) L[k * LROW + r] = (i < mp) ? P[(size_t)k * ld + i] : 0.0;
+    double v[QR_NB];
+#pragma unroll
+    for (int k = 0; k < QR_NB; ++k)
+        v[k] = (k >= c0 && k < nb && i < mp) ? P[(size_t)k * ld + i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < QR_NB; ++k)
+        if (k >= c0 && k < nb) L[k * LROW + r] = v[k];
 }
 
 __device__ __forceinline__ void panel_store(const double *L, double *P, int ld, int mp, int g,
                                             int c0, int nb) {
     const int r = threadIdx.x;
     const int i = g * QR_RC + r;
-    if (i < mp)
-        for (int k = c0; k < nb; ++k) P[(size_t)k * ld + i] = L[k * LROW + r];
+    if (i < mp) {
+#pragma unroll
+        for (int k = 0; k < QR_NB; ++k)
+            if (k >= c0 && k < nb) P[(size_t)k * ld + i] = L[k * LROW + r];
+    }
 }
 
 // Partial dots for the reflector of column jn: over local rows i > jn,
