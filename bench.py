@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark of the mixed-precision Jacobi SVD on one MI355X.
+
+Metric: time of an n = 4096 SVD, svd_mixed (Algorithm 4) against svd_plain
+(FP64 preconditioned Jacobi, Algorithm 2), on the same GPU, both with U and V
+requested, both checked against the accuracy gates
+(e_sigma <= 1e-13 after the column-scaled condition adjustment,
+||U^T U - I||_F, ||V^T V - I||_F <= 1e-13 n, ||A - U S V^T||_F/||A||_F <=
+1e-14 n).  value = T_plain / T_mixed; ms_per_step = T_mixed (one step = one
+mixed SVD of the whole path).
+
+Workload: 4096 x 4096 FP64 A = U diag(sigma) V^T, Haar U and V, sigma
+log-uniform in [1e-12, 1], seed 4 (testmats.config_c3b).  Inputs are resident
+in HBM before the timed region starts.
+
+Prints one JSON line.  Options: --gpus (only 1), --steps K, --warmup W,
+--n (size), --no-cpu-baseline, --cpu-sample-n.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TF = 78.6            # dense FP64 (vector and MFMA)
+FP32_PEAK_TF = 157.3           # dense FP32 (vector and MFMA)
+
+
+def algorithmic_flops(n: int, info: dict, mixed: bool) -> float:
+    """Algorithmic flop count of one SVD (square n, U and V formed), from the
+    stage formulas: pivot pass 4n^3/3, QR of A1 P 4n^3/3, LQ 4n^3/3, branch
+    SYRK n^3, FP32 sweeps 4n^2(n-1) each, switch 4.7 n^3, FP64 sweeps with V
+    7n^2(n-1) each, back-transforms 4n^3."""
+    f = 4 * n ** 3 / 3 * 3 + 4 * n ** 3
+    if mixed:
+        f += n ** 3
+        if info["branch_taken"] == 1:
+            f += info["sweeps_low"] * 4 * n * n * (n - 1) + 4.7 * n ** 3
+    f += info["sweeps_work"] * 7 * n * n * (n - 1)
+    return f
+
+
+def gates_gpu(A, U, S, V, s_ref, kappa_s):
+    """The accuracy gates, evaluated with FP64 products on the GPU."""
+    import torch
+    n = A.shape[1]
+    eye = torch.eye(n, dtype=torch.float64, device=A.device)
+    orth_u = torch.linalg.norm(U.t() @ U - eye).item()
+    orth_v = torch.linalg.norm(V.t() @ V - eye).item()
+    res = (torch.linalg.norm(A - (U * S) @ V.t()) / torch.linalg.norm(A)).item()
+    r = {"orth_u": orth_u, "orth_v": orth_v, "residual": res}
+    if s_ref is not None:
+        sref = torch.from_numpy(s_ref).to(A.device)
+        rel = torch.max(torch.abs(S - sref) / sref).item()
+        r["rel_sigma"] = rel
+        r["e_sigma"] = rel / max(1.0, kappa_s)
+    ok = orth_u <= 1e-13 * n and orth_v <= 1e-13 * n and res <= 1e-14 * n
+    if "e_sigma" in r:
+        ok = ok and r["e_sigma"] <= 1e-13
+    r["pass"] = bool(ok)
+    return r
+
+
+def cpu_baseline(n_full: int, n_sample: int) -> dict:
+    """The FP64 oracle timed on this host's cores on a bounded sample: the
+    full oracle SVD (QRCP + LQ preconditioning, round-robin Jacobi on all
+    cores) of the same construction at n_sample, scaled by (n_full /
+    n_sample)^3 to one n_full SVD."""
+    import oracle
+    import testmats
+    oracle.set_threads(os.cpu_count() or 1)
+    A, _ = testmats.config_c3b(n=n_sample)
+    t0 = time.perf_counter()
+    _, _, _, info = oracle.svd(A, order="rr")
+    dt = time.perf_counter() - t0
+    scale = (n_full / n_sample) ** 3
+    est = dt * scale
+    return {
+        "value": 1.0 / est, "unit": "SVD/s", "cores": oracle.max_threads(), "kind": "oracle",
+        "sample": (f"full oracle SVD of the {n_sample}x{n_sample} instance of the same "
+                   f"construction ({dt:.2f} s, {info['sweeps']} sweeps), scaled by "
+                   f"({n_full}/{n_sample})^3 = {scale:.0f} to one {n_full}x{n_full} SVD"),
+        "est_ms_per_svd": est * 1e3,
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-n", type=int, default=1024)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr, flush=True)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2209_04626_amd as mp
+    import testmats
+
+    n = args.n
+    t0 = time.time()
+    A_np, _ = testmats.config_c3b(n=n)
+    print(f"[bench] generated {n}x{n} input in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(np.ascontiguousarray(A_np)).to(dev)
+    ws = mp.Workspace()
+    opts_mixed = mp.default_opts(True)
+    opts_plain = mp.default_opts(False)
+
+    for _ in range(args.warmup):
+        mp.svd(A, "mixed", workspace=ws, opts=opts_mixed)
+        mp.svd(A, "plain", workspace=ws, opts=opts_plain)
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    # timed: K mixed SVDs (the step), with per-launch kernel clocks
+    opts_mixed.kernel_timing = 1
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Um, Sm, Vm, info = mp.svd(A, "mixed", workspace=ws, opts=opts_mixed)
+        infos.append(info)
+    torch.cuda.synchronize()
+    t_mixed = (time.perf_counter() - t0) / args.steps
+    print(f"[bench] mixed {t_mixed * 1e3:.1f} ms/SVD", file=sys.stderr, flush=True)
+
+    # K plain SVDs on the same matrix
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Up, Sp, Vp, info_p = mp.svd(A, "plain", workspace=ws, opts=opts_plain)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / args.steps
+    print(f"[bench] plain {t_plain * 1e3:.1f} ms/SVD", file=sys.stderr, flush=True)
+
+    # gates against the stored oracle sigma (when this size has one)
+    s_ref, kappa = None, None
+    if n == 4096:
+        sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+        try:
+            from make_oracle_sigma import load
+            s_ref, kappa, _, _ = load("C3b")
+        except FileNotFoundError:
+            s_ref = None
+    g_mixed = gates_gpu(A, Um, Sm, Vm, s_ref, kappa or 1.0)
+    g_plain = gates_gpu(A, Up, Sp, Vp, s_ref, kappa or 1.0)
+
+    # dominant kernel of the timed region and its roofline
+    K = len(infos)
+    ms = np.sum([i["kern_ms"] for i in infos], axis=0)
+    calls = np.sum([i["kern_calls"] for i in infos], axis=0)
+    byts = np.sum([i["kern_bytes"] for i in infos], axis=0)
+    dom = int(np.argmax(ms))
+    avg_s = ms[dom] / 1e3 / max(calls[dom], 1)
+    bytes_per_launch = byts[dom] / max(calls[dom], 1)
+    achieved = bytes_per_launch / avg_s / 1e9
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "kernel": mp.KERNEL_CLASSES[dom], "avg_us": round(avg_s * 1e6, 2),
+        "launches": int(calls[dom]), "bytes_per_launch": bytes_per_launch,
+        "kernel_ms_per_svd": {mp.KERNEL_CLASSES[c]: round(float(ms[c]) / K, 2)
+                              for c in range(7) if calls[c]},
+    }
+
+    info = infos[-1]
+    flops = algorithmic_flops(n, info, True)
+    line = {
+        "metric": "n=4096 SVD time: mixed vs plain FP64 Jacobi, same GPU, sigma rel err <=1e-13",
+        "value": round(t_plain / t_mixed, 4),
+        "unit": "x (T_plain / T_mixed)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_mixed * 1e3, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"C3b: {n}x{n} FP64, A = U diag(sigma) V^T, Haar U/V, "
+                               f"sigma log-uniform in [1e-12, 1], seed 4; U and V formed",
+                   "m": n, "n": n},
+        "mixed_ms": round(t_mixed * 1e3, 2), "plain_ms": round(t_plain * 1e3, 2),
+        "mixed_svd_per_s": round(1.0 / t_mixed, 4), "plain_svd_per_s": round(1.0 / t_plain, 4),
+        "mixed_gflops": round(flops / t_mixed / 1e9, 1),
+        "mixed_info": {k: info[k] for k in ("status", "branch_taken", "sweeps_low", "sweeps_work",
+                                            "orth", "cond_r")},
+        "mixed_stage_ms": [round(x, 2) for x in info["stage_ms"]],
+        "plain_info": {k: info_p[k] for k in ("status", "sweeps_work")},
+        "plain_stage_ms": [round(x, 2) for x in info_p["stage_ms"]],
+        "gates_mixed": g_mixed, "gates_plain": g_plain,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(n, args.cpu_sample_n)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

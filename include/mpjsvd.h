@@ -82,7 +82,20 @@ typedef struct {
     int block_cols;        /* Jacobi block width b (16 or 32); 0 = auto */
     int inner_sweeps;      /* cap on the Jacobi sweeps run on each 2b x 2b
                               Gram block per block pair; 0 = auto (1) */
+    int kernel_timing;     /* 1: bracket every launch of the hot kernels with
+                              HIP events and report per-class totals in
+                              svd_info.kern_ms / kern_calls (adds host work) */
 } svd_opts;
+
+/* Kernel classes reported by svd_info.kern_ms when kernel_timing = 1 */
+#define SVD_K_GRAM32 0     /* Jacobi Gram blocks, FP32 stage          */
+#define SVD_K_INNER32 1    /* Jacobi 2b x 2b inner solve, FP32 stage  */
+#define SVD_K_UPDATE32 2   /* Jacobi block rotation update, FP32      */
+#define SVD_K_GRAM64 3
+#define SVD_K_INNER64 4
+#define SVD_K_UPDATE64 5
+#define SVD_K_QRCP 6       /* one pivot step of the QRCP pass         */
+#define SVD_K_NCLASS 8
 
 typedef struct {
     int status;            /* SVD_OK / SVD_WARN_* / SVD_ERR_* */
@@ -94,6 +107,9 @@ typedef struct {
     double cond_r;         /* max|r_ii| / min|r_ii| of the pivoted R */
     float stage_ms[8];     /* ingest+tall QR, pivots, QR, LQ, tests,
                               FP32 sweeps, switch, FP64 sweeps+finalise */
+    float kern_ms[SVD_K_NCLASS];   /* summed kernel durations per class */
+    int kern_calls[SVD_K_NCLASS];  /* launches per class (kernel_timing = 1) */
+    double kern_bytes[SVD_K_NCLASS]; /* algorithmic HBM bytes of those launches */
 } svd_info;
 
 /* Fill *o with the defaults above; mixed = 1 selects pivot_precision 32,

@@ -25,6 +25,8 @@ EXPORTS = [
 ]
 
 SVD_OK, SVD_WARN_NOCONV, SVD_ERR_NONFINITE, SVD_WARN_RANK_DEFICIENT = 0, 1, 2, 3
+KERNEL_CLASSES = ["jac_gram<f32>", "jac_inner<f32>", "jac_update<f32>", "jac_gram<f64>",
+                  "jac_inner<f64>", "jac_update<f64>", "qrcp_step", "-"]
 BRANCH_AUTO, BRANCH_LOW, BRANCH_SKIP = 0, 1, 2
 
 
@@ -38,6 +40,7 @@ class SvdOpts(ctypes.Structure):
         ("branch", ctypes.c_int), ("switch_method", ctypes.c_int),
         ("pivot_precision", ctypes.c_int), ("sign_normalize", ctypes.c_int),
         ("block_cols", ctypes.c_int), ("inner_sweeps", ctypes.c_int),
+        ("kernel_timing", ctypes.c_int),
     ]
 
 
@@ -46,6 +49,8 @@ class SvdInfo(ctypes.Structure):
         ("status", ctypes.c_int), ("branch_taken", ctypes.c_int), ("sweeps_low", ctypes.c_int),
         ("sweeps_work", ctypes.c_int), ("n_small", ctypes.c_int), ("orth", ctypes.c_double),
         ("cond_r", ctypes.c_double), ("stage_ms", ctypes.c_float * 8),
+        ("kern_ms", ctypes.c_float * 8), ("kern_calls", ctypes.c_int * 8),
+        ("kern_bytes", ctypes.c_double * 8),
     ]
 
     def as_dict(self) -> dict:
@@ -54,6 +59,8 @@ class SvdInfo(ctypes.Structure):
             "sweeps_low": self.sweeps_low, "sweeps_work": self.sweeps_work,
             "n_small": self.n_small, "orth": self.orth, "cond_r": self.cond_r,
             "stage_ms": list(self.stage_ms),
+            "kern_ms": list(self.kern_ms), "kern_calls": list(self.kern_calls),
+            "kern_bytes": list(self.kern_bytes),
         }
 
 

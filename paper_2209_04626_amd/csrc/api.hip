@@ -38,6 +38,7 @@ extern "C" void svd_default_opts(svd_opts *o, int mixed) {
     o->sign_normalize = 1;
     o->block_cols = 0;
     o->inner_sweeps = 0;
+    o->kernel_timing = 0;
 }
 
 namespace {
@@ -45,16 +46,20 @@ namespace {
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    int m, n, N, b;
+    int m, n, N, b32, b64;
     size_t off_atall, off_tau0, off_t0, off_a1, off_wp, off_nrm2, off_piv, off_a1p, off_tau1,
         off_t1, off_rt, off_tau2, off_t2, off_x, off_y, off_vacc, off_y32, off_xt, off_ulow, off_bm,
         off_tau3, off_t3, off_ux, off_vx, off_sig, off_rank, off_nrmx, off_small, off_qr, off_jac,
         total;
 };
 
-int pick_b(int n, const svd_opts &o) {
+// Jacobi block width per stage: the FP32 stage is bound by the latency of
+// the inner 2b x 2b solves (b = 16 keeps them short), the FP64 stage with V by
+// the traffic of the block updates (b = 32 halves the rounds per sweep).
+int pick_b(int n, const svd_opts &o, bool low) {
     if (o.block_cols == 16 || o.block_cols == 32) return o.block_cols;
-    return 16;
+    if (low) return 16;
+    return n >= 512 ? 32 : 16;
 }
 
 Layout layout(int m, int n, const svd_opts &o) {
@@ -62,7 +67,8 @@ Layout layout(int m, int n, const svd_opts &o) {
     L.m = m; L.n = n;
     L.N = ((n + 63) / 64) * 64;
     if (L.N == 0) L.N = 64;
-    L.b = pick_b(n, o);
+    L.b32 = pick_b(n, o, true);
+    L.b64 = pick_b(n, o, false);
     const size_t d = sizeof(double), f = sizeof(float);
     const size_t nn = (size_t)n * n, NN = (size_t)L.N * L.N;
     const size_t nblk = (size_t)cdiv(n, QR_NB) * QR_NB * QR_NB;
@@ -97,7 +103,11 @@ Layout layout(int m, int n, const svd_opts &o) {
     L.off_nrmx = take((size_t)n * d);
     L.off_small = take(4096);
     L.off_qr = take(qr_scratch_doubles(m > n ? m : n, n, nullptr) * d);
-    L.off_jac = take(jacobi_scratch_bytes(L.N, L.b, (int)d));
+    {
+        const size_t j32 = jacobi_scratch_bytes(L.N, L.b32, (int)f);
+        const size_t j64 = jacobi_scratch_bytes(L.N, L.b64, (int)d);
+        L.off_jac = take(j32 > j64 ? j32 : j64);
+    }
     L.total = p;
     return L;
 }
@@ -191,15 +201,17 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     double *UX = D(L.off_ux), *VX = D(L.off_vx), *sig = D(L.off_sig), *nrmX = D(L.off_nrmx);
     int *piv = (int *)(w + L.off_piv), *rank = (int *)(w + L.off_rank);
     Small *sm = (Small *)(w + L.off_small);
-    const int N = L.N, b = L.b;
+    const int N = L.N;
     const int inner = o.inner_sweeps > 0 ? o.inner_sweeps : 1;
 
     QRScratch q;
     qr_scratch_carve(q, D(L.off_qr), m > n ? m : n, n);
     JacobiWork jw;
-    jacobi_carve(jw, w + L.off_jac, N, b, (int)sizeof(double));
     int hflag = 0;
     jw.hflag = &hflag;
+    KernelClock kclock;
+    kclock.on = o.kernel_timing != 0;
+    jw.kc = kclock.on ? &kclock : nullptr;
 
     Timer tm(s);
     Small hs;
@@ -223,9 +235,9 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     tm.mark(0);
     // a2: pivots (Algorithm 5 in FP32, or FP64)
     if (o.pivot_precision == 32)
-        qrcp_pivots<float>(s, n, A1, n, (float *)D(L.off_wp), (float *)D(L.off_nrm2), piv);
+        qrcp_pivots<float>(s, n, A1, n, (float *)D(L.off_wp), (float *)D(L.off_nrm2), piv, jw.kc);
     else
-        qrcp_pivots<double>(s, n, A1, n, D(L.off_wp), D(L.off_nrm2), piv);
+        qrcp_pivots<double>(s, n, A1, n, D(L.off_wp), D(L.off_nrm2), piv, jw.kc);
     tm.mark(1);
     // a3: FP64 QR of A1 P
     gather_cols(s, n, n, A1, n, piv, A1P, n);
@@ -271,8 +283,9 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     if (branch == SVD_BRANCH_LOW) {
         // a6: FP32 one-sided Jacobi on low(X), no V (Section 3.2)
         convert_f64_f32(s, N, N, X, N, Y32, N);
-        sweeps_low = jacobi_sweeps<float>(s, N, b, Y32, nullptr, eps_low, o.maxsweep_low, inner, jw,
-                                          &conv_low);
+        jacobi_carve(jw, w + L.off_jac, N, L.b32, (int)sizeof(float));
+        sweeps_low = jacobi_sweeps<float>(s, N, L.b32, Y32, nullptr, eps_low, o.maxsweep_low, inner,
+                                          jw, &conv_low);
         if (sweeps_low < 0) return SVD_ERR_HIP;
         normalize_f32_to_f64(s, N, N, Y32, N, Ulow, N);
         tm.mark(5);
@@ -295,7 +308,8 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
 
     // a8: FP64 one-sided Jacobi (Algorithm 1) with V accumulated from Q
     int conv_work = 0;
-    const int sweeps_work = jacobi_sweeps<double>(s, N, b, Y, o.want_v ? Vacc : nullptr, eps_work,
+    jacobi_carve(jw, w + L.off_jac, N, L.b64, (int)sizeof(double));
+    const int sweeps_work = jacobi_sweeps<double>(s, N, L.b64, Y, o.want_v ? Vacc : nullptr, eps_work,
                                                   o.maxsweep_work, inner, jw, &conv_work);
     if (sweeps_work < 0) return SVD_ERR_HIP;
 
@@ -314,7 +328,13 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     MPJ_CHECK(hipGetLastError());
     tm.mark(7);
     if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
+    kclock.collect();
     if (info) {
+        for (int c = 0; c < SVD_K_NCLASS; ++c) {
+            info->kern_ms[c] = kclock.ms[c];
+            info->kern_calls[c] = kclock.calls[c];
+            info->kern_bytes[c] = kclock.tot_bytes[c];
+        }
         tm.fill(info);
         info->branch_taken = branch;
         info->sweeps_low = sweeps_low;

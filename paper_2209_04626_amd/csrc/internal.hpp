@@ -3,7 +3,58 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 
+#include <vector>
+
 namespace mpj {
+
+// Per-launch HIP event timing for a kernel class (opt-in).  Pairs of events
+// are taken from a pool, recorded around each launch and read after the
+// caller synchronises.
+struct KernelClock {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> cls;
+    std::vector<double> bytes;
+    size_t used = 0;
+    bool on = false;
+    float ms[8] = {0};
+    int calls[8] = {0};
+    double tot_bytes[8] = {0};
+    void begin(hipStream_t s, int c, double b) {
+        if (!on) return;
+        if (used + 2 > ev.size()) {
+            hipEvent_t e0, e1;
+            hipEventCreate(&e0);
+            hipEventCreate(&e1);
+            ev.push_back(e0);
+            ev.push_back(e1);
+            cls.push_back(c);
+            bytes.push_back(b);
+        }
+        cls[used / 2] = c;
+        bytes[used / 2] = b;
+        hipEventRecord(ev[used], s);
+    }
+    void end(hipStream_t s) {
+        if (!on) return;
+        hipEventRecord(ev[used + 1], s);
+        used += 2;
+    }
+    // call after the stream has been synchronised
+    void collect() {
+        if (!on) return;
+        for (size_t i = 0; i < used; i += 2) {
+            float t = 0.f;
+            hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+            ms[cls[i / 2]] += t;
+            calls[cls[i / 2]] += 1;
+            tot_bytes[cls[i / 2]] += bytes[i / 2];
+        }
+        used = 0;
+    }
+    ~KernelClock() {
+        for (auto e : ev) hipEventDestroy(e);
+    }
+};
 
 // ---------------------------------------------------------------- GEMM
 // C (M x N, column-major, ldc) = alpha op(A) op(B) + beta C, op = transpose
@@ -52,7 +103,7 @@ void qr_apply_left(hipStream_t s, bool trans, int m, int k, const double *Qf,
 // 2n elements of T.
 template <typename T>
 void qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W,
-                 T *norms2, int *piv);
+                 T *norms2, int *piv, KernelClock *kc = nullptr);
 
 // ---------------------------------------------------------------- Jacobi
 struct JacobiWork {
@@ -60,7 +111,8 @@ struct JacobiWork {
     void *wmat;      // per-pair rotation blocks
     int *skip;       // per-pair "nothing to rotate" flags
     int *flag;       // device: any rotation this sweep
-    int *hflag;      // pinned host mirror of flag
+    int *hflag;      // host copy of flag
+    KernelClock *kc = nullptr;
 };
 size_t jacobi_scratch_bytes(int N, int b, int elem);
 void jacobi_carve(JacobiWork &j, char *base, int N, int b, int elem);

@@ -24,61 +24,82 @@ namespace mpj {
 
 constexpr int JR_NT = 256;   // threads per workgroup
 constexpr int JR_RG = 256;   // rows per workgroup in update
-constexpr int JR_RGG = 1024; // rows per workgroup in gram
+constexpr int JR_RGG = 256;  // rows per workgroup in gram
 constexpr int JR_SLAB = 32;  // rows staged in LDS at a time
 
 __device__ __forceinline__ int blk_col(int c, int b, int I, int J) {
     return c < b ? I * b + c : J * b + (c - b);
 }
 
+// Partial Gram block of one row chunk.  Only the 16 x 16 tiles on or above
+// the block diagonal are formed (G is symmetric; the inner solve reads the
+// upper triangle).  The next 32-row slab is loaded into registers while the
+// matrix cores work on the current one.
 template <typename T, int B2>
 __global__ __launch_bounds__(JR_NT) void jac_gram(int N, int nblk, int r, const T *__restrict__ Y,
                                                   int ldy, T *__restrict__ Gp, int nchunk) {
     constexpr int b = B2 / 2;
-    constexpr int NTT = B2 / 16;           // tiles per dimension
-    constexpr int TPW = (NTT * NTT + 3) / 4;
+    constexpr int NTT = B2 / 16;                       // tiles per dimension
+    constexpr int NUT = NTT * (NTT + 1) / 2;           // upper-triangle tiles
+    constexpr int TPW = (NUT + 3) / 4;
+    constexpr int PER = B2 * JR_SLAB / JR_NT;          // slab elements per thread
     __shared__ T Ps[B2][JR_SLAB + 1];
     const int pair = blockIdx.x, chunk = blockIdx.y;
     int I, J;
     rr_slot(nblk, r, pair, &I, &J);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // this wavefront's tiles (ti <= tj), enumerated row by row
+    int tI[TPW], tJ[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        int u = w + 4 * q, ti = 0;
+        while (u >= NTT - ti && ti < NTT) { u -= NTT - ti; ++ti; }
+        tI[q] = ti; tJ[q] = ti + u;
+    }
     typedef typename acc4<T>::type V4;
     V4 acc[TPW];
 #pragma unroll
     for (int q = 0; q < TPW; ++q) acc[q] = V4{0, 0, 0, 0};
     const int rbeg = chunk * JR_RGG, rend = min(N, rbeg + JR_RGG);
-    for (int r0 = rbeg; r0 < rend; r0 += JR_SLAB) {
+    T pf[PER];
+    auto fetch = [&](int r0) {
 #pragma unroll
-        for (int e = tid; e < B2 * JR_SLAB; e += JR_NT) {
+        for (int e0 = 0; e0 < PER; ++e0) {
+            const int e = tid + e0 * JR_NT;
             const int c = e / JR_SLAB, rr = e % JR_SLAB;
             const int gi = r0 + rr;
-            Ps[c][rr] = gi < N ? Y[(size_t)blk_col(c, b, I, J) * ldy + gi] : T(0);
+            pf[e0] = gi < rend ? Y[(size_t)blk_col(c, b, I, J) * ldy + gi] : T(0);
+        }
+    };
+    fetch(rbeg);
+    for (int r0 = rbeg; r0 < rend; r0 += JR_SLAB) {
+        __syncthreads();
+#pragma unroll
+        for (int e0 = 0; e0 < PER; ++e0) {
+            const int e = tid + e0 * JR_NT;
+            Ps[e / JR_SLAB][e % JR_SLAB] = pf[e0];
         }
         __syncthreads();
+        if (r0 + JR_SLAB < rend) fetch(r0 + JR_SLAB);
 #pragma unroll
         for (int kk = 0; kk < JR_SLAB; kk += 4) {
 #pragma unroll
             for (int q = 0; q < TPW; ++q) {
-                const int tile = w + 4 * q;
-                if (tile < NTT * NTT) {
-                    const int ti = tile % NTT, tj = tile / NTT;
-                    const T a = Ps[16 * ti + lane % 16][kk + lane / 16];
-                    const T bb = Ps[16 * tj + lane % 16][kk + lane / 16];
+                if (w + 4 * q < NUT) {
+                    const T a = Ps[16 * tI[q] + lane % 16][kk + lane / 16];
+                    const T bb = Ps[16 * tJ[q] + lane % 16][kk + lane / 16];
                     acc[q] = mfma16(a, bb, acc[q]);
                 }
             }
         }
-        __syncthreads();
     }
     T *out = Gp + ((size_t)pair * nchunk + chunk) * B2 * B2;
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
-        const int tile = w + 4 * q;
-        if (tile < NTT * NTT) {
-            const int ti = tile % NTT, tj = tile / NTT;
+        if (w + 4 * q < NUT) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int i = 16 * ti + mfma_row<T>(lane, e), j = 16 * tj + lane % 16;
+                const int i = 16 * tI[q] + mfma_row<T>(lane, e), j = 16 * tJ[q] + lane % 16;
                 out[i + j * B2] = acc[q][e];
             }
         }
@@ -263,6 +284,8 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
     }
 }
 
+// [Y_I Y_J] <- [Y_I Y_J] W (and V) on one row chunk: 32-row slabs through
+// LDS, the next slab loaded into registers during the MFMA of the current one.
 template <typename T, int B2>
 __global__ __launch_bounds__(JR_NT) void jac_update(int N, int nblk, int r, T *__restrict__ Y,
                                                     int ldy, T *__restrict__ V, int ldv,
@@ -272,6 +295,7 @@ __global__ __launch_bounds__(JR_NT) void jac_update(int N, int nblk, int r, T *_
     constexpr int NTJ = B2 / 16;                 // column tiles
     constexpr int NT = 2 * NTJ;                  // 2 row tiles (32 rows) x NTJ
     constexpr int TPW = NT / 4;
+    constexpr int PER = B2 * JR_SLAB / JR_NT;
     __shared__ T Ws[B2][B2 + 1];
     __shared__ T Ps[B2][JR_SLAB + 1];
     const int pair = blockIdx.x;
@@ -287,13 +311,26 @@ __global__ __launch_bounds__(JR_NT) void jac_update(int N, int nblk, int r, T *_
     else { M = V; ld = ldv; chunk = blockIdx.y - nchY; }
     const int rbeg = chunk * JR_RG, rend = min(N, rbeg + JR_RG);
     typedef typename acc4<T>::type V4;
-    for (int r0 = rbeg; r0 < rend; r0 += JR_SLAB) {
-        for (int e = tid; e < B2 * JR_SLAB; e += JR_NT) {
+    T pf[PER];
+    auto fetch = [&](int r0) {
+#pragma unroll
+        for (int e0 = 0; e0 < PER; ++e0) {
+            const int e = tid + e0 * JR_NT;
             const int c = e / JR_SLAB, rr = e % JR_SLAB;
             const int gi = r0 + rr;
-            Ps[c][rr] = gi < N ? M[(size_t)blk_col(c, b, I, J) * ld + gi] : T(0);
+            pf[e0] = gi < rend ? M[(size_t)blk_col(c, b, I, J) * ld + gi] : T(0);
+        }
+    };
+    fetch(rbeg);
+    for (int r0 = rbeg; r0 < rend; r0 += JR_SLAB) {
+        __syncthreads();
+#pragma unroll
+        for (int e0 = 0; e0 < PER; ++e0) {
+            const int e = tid + e0 * JR_NT;
+            Ps[e / JR_SLAB][e % JR_SLAB] = pf[e0];
         }
         __syncthreads();
+        if (r0 + JR_SLAB < rend) fetch(r0 + JR_SLAB);
         V4 acc[TPW];
 #pragma unroll
         for (int q = 0; q < TPW; ++q) acc[q] = V4{0, 0, 0, 0};
@@ -308,7 +345,6 @@ __global__ __launch_bounds__(JR_NT) void jac_update(int N, int nblk, int r, T *_
                 acc[q] = mfma16(a, bb, acc[q]);
             }
         }
-        __syncthreads();
 #pragma unroll
         for (int q = 0; q < TPW; ++q) {
             const int tile = w + 4 * q;
@@ -318,7 +354,7 @@ __global__ __launch_bounds__(JR_NT) void jac_update(int N, int nblk, int r, T *_
                 const int i = 16 * ti + mfma_row<T>(lane, e);
                 const int j = 16 * tj + lane % 16;
                 const int gi = r0 + i;
-                if (gi < N) M[(size_t)blk_col(j, b, I, J) * ld + gi] = acc[q][e];
+                if (gi < rend) M[(size_t)blk_col(j, b, I, J) * ld + gi] = acc[q][e];
             }
         }
     }
@@ -360,18 +396,28 @@ static int sweeps_impl(hipStream_t s, int N, T *Y, T *V, double eps, int maxswee
     for (; sw < maxsweep; ++sw) {
         hipError_t e = hipMemsetAsync(jw.flag, 0, sizeof(int), s);
         if (e != hipSuccess) { note_hip_error(e, "jacobi flag reset"); return -1; }
+        // kernel-class ids for the optional per-launch clock
+        const int kbase = sizeof(T) == 4 ? 0 : 3;
+        const double E = sizeof(T);
+        const double gram_bytes = (double)N * N * E;                      // Y read once
+        const double upd_bytes = 2.0 * (double)N * N * E * (V ? 2 : 1);   // Y (and V) read + written
         for (int r = 0; r < nblk - 1; ++r) {
+            if (jw.kc) jw.kc->begin(s, kbase + 0, gram_bytes);
             hipLaunchKernelGGL((jac_gram<T, B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, N, nblk, r, Y,
                                N, (T *)jw.gram, nchG);
+            if (jw.kc) { jw.kc->end(s); jw.kc->begin(s, kbase + 1, 0.0); }
             hipLaunchKernelGGL((jac_inner<T, B2, INNER_NT>), dim3(npairs), dim3(INNER_NT), 0, s, nchG,
                                (const T *)jw.gram, (T *)jw.wmat, jw.skip, jw.flag, eps, max_inner);
+            if (jw.kc) { jw.kc->end(s); jw.kc->begin(s, kbase + 2, upd_bytes); }
             hipLaunchKernelGGL((jac_update<T, B2>), dim3(npairs, nch + nchV), dim3(JR_NT), 0, s, N,
                                nblk, r, Y, N, V, N, nch, (const T *)jw.wmat, jw.skip);
+            if (jw.kc) jw.kc->end(s);
         }
         e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(jw.hflag, jw.flag, sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { note_hip_error(e, "jacobi sweep"); return -1; }
+        if (jw.kc) jw.kc->collect();
         if (*jw.hflag == 0) { *conv = 1; ++sw; break; }
     }
     return sw;

@@ -242,7 +242,8 @@ __global__ __launch_bounds__(CR_NT) void qrcp_step_reg(int k, int n, T *W, const
 }
 
 template <typename T>
-void qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, T *norms2, int *piv) {
+void qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, T *norms2, int *piv,
+                 KernelClock *kc) {
     if (n <= 0) return;
     hipLaunchKernelGGL((qrcp_init<T>), dim3(cdiv(n, CP_NT / 64)), dim3(CP_NT), 0, s, n, A1, lda, W,
                        norms2);
@@ -250,6 +251,11 @@ void qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, T *norms
         const T *nin = norms2 + (size_t)(k & 1) * n;
         T *nout = norms2 + (size_t)((k + 1) & 1) * n;
         const dim3 g(cdiv(n, CR_W));
+        // algorithmic bytes of step k: the active trailing block (rows k..n-1
+        // of the n-k-1 remaining columns) read and written once, the pivot
+        // column read once
+        const double m = n - k;
+        if (kc) kc->begin(s, 6, (2.0 * m * (m - 1) + m) * sizeof(T));
         if (n <= 64 * 16)
             hipLaunchKernelGGL((qrcp_step_reg<T, 16>), g, dim3(CR_NT), 0, s, k, n, W, nin, nout, piv);
         else if (n <= 64 * 32)
@@ -259,10 +265,13 @@ void qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, T *norms
         else
             hipLaunchKernelGGL((qrcp_step<T>), dim3(cdiv(n, CP_CPW)), dim3(CP_NT), 0, s, k, n, W, nin,
                                nout, piv);
+        if (kc) kc->end(s);
     }
 }
 
-template void qrcp_pivots<float>(hipStream_t, int, const double *, int, float *, float *, int *);
-template void qrcp_pivots<double>(hipStream_t, int, const double *, int, double *, double *, int *);
+template void qrcp_pivots<float>(hipStream_t, int, const double *, int, float *, float *, int *,
+                                 KernelClock *);
+template void qrcp_pivots<double>(hipStream_t, int, const double *, int, double *, double *, int *,
+                                  KernelClock *);
 
 } // namespace mpj
