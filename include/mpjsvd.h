@@ -44,7 +44,9 @@ extern "C" {
 
 /* svd_info.status values */
 #define SVD_OK 0
-#define SVD_WARN_NOCONV 1        /* a Jacobi phase hit its sweep cap        */
+#define SVD_WARN_NOCONV 1        /* the FP64 sweeps hit their cap (the FP32
+                                    stage may stop at its cap: it only
+                                    preconditions, Section 4) */
 #define SVD_ERR_NONFINITE 2      /* A holds NaN or Inf; outputs undefined   */
 #define SVD_WARN_RANK_DEFICIENT 3 /* some sigma_i == 0; U(:, i) set to zero */
 
@@ -82,9 +84,14 @@ typedef struct {
     int block_cols;        /* Jacobi block width b (16 or 32); 0 = auto */
     int inner_sweeps;      /* cap on the Jacobi sweeps run on each 2b x 2b
                               Gram block per block pair; 0 = auto (1) */
-    int kernel_timing;     /* 1: bracket every launch of the hot kernels with
-                              HIP events and report per-class totals in
-                              svd_info.kern_ms / kern_calls (adds host work) */
+    int kernel_timing;     /* 1: time the QRCP pivot pass as one interval
+                              (class SVD_K_QRCP, negligible overhead);
+                              2: bracket every launch of every hot kernel with
+                              HIP events (per-class totals; adds host work).
+                              Results in svd_info.kern_ms / kern_calls. */
+    double low_stop_off;   /* end the FP32 stage once a sweep starts with
+                              every |g_pq| <= low_stop_off sqrt(g_pp g_qq);
+                              0 = only the eps_low rule.  Default 0. */
 } svd_opts;
 
 /* Kernel classes reported by svd_info.kern_ms when kernel_timing = 1 */
@@ -107,6 +114,9 @@ typedef struct {
     double cond_r;         /* max|r_ii| / min|r_ii| of the pivoted R */
     float stage_ms[8];     /* ingest+tall QR, pivots, QR, LQ, tests,
                               FP32 sweeps, switch, FP64 sweeps+finalise */
+    float off_low[32];     /* per FP32 sweep: max |g_pq| / sqrt(g_pp g_qq)
+                              on the fresh Gram blocks (convergence trace) */
+    float off_work[32];    /* the same for the FP64 sweeps */
     float kern_ms[SVD_K_NCLASS];   /* summed kernel durations per class */
     int kern_calls[SVD_K_NCLASS];  /* launches per class (kernel_timing = 1) */
     double kern_bytes[SVD_K_NCLASS]; /* algorithmic HBM bytes of those launches */

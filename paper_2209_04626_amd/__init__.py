@@ -40,7 +40,7 @@ class SvdOpts(ctypes.Structure):
         ("branch", ctypes.c_int), ("switch_method", ctypes.c_int),
         ("pivot_precision", ctypes.c_int), ("sign_normalize", ctypes.c_int),
         ("block_cols", ctypes.c_int), ("inner_sweeps", ctypes.c_int),
-        ("kernel_timing", ctypes.c_int),
+        ("kernel_timing", ctypes.c_int), ("low_stop_off", ctypes.c_double),
     ]
 
 
@@ -49,6 +49,7 @@ class SvdInfo(ctypes.Structure):
         ("status", ctypes.c_int), ("branch_taken", ctypes.c_int), ("sweeps_low", ctypes.c_int),
         ("sweeps_work", ctypes.c_int), ("n_small", ctypes.c_int), ("orth", ctypes.c_double),
         ("cond_r", ctypes.c_double), ("stage_ms", ctypes.c_float * 8),
+        ("off_low", ctypes.c_float * 32), ("off_work", ctypes.c_float * 32),
         ("kern_ms", ctypes.c_float * 8), ("kern_calls", ctypes.c_int * 8),
         ("kern_bytes", ctypes.c_double * 8),
     ]
@@ -59,6 +60,8 @@ class SvdInfo(ctypes.Structure):
             "sweeps_low": self.sweeps_low, "sweeps_work": self.sweeps_work,
             "n_small": self.n_small, "orth": self.orth, "cond_r": self.cond_r,
             "stage_ms": list(self.stage_ms),
+            "off_low": list(self.off_low)[:max(self.sweeps_low, 0)],
+            "off_work": list(self.off_work)[:max(self.sweeps_work, 0)],
             "kern_ms": list(self.kern_ms), "kern_calls": list(self.kern_calls),
             "kern_bytes": list(self.kern_bytes),
         }

@@ -39,6 +39,7 @@ extern "C" void svd_default_opts(svd_opts *o, int mixed) {
     o->block_cols = 0;
     o->inner_sweeps = 0;
     o->kernel_timing = 0;
+    o->low_stop_off = 0.0;
 }
 
 namespace {
@@ -207,11 +208,13 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     QRScratch q;
     qr_scratch_carve(q, D(L.off_qr), m > n ? m : n, n);
     JacobiWork jw;
-    int hflag = 0;
-    jw.hflag = &hflag;
+    int hflag[3] = {0, 0, 0};
+    jw.hflag = hflag;
+    jw.n_real = n;
     KernelClock kclock;
     kclock.on = o.kernel_timing != 0;
-    jw.kc = kclock.on ? &kclock : nullptr;
+    jw.kc = o.kernel_timing >= 2 ? &kclock : nullptr;
+    float off_low[32] = {0}, off_work[32] = {0};
 
     Timer tm(s);
     Small hs;
@@ -234,10 +237,25 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     }
     tm.mark(0);
     // a2: pivots (Algorithm 5 in FP32, or FP64)
+    // kernel_timing 1: the pass is one interval of n back-to-back step launches
+    if (o.kernel_timing == 1)
+        kclock.begin(s, SVD_K_QRCP, 0.0);
     if (o.pivot_precision == 32)
         qrcp_pivots<float>(s, n, A1, n, (float *)D(L.off_wp), (float *)D(L.off_nrm2), piv, jw.kc);
     else
         qrcp_pivots<double>(s, n, A1, n, D(L.off_wp), D(L.off_nrm2), piv, jw.kc);
+    if (o.kernel_timing == 1) {
+        kclock.end(s);
+        // launches and algorithmic bytes of the whole pass (see qrcp_pivots)
+        const size_t es = o.pivot_precision == 32 ? 4 : 8;
+        double bytes = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double mm = n - k;
+            bytes += (2.0 * mm * (mm - 1) + mm) * es;
+        }
+        kclock.bytes[0] = bytes;
+        kclock.pass_calls = n;
+    }
     tm.mark(1);
     // a3: FP64 QR of A1 P
     gather_cols(s, n, n, A1, n, piv, A1P, n);
@@ -284,8 +302,11 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         // a6: FP32 one-sided Jacobi on low(X), no V (Section 3.2)
         convert_f64_f32(s, N, N, X, N, Y32, N);
         jacobi_carve(jw, w + L.off_jac, N, L.b32, (int)sizeof(float));
+        jw.off_hist = off_low;
+        jw.stop_off = o.low_stop_off;
         sweeps_low = jacobi_sweeps<float>(s, N, L.b32, Y32, nullptr, eps_low, o.maxsweep_low, inner,
                                           jw, &conv_low);
+        jw.stop_off = 0.0;
         if (sweeps_low < 0) return SVD_ERR_HIP;
         normalize_f32_to_f64(s, N, N, Y32, N, Ulow, N);
         tm.mark(5);
@@ -309,6 +330,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     // a8: FP64 one-sided Jacobi (Algorithm 1) with V accumulated from Q
     int conv_work = 0;
     jacobi_carve(jw, w + L.off_jac, N, L.b64, (int)sizeof(double));
+    jw.off_hist = off_work;
     const int sweeps_work = jacobi_sweeps<double>(s, N, L.b64, Y, o.want_v ? Vacc : nullptr, eps_work,
                                                   o.maxsweep_work, inner, jw, &conv_work);
     if (sweeps_work < 0) return SVD_ERR_HIP;
@@ -335,6 +357,8 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
             info->kern_calls[c] = kclock.calls[c];
             info->kern_bytes[c] = kclock.tot_bytes[c];
         }
+        if (o.kernel_timing == 1) info->kern_calls[SVD_K_QRCP] = kclock.pass_calls;
+        for (int i = 0; i < 32; ++i) { info->off_low[i] = off_low[i]; info->off_work[i] = off_work[i]; }
         tm.fill(info);
         info->branch_taken = branch;
         info->sweeps_low = sweeps_low;
@@ -343,7 +367,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         info->orth = orth;
         info->cond_r = mixed ? cond : 0.0;
         int st = SVD_OK;
-        if (!conv_work || (branch == SVD_BRANCH_LOW && !conv_low)) st = SVD_WARN_NOCONV;
+        if (!conv_work) st = SVD_WARN_NOCONV;
         if (hs.nzero) st = SVD_WARN_RANK_DEFICIENT;
         info->status = st;
     }

@@ -18,6 +18,7 @@ struct KernelClock {
     bool on = false;
     float ms[8] = {0};
     int calls[8] = {0};
+    int pass_calls = 0;
     double tot_bytes[8] = {0};
     void begin(hipStream_t s, int c, double b) {
         if (!on) return;
@@ -110,9 +111,14 @@ struct JacobiWork {
     void *gram;      // partial Gram blocks
     void *wmat;      // per-pair rotation blocks
     int *skip;       // per-pair "nothing to rotate" flags
-    int *flag;       // device: any rotation this sweep
-    int *hflag;      // host copy of flag
+    int *flag;       // device: [0] any rotation this sweep, [1] max relative
+                     // off-diagonal |g_pq| / sqrt(g_pp g_qq) seen, [2] max
+                     // |sin| of the rotations applied (float bits)
+    int *hflag;      // host copy of flag[0..2]
+    int n_real = 0;  // columns of the problem (before padding)
     KernelClock *kc = nullptr;
+    float *off_hist = nullptr;  // per-sweep max relative off-diagonal (host, 32)
+    double stop_off = 0.0;      // also stop once a sweep starts with off <= this
 };
 size_t jacobi_scratch_bytes(int N, int b, int elem);
 void jacobi_carve(JacobiWork &j, char *base, int N, int b, int elem);

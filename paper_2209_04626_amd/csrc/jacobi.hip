@@ -17,6 +17,8 @@
 // Applying any orthogonal W keeps the computation rowwise backward stable
 // (the argument of Section 4), and convergence is declared only after a sweep
 // in which no block pair needed a rotation on a freshly computed Gram block.
+#include <string.h>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -168,16 +170,22 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
     }
     __syncthreads();
 
-    // 2. does any pair of the block need a rotation?
+    // 2. does any pair of the block need a rotation?  Also the largest
+    // |g_pq| / sqrt(g_pp g_qq) of the block, kept per sweep as a diagnostic.
     int need = 0;
+    float offmax = 0.f;
 #pragma unroll
     for (int k = 0; k < TE; ++k) {
         const int e = tid + k * NT, p = e % B2, q = e / B2;
         if (p < q) {
             const double g = (double)G[p * LD + q];
-            if (g * g > eps2 * (double)G[p * LD + p] * (double)G[q * LD + q]) need = 1;
+            const double pq = (double)G[p * LD + p] * (double)G[q * LD + q];
+            if (g * g > eps2 * pq) need = 1;
+            if (pq > 0.0) offmax = fmaxf(offmax, (float)(fabs(g) / sqrt(pq)));
         }
     }
+    offmax = wave_max(offmax);
+    if ((tid & 63) == 0 && offmax > 0.f) atomicMax((unsigned int *)(flag + 1), __float_as_uint(offmax));
     need = block_or<NT>(need, ired);
     if (!need) {
         if (tid == 0) skip[pair] = 1;
@@ -186,6 +194,7 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
     if (tid == 0) { skip[pair] = 0; *flag = 1; }
 
     // 3. cyclic rounds of disjoint rotations on G, accumulating W = prod J
+    float smax = 0.f;   // largest |sin| of the rotations this thread computed
     for (int sw = 0; sw < max_inner; ++sw) {
         __syncthreads();
         if (tid == 0) any_rot = 0;
@@ -200,6 +209,7 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
                 if (ga * ga > eps2 * al * be) {
                     jac_rot(al, be, ga, &c, &s, &t);
                     any_rot = 1;
+                    smax = fmaxf(smax, (float)fabs(s));
                 }
                 ca[p] = (T)c; cb[p] = (T)(-s);
                 ca[q] = (T)c; cb[q] = (T)s;
@@ -274,6 +284,9 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
         const int ar = any_rot;
         if (!ar) break;
     }
+
+    smax = wave_max(smax);
+    if ((tid & 63) == 0 && smax > 0.f) atomicMax((unsigned int *)(flag + 2), __float_as_uint(smax));
 
     // 4. write W (column-major)
     T *wo = Wm + (size_t)pair * B2 * B2;
@@ -394,7 +407,7 @@ static int sweeps_impl(hipStream_t s, int N, T *Y, T *V, double eps, int maxswee
     *conv = 0;
     int sw = 0;
     for (; sw < maxsweep; ++sw) {
-        hipError_t e = hipMemsetAsync(jw.flag, 0, sizeof(int), s);
+        hipError_t e = hipMemsetAsync(jw.flag, 0, 3 * sizeof(int), s);
         if (e != hipSuccess) { note_hip_error(e, "jacobi flag reset"); return -1; }
         // kernel-class ids for the optional per-launch clock
         const int kbase = sizeof(T) == 4 ? 0 : 3;
@@ -414,11 +427,23 @@ static int sweeps_impl(hipStream_t s, int N, T *Y, T *V, double eps, int maxswee
             if (jw.kc) jw.kc->end(s);
         }
         e = hipGetLastError();
-        if (e == hipSuccess) e = hipMemcpyAsync(jw.hflag, jw.flag, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(jw.hflag, jw.flag, 3 * sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { note_hip_error(e, "jacobi sweep"); return -1; }
         if (jw.kc) jw.kc->collect();
+        float off, smx;
+        memcpy(&off, jw.hflag + 1, sizeof(float));
+        memcpy(&smx, jw.hflag + 2, sizeof(float));
+        if (jw.off_hist && sw < 32) jw.off_hist[sw] = off;
+        // Algorithm 1's rule: a sweep without rotations
         if (*jw.hflag == 0) { *conv = 1; ++sw; break; }
+        // xGESVJ's rule: the remaining off-diagonal is within sqrt(n) of the
+        // tolerance and the rotations of the sweep were too small to matter
+        const double nn = jw.n_real;
+        if ((double)off < sqrt(nn) * eps && nn * (double)off * (double)smx < eps) {
+            *conv = 1; ++sw; break;
+        }
+        if (jw.stop_off > 0.0 && off <= jw.stop_off) { *conv = 1; ++sw; break; }
     }
     return sw;
 }

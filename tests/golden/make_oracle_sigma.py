@@ -29,6 +29,17 @@ def sha_of(A: np.ndarray) -> str:
     return hashlib.sha256(np.asfortranarray(A).tobytes(order="F")).hexdigest()
 
 
+def fingerprint(A: np.ndarray) -> list:
+    """Frobenius norm and eight fixed entries of A: the seeded input is
+    regenerated with LAPACK/BLAS calls whose last bits depend on the host CPU,
+    so a regenerated A is compared to these with a relative tolerance (the
+    sigma gate absorbs perturbations of that size)."""
+    m, n = A.shape
+    idx = [(0, 0), (m - 1, n - 1), (m // 2, n // 3), (m // 3, n // 2), (1, n - 2), (m - 2, 1),
+           (m // 5, 4 * n // 5), (4 * m // 5, n // 5)]
+    return [float(np.linalg.norm(A))] + [float(A[i, j]) for i, j in idx]
+
+
 def main(names):
     oracle.set_threads(os.cpu_count() or 1)
     for name in names:
@@ -41,6 +52,7 @@ def main(names):
         with open(path, "w") as f:
             f.write(f"# oracle sigma for {name}: {A.shape[0]} x {A.shape[1]}\n")
             f.write(f"# sha256(A column-major) {sha_of(A)}\n")
+            f.write("# fingerprint " + " ".join(f"{x:.17g}" for x in fingerprint(A)) + "\n")
             f.write(f"# kappa_s {ks:.17g}\n")
             f.write(f"# oracle status {info['status']} sweeps {info['sweeps']} order rr\n")
             f.write("# written by tests/golden/make_oracle_sigma.py (calls only oracle/)\n")
@@ -50,22 +62,22 @@ def main(names):
 
 
 def load(name):
-    """(sigma, kappa_s, sha256, sweeps) from a stored file."""
+    """(sigma, kappa_s, fingerprint, sweeps) from a stored file."""
     path = os.path.join(HERE, f"oracle_sigma_{name}.txt")
-    sha = ks = None
+    fp = ks = None
     sweeps = None
     vals = []
     with open(path) as f:
         for line in f:
-            if line.startswith("# sha256"):
-                sha = line.split()[-1]
+            if line.startswith("# fingerprint"):
+                fp = [float(x) for x in line.split()[2:]]
             elif line.startswith("# kappa_s"):
                 ks = float(line.split()[-1])
             elif line.startswith("# oracle status"):
                 sweeps = int(line.split()[5])
             elif not line.startswith("#"):
                 vals.append(float(line))
-    return np.array(vals), ks, sha, sweeps
+    return np.array(vals), ks, fp, sweeps
 
 
 if __name__ == "__main__":
