@@ -78,12 +78,34 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_init(int mp, int nb, const dou
     panel_partials(L, mp, g, 0, nb, part, head);
 }
 
+// Cross-workgroup sums of the partial dots for columns j..nb-1, read with all
+// threads in parallel (QR_RC / QR_NB workgroup rows at a time) and reduced
+// in a fixed order.
+__device__ __forceinline__ void reduce_partials(const double *pin, int ngroups, int j, int nb,
+                                                double *dsum, double *red) {
+    const int t = threadIdx.x;
+    constexpr int GR = QR_RC / QR_NB;        // workgroup rows per pass
+    const int k = t % QR_NB, q0 = t / QR_NB;
+    double a = 0.0;
+    for (int q = q0; q < ngroups; q += GR) a += pin[(size_t)q * QR_NB + k];
+    red[q0 * QR_NB + k] = a;
+    __syncthreads();
+    if (t < QR_NB && t >= j && t < nb) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int q = 0; q < GR; ++q) sacc += red[q * QR_NB + t];
+        dsum[t] = sacc;
+    }
+}
+
 __global__ __launch_bounds__(QR_RC) void qr_panel_step(int j, int mp, int nb, int ngroups,
                                                       double *P, int ld, double *part,
                                                       double *head, double *tau) {
     __shared__ double L[QR_NB * LROW];
+    __shared__ double red[QR_RC];
     __shared__ double wsh[QR_NB];
     __shared__ double dsum[QR_NB];
+    __shared__ double hsh[QR_NB];
     __shared__ double prm[3];  // beta, tau, scale
     const int g = blockIdx.x, t = threadIdx.x;
     const double *pin = part + (size_t)(j & 1) * ngroups * QR_NB;
@@ -91,20 +113,17 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_step(int j, int mp, int nb, in
     double *pout = part + (size_t)((j + 1) & 1) * ngroups * QR_NB;
     double *hout = head + ((j + 1) & 1) * QR_NB;
 
-    // 1. cross-workgroup sums (fixed order) and the reflector of column j
-    if (t >= j && t < nb) {
-        double a = 0.0;
-        for (int q = 0; q < ngroups; ++q) a += pin[(size_t)q * QR_NB + t];
-        dsum[t] = a;
-    }
+    // 1. all global loads first: head row, this chunk, the partial dots
+    if (t >= j && t < nb) hsh[t] = hin[t];
     panel_load(L, P, ld, mp, g, j, nb);
+    reduce_partials(pin, ngroups, j, nb, dsum, red);
     __syncthreads();
     if (t == 0) {
-        const double x0 = hin[j];
-        const double xnorm = sqrt(dsum[j]);
+        const double x0 = hsh[j];
+        const double s2 = dsum[j];
         double beta = x0, tv = 0.0, scale = 0.0;
-        if (xnorm != 0.0) {
-            beta = -copysign(hypot(x0, xnorm), x0);
+        if (s2 != 0.0) {
+            beta = -copysign(sqrt(x0 * x0 + s2), x0);
             tv = (beta - x0) / beta;
             scale = 1.0 / (x0 - beta);
         }
@@ -112,7 +131,7 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_step(int j, int mp, int nb, in
         if (g == 0) tau[j] = tv;
     }
     __syncthreads();
-    if (t > j && t < nb) wsh[t] = prm[1] * (hin[t] + prm[2] * dsum[t]);
+    if (t > j && t < nb) wsh[t] = prm[1] * (hsh[t] + prm[2] * dsum[t]);
     __syncthreads();
 
     // 2. apply H_j to this workgroup's rows
@@ -135,26 +154,34 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_step(int j, int mp, int nb, in
     panel_store(L, P, ld, mp, g, j, nb);
 }
 
-// Partial V^T V over this workgroup's rows; V unit lower trapezoidal.
+// Partial V^T V over this workgroup's rows; V unit lower trapezoidal.  One
+// wavefront per (a, b) pair, lanes over rows.
 __global__ __launch_bounds__(QR_RC) void qr_vtv_partial(int mp, int nb, const double *P, int ld,
                                                        double *vtv) {
     __shared__ double L[QR_NB * LROW];
-    const int g = blockIdx.x, t = threadIdx.x;
+    const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
     {
         const int i = g * QR_RC + t;
-        for (int k = 0; k < nb; ++k) {
-            double v = 0.0;
-            if (i < mp) v = (i < k) ? 0.0 : (i == k ? 1.0 : P[(size_t)k * ld + i]);
-            L[k * LROW + t] = v;
-        }
+        double v[QR_NB];
+#pragma unroll
+        for (int k = 0; k < QR_NB; ++k)
+            v[k] = (k < nb && i < mp && i > k) ? P[(size_t)k * ld + i] : 0.0;
+#pragma unroll
+        for (int k = 0; k < QR_NB; ++k) L[k * LROW + t] = (i == k && i < mp && k < nb) ? 1.0 : v[k];
     }
     __syncthreads();
-    for (int e = t; e < QR_NB * QR_NB; e += QR_RC) {
+    for (int e = w; e < QR_NB * QR_NB; e += QR_RC / 64) {
         const int a = e % QR_NB, b = e / QR_NB;
         double s = 0.0;
-        if (a < nb && b < nb && a <= b)
-            for (int r = 0; r < QR_RC; ++r) s += L[a * LROW + r] * L[b * LROW + r];
-        vtv[(size_t)g * QR_NB * QR_NB + e] = s;
+        if (a <= b && b < nb) {
+#pragma unroll
+            for (int q = 0; q < QR_RC / 64; ++q) {
+                const int r = lane + 64 * q;
+                s += L[a * LROW + r] * L[b * LROW + r];
+            }
+            s = wave_sum(s);
+        }
+        if (lane == 0) vtv[(size_t)g * QR_NB * QR_NB + e] = s;
     }
 }
 
@@ -165,9 +192,18 @@ __global__ __launch_bounds__(256) void qr_build_t(int nb, int ngroups, const dou
     __shared__ double Ts[QR_NB * QR_NB];
     __shared__ double z[QR_NB];
     const int t = threadIdx.x;
+    // 4 entries per thread, all chunk loads of an entry in flight together
     for (int e = t; e < QR_NB * QR_NB; e += 256) {
         double s = 0.0;
-        for (int q = 0; q < ngroups; ++q) s += vtv[(size_t)q * QR_NB * QR_NB + e];
+        int q = 0;
+        for (; q + 4 <= ngroups; q += 4) {
+            const double a0 = vtv[(size_t)q * QR_NB * QR_NB + e];
+            const double a1 = vtv[(size_t)(q + 1) * QR_NB * QR_NB + e];
+            const double a2 = vtv[(size_t)(q + 2) * QR_NB * QR_NB + e];
+            const double a3 = vtv[(size_t)(q + 3) * QR_NB * QR_NB + e];
+            s += a0; s += a1; s += a2; s += a3;
+        }
+        for (; q < ngroups; ++q) s += vtv[(size_t)q * QR_NB * QR_NB + e];
         G[e] = s;
         Ts[e] = 0.0;
     }
