@@ -14,13 +14,20 @@ log-uniform in [1e-12, 1], seed 4 (testmats.config_c3b).  Inputs are resident
 in HBM before the timed region starts.
 
 Prints one JSON line.  Options: --gpus (only 1), --steps K, --warmup W,
---n (size), --no-cpu-baseline, --cpu-sample-n.
+--n (size), --mode (both | mixed | plain: "both" is the metric, the others are
+for profiling runs), --no-cpu-baseline, --cpu-sample-n.
+
+roofline.traffic is the HBM traffic per launch of the dominant kernel from
+the counter runs recorded in profiles/qrcp_step_reg_f32_n4096_traffic.md; it
+is reported only while the kernel's sources hash to the value recorded there.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -44,6 +51,38 @@ def algorithmic_flops(n: int, info: dict, mixed: bool) -> float:
             f += info["sweeps_low"] * 4 * n * n * (n - 1) + 4.7 * n ** 3
     f += info["sweeps_work"] * 7 * n * n * (n - 1)
     return f
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "qrcp_step_reg_f32_n4096_traffic.md")
+TRAFFIC_SOURCES = ["paper_2209_04626_amd/csrc/qrcp.hip", "paper_2209_04626_amd/csrc/common.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(n: int):
+    """HBM bytes per launch of the pivot step kernel measured with the
+    FETCH_SIZE / WRITE_SIZE counters (copy-calibrated), or None when there is
+    no record for this size or the kernel has changed since."""
+    if n != 4096 or not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            m = re.match(r"^- (\w+): `?([^`\s]+)`?", line.strip())
+            if m:
+                rec[m.group(1)] = m.group(2)
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def gates_gpu(A, U, S, V, s_ref, kappa_s):
@@ -96,6 +135,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--mode", choices=("both", "mixed", "plain"), default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=1024)
     args = ap.parse_args()
@@ -120,9 +160,13 @@ def main() -> int:
     opts_mixed = mp.default_opts(True)
     opts_plain = mp.default_opts(False)
 
+    do_mixed = args.mode in ("both", "mixed")
+    do_plain = args.mode in ("both", "plain")
     for _ in range(args.warmup):
-        mp.svd(A, "mixed", workspace=ws, opts=opts_mixed)
-        mp.svd(A, "plain", workspace=ws, opts=opts_plain)
+        if do_mixed:
+            mp.svd(A, "mixed", workspace=ws, opts=opts_mixed)
+        if do_plain:
+            mp.svd(A, "plain", workspace=ws, opts=opts_plain)
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
@@ -130,24 +174,29 @@ def main() -> int:
     # step) is clocked with HIP events on the library's stream, one interval
     # per pass of n back-to-back launches
     opts_mixed.kernel_timing = 1
-    infos = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        Um, Sm, Vm, info = mp.svd(A, "mixed", workspace=ws, opts=opts_mixed)
-        infos.append(info)
-    torch.cuda.synchronize()
-    t_mixed = (time.perf_counter() - t0) / args.steps
-    print(f"[bench] mixed {t_mixed * 1e3:.1f} ms/SVD", file=sys.stderr, flush=True)
+    opts_plain.kernel_timing = 1
+    infos, infos_p = [], []
+    t_mixed = t_plain = None
+    if do_mixed:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            Um, Sm, Vm, info = mp.svd(A, "mixed", workspace=ws, opts=opts_mixed)
+            infos.append(info)
+        torch.cuda.synchronize()
+        t_mixed = (time.perf_counter() - t0) / args.steps
+        print(f"[bench] mixed {t_mixed * 1e3:.1f} ms/SVD", file=sys.stderr, flush=True)
 
     # K plain SVDs on the same matrix
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        Up, Sp, Vp, info_p = mp.svd(A, "plain", workspace=ws, opts=opts_plain)
-    torch.cuda.synchronize()
-    t_plain = (time.perf_counter() - t0) / args.steps
-    print(f"[bench] plain {t_plain * 1e3:.1f} ms/SVD", file=sys.stderr, flush=True)
+    if do_plain:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            Up, Sp, Vp, info_p = mp.svd(A, "plain", workspace=ws, opts=opts_plain)
+            infos_p.append(info_p)
+        torch.cuda.synchronize()
+        t_plain = (time.perf_counter() - t0) / args.steps
+        print(f"[bench] plain {t_plain * 1e3:.1f} ms/SVD", file=sys.stderr, flush=True)
 
     # gates against the stored oracle sigma (when this size has one)
     s_ref, kappa = None, None
@@ -160,51 +209,63 @@ def main() -> int:
                 raise RuntimeError("regenerated input differs from the one the stored sigma is for")
         except FileNotFoundError:
             s_ref = None
-    g_mixed = gates_gpu(A, Um, Sm, Vm, s_ref, kappa or 1.0)
-    g_plain = gates_gpu(A, Up, Sp, Vp, s_ref, kappa or 1.0)
+    g_mixed = gates_gpu(A, Um, Sm, Vm, s_ref, kappa or 1.0) if do_mixed else None
+    g_plain = gates_gpu(A, Up, Sp, Vp, s_ref, kappa or 1.0) if do_plain else None
 
-    # dominant kernel of the timed region and its roofline
-    K = len(infos)
-    ms = np.sum([i["kern_ms"] for i in infos], axis=0)
-    calls = np.sum([i["kern_calls"] for i in infos], axis=0)
-    byts = np.sum([i["kern_bytes"] for i in infos], axis=0)
-    dom = 6  # qrcp_step: the largest kernel class of the path by total time
-    avg_s = ms[dom] / 1e3 / max(calls[dom], 1)
-    bytes_per_launch = byts[dom] / max(calls[dom], 1)
-    achieved = bytes_per_launch / avg_s / 1e9
-    roofline = {
-        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-        "kernel": mp.KERNEL_CLASSES[dom], "avg_us": round(avg_s * 1e6, 2),
-        "launches": int(calls[dom]), "bytes_per_launch": bytes_per_launch,
-    }
+    # dominant kernel of the timed region (the FP32 pivot step of the mixed
+    # path) and its roofline
+    roofline = None
+    if do_mixed:
+        ms = np.sum([i["kern_ms"] for i in infos], axis=0)
+        calls = np.sum([i["kern_calls"] for i in infos], axis=0)
+        byts = np.sum([i["kern_bytes"] for i in infos], axis=0)
+        dom = mp.KERNEL_CLASSES.index("qrcp_step")
+        avg_s = ms[dom] / 1e3 / max(calls[dom], 1)
+        bytes_per_launch = byts[dom] / max(calls[dom], 1)
+        achieved = bytes_per_launch / avg_s / 1e9
+        traffic = recorded_traffic(n)
+        roofline = {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic),
+            "kernel": "qrcp_step_reg<float,64>", "avg_us": round(avg_s * 1e6, 2),
+            "launches": int(calls[dom]), "bytes_per_launch": round(bytes_per_launch),
+        }
 
-    info = infos[-1]
-    flops = algorithmic_flops(n, info, True)
     line = {
         "metric": "n=4096 SVD time: mixed vs plain FP64 Jacobi, same GPU, sigma rel err <=1e-13",
-        "value": round(t_plain / t_mixed, 4),
+        "value": round(t_plain / t_mixed, 4) if (t_plain and t_mixed) else None,
         "unit": "x (T_plain / T_mixed)",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(t_mixed * 1e3, 2),
+        "ms_per_step": round((t_mixed or t_plain) * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": f"C3b: {n}x{n} FP64, A = U diag(sigma) V^T, Haar U/V, "
                                f"sigma log-uniform in [1e-12, 1], seed 4; U and V formed",
-                   "m": n, "n": n},
-        "mixed_ms": round(t_mixed * 1e3, 2), "plain_ms": round(t_plain * 1e3, 2),
-        "mixed_svd_per_s": round(1.0 / t_mixed, 4), "plain_svd_per_s": round(1.0 / t_plain, 4),
-        "mixed_gflops": round(flops / t_mixed / 1e9, 1),
-        "mixed_info": {k: info[k] for k in ("status", "branch_taken", "sweeps_low", "sweeps_work",
-                                            "orth", "cond_r")},
-        "mixed_off_trace": {"fp32": [float("%.3g" % x) for x in info["off_low"]],
-                            "fp64": [float("%.3g" % x) for x in info["off_work"]]},
-        "mixed_stage_ms": [round(x, 2) for x in info["stage_ms"]],
-        "plain_info": {k: info_p[k] for k in ("status", "sweeps_work")},
-        "plain_stage_ms": [round(x, 2) for x in info_p["stage_ms"]],
-        "gates_mixed": g_mixed, "gates_plain": g_plain,
-        "roofline": roofline,
+                   "m": n, "n": n, "mode": args.mode},
     }
+    if do_mixed:
+        info = infos[-1]
+        flops = algorithmic_flops(n, info, True)
+        line.update({
+            "mixed_ms": round(t_mixed * 1e3, 2), "mixed_svd_per_s": round(1.0 / t_mixed, 4),
+            "mixed_gflops": round(flops / t_mixed / 1e9, 1),
+            "mixed_info": {k: info[k] for k in ("status", "branch_taken", "sweeps_low", "sweeps_work",
+                                                "orth", "cond_r")},
+            "mixed_off_trace": {"fp32": [float("%.3g" % x) for x in info["off_low"]],
+                                "fp64": [float("%.3g" % x) for x in info["off_work"]]},
+            "mixed_stage_ms": [round(x, 2) for x in info["stage_ms"]],
+            "gates_mixed": g_mixed,
+        })
+    if do_plain:
+        info_p = infos_p[-1]
+        line.update({
+            "plain_ms": round(t_plain * 1e3, 2), "plain_svd_per_s": round(1.0 / t_plain, 4),
+            "plain_info": {k: info_p[k] for k in ("status", "sweeps_work")},
+            "plain_stage_ms": [round(x, 2) for x in info_p["stage_ms"]],
+            "gates_plain": g_plain,
+        })
+    line["roofline"] = roofline
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_sample_n)

@@ -80,7 +80,7 @@ Layout layout(int m, int n, const svd_opts &o) {
     L.off_t0 = take(nblk * d);
     L.off_a1 = take(nn * d);
     L.off_wp = take(nn * d);
-    L.off_nrm2 = take((size_t)2 * n * d);
+    L.off_nrm2 = take(qrcp_scratch_bytes(n, (int)d));
     L.off_piv = take((size_t)n * sizeof(int));
     L.off_a1p = take(nn * d);
     L.off_tau1 = take((size_t)n * d);
@@ -241,9 +241,9 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     if (o.kernel_timing == 1)
         kclock.begin(s, SVD_K_QRCP, 0.0);
     if (o.pivot_precision == 32)
-        qrcp_pivots<float>(s, n, A1, n, (float *)D(L.off_wp), (float *)D(L.off_nrm2), piv, jw.kc);
+        qrcp_pivots<float>(s, n, A1, n, (float *)D(L.off_wp), w + L.off_nrm2, piv, jw.kc);
     else
-        qrcp_pivots<double>(s, n, A1, n, D(L.off_wp), D(L.off_nrm2), piv, jw.kc);
+        qrcp_pivots<double>(s, n, A1, n, D(L.off_wp), w + L.off_nrm2, piv, jw.kc);
     if (o.kernel_timing == 1) {
         kclock.end(s);
         // launches and algorithmic bytes of the whole pass (see qrcp_pivots)

@@ -100,11 +100,12 @@ void qr_apply_left(hipStream_t s, bool trans, int m, int k, const double *Qf,
 
 // ---------------------------------------------------------------- QRCP
 // Businger-Golub pivot selection on a working copy of the n x n matrix A1:
-// piv[k] = column chosen at step k.  W holds n*n elements of T; norms2 holds
-// 2n elements of T.
+// piv[k] = column chosen at step k.  W holds n*n elements of T; scratch holds
+// qrcp_scratch_bytes(n, sizeof(T)) bytes.
+size_t qrcp_scratch_bytes(int n, int elem);
 template <typename T>
 void qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W,
-                 T *norms2, int *piv, KernelClock *kc = nullptr);
+                 void *scratch, int *piv, KernelClock *kc = nullptr);
 
 // ---------------------------------------------------------------- Jacobi
 struct JacobiWork {

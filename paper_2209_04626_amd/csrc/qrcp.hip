@@ -11,6 +11,9 @@
 // double-buffered between launches so that the pivot every workgroup reads
 // is the one all of them read.  Columns stay in place; a used column is
 // marked by a norm of -1.
+#include <climits>
+
+#include "../../include/mpjsvd.h"
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -126,152 +129,238 @@ __global__ __launch_bounds__(CP_NT) void qrcp_step(int k, int n, T *W, const T *
 }
 
 
-// Register-cached step: one wavefront per owned column, the column's rows
-// k..n-1 are loaded into registers with all loads in flight, then the dot
-// product, the update and the new trailing norm are computed from registers
-// and the column is stored once.  Requires n <= 64 * RPL.
-constexpr int CR_NT = 512;            // 8 wavefronts = 8 columns per workgroup
-constexpr int CR_W = CR_NT / 64;
+// Register-cached step with column compaction (n <= 64 * RPL).
+//
+// Before step k the live positions are k..n-1; position j holds the data of
+// working column perm[j] (columns never move; perm is the indirection).  Step
+// k takes the pivot position p from the per-workgroup candidates of step k-1
+// (largest trailing norm, ties to the smallest column index), exchanges
+// positions k and p (position p now refers to the column that sat at k), and
+// updates the live positions k+1..n-1 with the reflector of the pivot column.
+// One wavefront owns one position: its column's rows k..n-1 are held in
+// registers (row k + lane + 64 r in x[r]), loaded before the pivot is known,
+// and stored once.  The reflector needs only the pivot's row-k entry and its
+// trailing norm (carried in the candidate), so the pivot column is staged in
+// LDS only for the dot products.  Each workgroup leaves the best of its new
+// trailing norms (rows k+1..n-1) as the candidate for step k+1.
+constexpr int Q2_NT = 512;            // 8 wavefronts = 8 positions per workgroup
+constexpr int Q2_W = Q2_NT / 64;
 
-template <typename T, int RPL>
-__global__ __launch_bounds__(CR_NT) void qrcp_step_reg(int k, int n, T *W, const T *nin, T *nout,
-                                                       int *piv) {
-    __shared__ T pc[CP_MAXN];
-    __shared__ T rv[CR_W];
-    __shared__ int ri[CR_W];
-    __shared__ T red[CR_W];
-    __shared__ T prm[2];
-    __shared__ int psh;
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int j = blockIdx.x * CR_W + w;
+template <typename T>
+struct Cand {
+    T v;
+    int pos, col;
+};
 
-    // the owned column: start its loads before the pivot search
-    T x[RPL];
-    const bool live = j < n && nin[j] >= T(0);
-    if (live) {
-        const T *col = W + (size_t)j * n;
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            const int i = lane + 64 * r;
-            x[r] = (i >= k && i < n) ? col[i] : T(0);
-        }
-    }
-
-    // 1. pivot: argmax of the remaining norms, ties to the smallest index
-    T best = -2;
-    int bi = n;
-    for (int q = t; q < n; q += CR_NT) {
-        const T v = nin[q];
-        if (v > best) { best = v; bi = q; }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const T ov = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-    }
-    if (lane == 0) { rv[w] = best; ri[w] = bi; }
-    __syncthreads();
-    if (t == 0) {
-        T b = rv[0];
-        int i = ri[0];
-        for (int q = 1; q < CR_W; ++q)
-            if (rv[q] > b || (rv[q] == b && ri[q] < i)) { b = rv[q]; i = ri[q]; }
-        psh = i;
-        if (blockIdx.x == 0) piv[k] = i;
-    }
-    __syncthreads();
-    const int p = psh;
-
-    // 2. reflector of the pivot column from rows k..n-1
-    T s = 0;
-    for (int i = k + t; i < n; i += CR_NT) {
-        const T v = W[(size_t)p * n + i];
-        pc[i] = v;
-        if (i > k) s += v * v;
-    }
-    s = block_sum<CR_NT>(s, red);
-    if (t == 0) {
-        const T x0 = pc[k];
-        T tau = 0, scale = 0;
-        if (s != T(0)) {
-            const T beta = -copysign(tsqrt(x0 * x0 + s), x0);
-            tau = (beta - x0) / beta;
-            scale = T(1) / (x0 - beta);
-        }
-        prm[0] = tau; prm[1] = scale;
-    }
-    __syncthreads();
-    if (j >= n) return;
-    if (!live || j == p) {
-        if (lane == 0) nout[j] = T(-1);
-        return;
-    }
-    const T tau = prm[0], scale = prm[1];
-
-    // 3. update the owned column from registers, store once
-    T d = 0;
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int i = lane + 64 * r;
-        if (i > k && i < n) d += pc[i] * x[r];
-    }
-    d = wave_sum(d);
-    const int qk = k / 64, rk = k % 64;
-    T xk = 0;
-#pragma unroll
-    for (int r = 0; r < RPL; ++r)
-        if (r == qk) xk = x[r];
-    xk = __shfl(xk, rk, 64);
-    const T wv = tau * (xk + scale * d);
-    T ns = 0;
-    T *col = W + (size_t)j * n;
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int i = lane + 64 * r;
-        if (i > k && i < n) {
-            const T v = x[r] - wv * scale * pc[i];
-            col[i] = v;
-            ns += v * v;
-        } else if (i == k) {
-            col[i] = x[r] - wv;
-        }
-    }
-    ns = wave_sum(ns);
-    if (lane == 0) nout[j] = tsqrt(ns);
+template <typename T>
+__device__ __forceinline__ bool cand_better(T v, int c, T bv, int bc) {
+    return v > bv || (v == bv && c < bc);
 }
 
 template <typename T>
-void qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, T *norms2, int *piv,
+__global__ __launch_bounds__(Q2_NT) void qrcp_init2(int n, const double *A1, int lda, T *W,
+                                                    int *perm, Cand<T> *cout) {
+    __shared__ T cv[Q2_W];
+    __shared__ int cc[Q2_W];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = blockIdx.x * Q2_W + w;
+    T s = 0;
+    if (j < n) {
+        for (int i = lane; i < n; i += 64) {
+            const T v = (T)A1[(size_t)j * lda + i];
+            W[(size_t)j * n + i] = v;
+            s += v * v;
+        }
+    }
+    s = wave_sum(s);
+    if (lane == 0) {
+        cv[w] = j < n ? tsqrt(s) : T(-1);
+        cc[w] = j < n ? j : INT_MAX;
+        if (j < n) perm[j] = j;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T bv = cv[0];
+        int bc = cc[0];
+        for (int q = 1; q < Q2_W; ++q)
+            if (cand_better(cv[q], cc[q], bv, bc)) { bv = cv[q]; bc = cc[q]; }
+        cout[blockIdx.x] = Cand<T>{bv, bc, bc};
+    }
+}
+
+template <typename T, int RPL>
+__global__ __launch_bounds__(Q2_NT) void qrcp_step2(int k, int n, T *__restrict__ W,
+                                                    int *__restrict__ perm,
+                                                    const Cand<T> *__restrict__ cin, int ncin,
+                                                    Cand<T> *__restrict__ cout,
+                                                    int *__restrict__ piv) {
+    __shared__ T pc[64 * RPL];
+    __shared__ T rv[Q2_W];
+    __shared__ int rp[Q2_W], rc[Q2_W];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int j = k + 1 + blockIdx.x * Q2_W + w;
+    const bool live = j < n;
+    const int m = n - k;                      // rows k..n-1
+
+    // the owned position's column, loaded before the pivot is known
+    int col = live ? perm[j] : 0;
+    T x[RPL];
+    auto load = [&](int c) {
+        const T *src = W + (size_t)c * n + k;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = lane + 64 * r;
+            x[r] = i < m ? src[i] : T(0);
+        }
+    };
+    if (live) load(col);
+
+    // 1. pivot: best of the previous step's candidates
+    T bv = T(-2);
+    int bp = -1, bc = INT_MAX;
+    if (t < ncin) {
+        const Cand<T> c = cin[t];
+        bv = c.v; bp = c.pos; bc = c.col;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const T ov = __shfl_xor(bv, o, 64);
+        const int op = __shfl_xor(bp, o, 64);
+        const int oc = __shfl_xor(bc, o, 64);
+        if (cand_better(ov, oc, bv, bc)) { bv = ov; bp = op; bc = oc; }
+    }
+    if (lane == 0) { rv[w] = bv; rp[w] = bp; rc[w] = bc; }
+    __syncthreads();
+    bv = rv[0]; bp = rp[0]; bc = rc[0];
+#pragma unroll
+    for (int q = 1; q < Q2_W; ++q)
+        if (cand_better(rv[q], rc[q], bv, bc)) { bv = rv[q]; bp = rp[q]; bc = rc[q]; }
+    const int p = bp, pcol = bc;
+    const T pnorm = bv;
+
+    // 2. stage the pivot column (rows k..n-1); position p takes over the
+    // column that sat at position k
+    {
+        const T *src = W + (size_t)pcol * n + k;
+        for (int i = t; i < m; i += Q2_NT) pc[i] = src[i];
+    }
+    if (blockIdx.x == 0 && t == 0) piv[k] = pcol;
+    if (live && j == p) {
+        col = perm[k];
+        load(col);
+        if (lane == 0) perm[p] = col;
+    }
+    __syncthreads();
+
+    // 3. reflector H = I - tau v v^T with v = [1; x(k+1:)/(x_k - beta)]
+    T tau = 0, scale = 0;
+    {
+        const T x0 = pc[0];
+        if (pnorm > T(0)) {
+            const T beta = -copysign(pnorm, x0);
+            tau = (beta - x0) / beta;
+            scale = T(1) / (x0 - beta);
+        }
+    }
+
+    // 4. apply it to the owned column, store rows k+1..n-1, new trailing norm
+    T nv = T(-1);
+    if (live) {
+        T d = 0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = lane + 64 * r;
+            if (i >= 1 && i < m) d += pc[i] * x[r];
+        }
+        d = wave_sum(d);
+        const T xk = __shfl(x[0], 0, 64);
+        const T wv = tau * (xk + scale * d);
+        const T f = wv * scale;
+        T ns = 0;
+        T *dst = W + (size_t)col * n + k;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = lane + 64 * r;
+            if (i >= 1 && i < m) {
+                const T v = x[r] - f * pc[i];
+                dst[i] = v;
+                ns += v * v;
+            }
+        }
+        nv = tsqrt(wave_sum(ns));
+    }
+
+    // 5. this workgroup's candidate for step k+1
+    __syncthreads();   // rv/rp/rc are reused
+    if (lane == 0) { rv[w] = nv; rp[w] = live ? j : -1; rc[w] = live ? col : INT_MAX; }
+    __syncthreads();
+    if (t == 0) {
+        T cv = rv[0];
+        int cp = rp[0], cc = rc[0];
+        for (int q = 1; q < Q2_W; ++q)
+            if (cand_better(rv[q], rc[q], cv, cc)) { cv = rv[q]; cp = rp[q]; cc = rc[q]; }
+        cout[blockIdx.x] = Cand<T>{cv, cp, cc};
+    }
+}
+
+size_t qrcp_scratch_bytes(int n, int elem) {
+    // fallback: two norm vectors; compacted step: perm + two candidate arrays
+    const size_t a = (size_t)2 * n * elem;
+    const size_t ncand = (size_t)cdiv(n, Q2_W) + 1;
+    const size_t b = (size_t)n * sizeof(int) + 64 + 2 * ncand * sizeof(Cand<double>);
+    return a > b ? a : b;
+}
+
+template <typename T>
+void qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, void *scratch, int *piv,
                  KernelClock *kc) {
     if (n <= 0) return;
-    hipLaunchKernelGGL((qrcp_init<T>), dim3(cdiv(n, CP_NT / 64)), dim3(CP_NT), 0, s, n, A1, lda, W,
-                       norms2);
+    if (n > 64 * 64) {
+        T *norms2 = (T *)scratch;
+        hipLaunchKernelGGL((qrcp_init<T>), dim3(cdiv(n, CP_NT / 64)), dim3(CP_NT), 0, s, n, A1, lda,
+                           W, norms2);
+        for (int k = 0; k < n; ++k) {
+            const T *nin = norms2 + (size_t)(k & 1) * n;
+            T *nout = norms2 + (size_t)((k + 1) & 1) * n;
+            const double m = n - k;
+            if (kc) kc->begin(s, SVD_K_QRCP, (2.0 * m * (m - 1) + m) * sizeof(T));
+            hipLaunchKernelGGL((qrcp_step<T>), dim3(cdiv(n, CP_CPW)), dim3(CP_NT), 0, s, k, n, W, nin,
+                               nout, piv);
+            if (kc) kc->end(s);
+        }
+        return;
+    }
+    int *perm = (int *)scratch;
+    const size_t ncand = (size_t)cdiv(n, Q2_W) + 1;
+    Cand<T> *cand = (Cand<T> *)((char *)scratch + (((size_t)n * sizeof(int) + 63) / 64) * 64);
+    hipLaunchKernelGGL((qrcp_init2<T>), dim3(cdiv(n, Q2_W)), dim3(Q2_NT), 0, s, n, A1, lda, W, perm,
+                       cand);
     for (int k = 0; k < n; ++k) {
-        const T *nin = norms2 + (size_t)(k & 1) * n;
-        T *nout = norms2 + (size_t)((k + 1) & 1) * n;
-        const dim3 g(cdiv(n, CR_W));
+        const Cand<T> *cin = cand + (size_t)(k & 1) * ncand;
+        Cand<T> *cout = cand + (size_t)((k + 1) & 1) * ncand;
+        const int ncin = cdiv(n - k, Q2_W);
+        const int nwg = n - k - 1 > 0 ? cdiv(n - k - 1, Q2_W) : 1;
         // algorithmic bytes of step k: the active trailing block (rows k..n-1
         // of the n-k-1 remaining columns) read and written once, the pivot
         // column read once
         const double m = n - k;
-        if (kc) kc->begin(s, 6, (2.0 * m * (m - 1) + m) * sizeof(T));
+        if (kc) kc->begin(s, SVD_K_QRCP, (2.0 * m * (m - 1) + m) * sizeof(T));
         if (n <= 64 * 16)
-            hipLaunchKernelGGL((qrcp_step_reg<T, 16>), g, dim3(CR_NT), 0, s, k, n, W, nin, nout, piv);
+            hipLaunchKernelGGL((qrcp_step2<T, 16>), dim3(nwg), dim3(Q2_NT), 0, s, k, n, W, perm, cin,
+                               ncin, cout, piv);
         else if (n <= 64 * 32)
-            hipLaunchKernelGGL((qrcp_step_reg<T, 32>), g, dim3(CR_NT), 0, s, k, n, W, nin, nout, piv);
-        else if (n <= 64 * 64)
-            hipLaunchKernelGGL((qrcp_step_reg<T, 64>), g, dim3(CR_NT), 0, s, k, n, W, nin, nout, piv);
+            hipLaunchKernelGGL((qrcp_step2<T, 32>), dim3(nwg), dim3(Q2_NT), 0, s, k, n, W, perm, cin,
+                               ncin, cout, piv);
         else
-            hipLaunchKernelGGL((qrcp_step<T>), dim3(cdiv(n, CP_CPW)), dim3(CP_NT), 0, s, k, n, W, nin,
-                               nout, piv);
+            hipLaunchKernelGGL((qrcp_step2<T, 64>), dim3(nwg), dim3(Q2_NT), 0, s, k, n, W, perm, cin,
+                               ncin, cout, piv);
         if (kc) kc->end(s);
     }
 }
 
-template void qrcp_pivots<float>(hipStream_t, int, const double *, int, float *, float *, int *,
+template void qrcp_pivots<float>(hipStream_t, int, const double *, int, float *, void *, int *,
                                  KernelClock *);
-template void qrcp_pivots<double>(hipStream_t, int, const double *, int, double *, double *, int *,
+template void qrcp_pivots<double>(hipStream_t, int, const double *, int, double *, void *, int *,
                                   KernelClock *);
 
 } // namespace mpj
