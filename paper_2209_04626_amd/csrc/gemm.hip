@@ -135,13 +135,8 @@ static void gemm_launch(hipStream_t s, int M, int N, int K, T alpha, const T *A,
     int nz = 1;
     if (K <= 0) {
         // C = beta C
-        if (split) {
-            hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_STORE>), dim3(tm, tn, 1), dim3(256), 0, s,
-                               M, N, 0, alpha, A, lda, B, ldb, beta, C, ldc, 16, (T *)nullptr, (float *)nullptr);
-        } else {
-            hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_STORE>), dim3(tm, tn, 1), dim3(256), 0, s,
-                               M, N, 0, alpha, A, lda, B, ldb, beta, C, ldc, 16, (T *)nullptr, (float *)nullptr);
-        }
+        hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_STORE>), dim3(tm, tn, 1), dim3(256), 0, s,
+                           M, N, 0, alpha, A, lda, B, ldb, beta, C, ldc, 16, (T *)nullptr, (float *)nullptr);
         return;
     }
     if (split && tiles < 512 && K >= 512) {

@@ -123,28 +123,85 @@ __device__ __forceinline__ void jac_rot(double al, double be, double ga, double 
     *c = cc; *s = tt * cc; *t = tt;
 }
 
+// 1/sqrt(x) and 1/x for x > 0 in FP64 from the hardware estimates refined by
+// NR Newton steps (each squares the relative error): two give FP64 accuracy,
+// one is ample when the rotation is rounded to FP32 afterwards.
+template <int NR>
+__device__ __forceinline__ double rsq64(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) r = r * fma(-h * r, r, 1.5);
+    return r;
+}
+template <int NR>
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) r = r * fma(-x, r, 2.0);
+    return r;
+}
+
+// The same rotation from d = beta - alpha and g2 = 2 gamma without forming
+// zeta: t = sign(zeta) |g2| / (|d| + sqrt(d^2 + g2^2)), c = 1/sqrt(1 + t^2),
+// s = t c, with the square roots and the quotient from refined hardware
+// estimates.  Returns false, with the identity, when the pair passes the test
+// g^2 <= eps^2 g_pp g_qq of Algorithm 1.
+template <int NR>
+__device__ __forceinline__ bool jac_rot_test(double al, double be, double ga, double eps2,
+                                             double *c, double *s, double *t) {
+    if (!(ga * ga > eps2 * al * be)) { *c = 1.0; *s = 0.0; *t = 0.0; return false; }
+    const double d = be - al, g2 = 2.0 * ga;
+    double tt;
+    if (d == 0.0) {
+        tt = 1.0;
+    } else if (fabs(d) < 1e150 && fabs(g2) < 1e150) {
+        const double h = fma(d, d, g2 * g2);
+        const double rh = rsq64<NR>(h);
+        double y = h * rh;                            // sqrt(h)
+        y = fma(0.5 * rh, fma(-y, y, h), y);
+        const double den = fabs(d) + y;
+        const double num = copysign(1.0, d) * g2;
+        tt = num * rcp64<NR>(den);
+    } else {
+        double cc, ss;
+        jac_rot(al, be, ga, &cc, &ss, &tt);
+    }
+    const double cc = rsq64<NR>(fma(tt, tt, 1.0));
+    *t = tt; *c = cc; *s = tt * cc;
+    return true;
+}
+
 // Inner solve of one block pair.  G and the accumulated W are held in the
 // stage's precision T (FP32 in the FP32 stage, FP64 in the FP64 stage); every
-// rotation angle and threshold test is evaluated in FP64.  The rotation test
-// |g_pq| > eps sqrt(g_pp g_qq) is evaluated squared (no square roots).  Each
-// round loads all of a thread's 2x2 groups of G and W entries first, then
-// updates and stores them, so the LDS latency is paid once per round.
+// rotation angle and threshold test is evaluated in FP64.
+//
+// Round rd rotates the column pairs of the round-robin schedule (pair k joins
+// (rd + k) mod (2b-1) and (rd - k) mod (2b-1); pair 0 joins rd and 2b-1).
+// Thread (a, g) computes the rotation of pair a from the current G and owns
+// the 2x2 groups {p_a, q_a} x {p_c, q_c} of G for its GPT pairs c (the groups
+// tile G) and RPT rows of W's column pair a.  Pair c's rotation comes from the
+// lane of the same wavefront whose pair is c (every wavefront holds every
+// pair index), so a round reads G from one LDS buffer, writes the rotated G
+// to the other, and needs a single barrier; no thread branches on its role.
 template <typename T, int B2, int NT>
 __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict__ Gp,
                                                 T *__restrict__ Wm, int *skip, int *flag,
                                                 double eps, int max_inner) {
     constexpr int LD = B2 + 1;
     constexpr int H = B2 / 2;
-    constexpr int TG = (H * H) / NT;      // 2x2 groups of G per thread
-    constexpr int TW = (B2 * H) / NT;     // W column-pair entries per thread
-    constexpr int TE = (B2 * B2) / NT;    // Gram entries per thread
-    static_assert(TG * NT == H * H && TW * NT == B2 * H && TE * NT == B2 * B2, "tiling");
-    __shared__ T G[B2 * LD];
+    constexpr int M = B2 - 1;
+    constexpr int CG = NT / H;            // thread groups along c
+    constexpr int GPT = H / CG;           // 2x2 groups per thread
+    constexpr int RPT = B2 / CG;          // W rows per thread
+    constexpr int TE = (B2 * B2) / NT;    // Gram entries per thread (set-up)
+    constexpr int NRS = sizeof(T) == 4 ? 1 : 2;
+    static_assert(CG * H == NT && GPT * CG == H && RPT * CG == B2 && TE * NT == B2 * B2,
+                  "tiling");
+    static_assert(64 % H == 0, "every wavefront holds every pair index");
+    __shared__ T G[2][B2 * LD];
     __shared__ T W[B2 * LD];
-    __shared__ T ca[B2], cb[B2];
-    __shared__ T tt[H];
-    __shared__ int ired[NT / 64 > 0 ? NT / 64 : 1];
-    __shared__ int any_rot;
+    __shared__ int ired[NT / 64];
     const int pair = blockIdx.x, tid = threadIdx.x;
     const double eps2 = eps * eps;
 
@@ -154,17 +211,26 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
         double acc[TE];
 #pragma unroll
         for (int k = 0; k < TE; ++k) acc[k] = 0.0;
-        for (int c = 0; c < nchunk; ++c) {
-            T v[TE];
+        int c = 0;
+        for (; c + 4 <= nchunk; c += 4) {
+            T v[4][TE];
 #pragma unroll
-            for (int k = 0; k < TE; ++k) v[k] = gp[(size_t)c * B2 * B2 + tid + k * NT];
+            for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int k = 0; k < TE; ++k) acc[k] += (double)v[k];
+                for (int k = 0; k < TE; ++k) v[u][k] = gp[(size_t)(c + u) * B2 * B2 + tid + k * NT];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < TE; ++k) acc[k] += (double)v[u][k];
+        }
+        for (; c < nchunk; ++c) {
+#pragma unroll
+            for (int k = 0; k < TE; ++k) acc[k] += (double)gp[(size_t)c * B2 * B2 + tid + k * NT];
         }
 #pragma unroll
         for (int k = 0; k < TE; ++k) {
             const int e = tid + k * NT, i = e % B2, j = e / B2;
-            if (i <= j) { G[i * LD + j] = (T)acc[k]; G[j * LD + i] = (T)acc[k]; }
+            if (i <= j) { G[0][i * LD + j] = (T)acc[k]; G[0][j * LD + i] = (T)acc[k]; }
             W[i * LD + j] = (i == j) ? T(1) : T(0);
         }
     }
@@ -178,8 +244,8 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
     for (int k = 0; k < TE; ++k) {
         const int e = tid + k * NT, p = e % B2, q = e / B2;
         if (p < q) {
-            const double g = (double)G[p * LD + q];
-            const double pq = (double)G[p * LD + p] * (double)G[q * LD + q];
+            const double g = (double)G[0][p * LD + q];
+            const double pq = (double)G[0][p * LD + p] * (double)G[0][q * LD + q];
             if (g * g > eps2 * pq) need = 1;
             if (pq > 0.0) offmax = fmaxf(offmax, (float)(fabs(g) / sqrt(pq)));
         }
@@ -194,95 +260,88 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
     if (tid == 0) { skip[pair] = 0; *flag = 1; }
 
     // 3. cyclic rounds of disjoint rotations on G, accumulating W = prod J
-    float smax = 0.f;   // largest |sin| of the rotations this thread computed
+    const int a = tid % H, cg = tid / H;
+    const int c0 = cg * GPT, w0 = cg * RPT;
+    const bool own_diag = a / GPT == cg;      // this thread holds group (a, a)
+    const int kd = a % GPT;
+    // schedule positions of pair a and of the thread's pairs c at round 0
+    int ax = a, ay = a == 0 ? M : M - a;
+    int cx[GPT], cy[GPT];
+#pragma unroll
+    for (int k = 0; k < GPT; ++k) {
+        const int c = c0 + k;
+        cx[k] = c;
+        cy[k] = c == 0 ? M : M - c;
+    }
+    float smax = 0.f;   // largest |sin| of the rotations of pair a (owner only)
+    int cur = 0;
     for (int sw = 0; sw < max_inner; ++sw) {
-        __syncthreads();
-        if (tid == 0) any_rot = 0;
-        __syncthreads();
-        for (int rd = 0; rd < B2 - 1; ++rd) {
-            if (tid < H) {
-                int p, q;
-                rr_slot(B2, rd, tid, &p, &q);
-                const double al = (double)G[p * LD + p], be = (double)G[q * LD + q];
-                const double ga = (double)G[p * LD + q];
-                double c = 1.0, s = 0.0, t = 0.0;
-                if (ga * ga > eps2 * al * be) {
-                    jac_rot(al, be, ga, &c, &s, &t);
-                    any_rot = 1;
-                    smax = fmaxf(smax, (float)fabs(s));
+        int rotated = 0;
+        for (int rd = 0; rd < M; ++rd) {
+            const T *g = G[cur];
+            T *gn = G[cur ^ 1];
+            const int p = min(ax, ay), q = max(ax, ay);
+            const double alp = (double)g[p * LD + p], bep = (double)g[q * LD + q];
+            const double gap = (double)g[p * LD + q];
+            int r[GPT], s[GPT];
+            T blk[GPT][4];
+#pragma unroll
+            for (int k = 0; k < GPT; ++k) {
+                r[k] = min(cx[k], cy[k]);
+                s[k] = max(cx[k], cy[k]);
+                blk[k][0] = g[p * LD + r[k]]; blk[k][1] = g[p * LD + s[k]];
+                blk[k][2] = g[q * LD + r[k]]; blk[k][3] = g[q * LD + s[k]];
+            }
+            T wp[RPT], wq[RPT];
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                wp[j] = W[(w0 + j) * LD + p];
+                wq[j] = W[(w0 + j) * LD + q];
+            }
+            double ca, sa, ta;
+            const bool ra = jac_rot_test<NRS>(alp, bep, gap, eps2, &ca, &sa, &ta);
+            if (own_diag && ra) {
+                rotated = 1;
+                smax = fmaxf(smax, (float)fabs(sa));
+            }
+            const T c1 = (T)ca, s1 = (T)sa;
+            // W <- W J on the column pair (p, q): x_p' = c x_p - s x_q, x_q' = s x_p + c x_q
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                W[(w0 + j) * LD + p] = c1 * wp[j] - s1 * wq[j];
+                W[(w0 + j) * LD + q] = s1 * wp[j] + c1 * wq[j];
+            }
+            // G <- J^T G J on the groups: rows (p, q) by pair a, columns (r, s) by pair c
+#pragma unroll
+            for (int k = 0; k < GPT; ++k) {
+                const T c2 = (T)__shfl(ca, c0 + k, 64), s2 = (T)__shfl(sa, c0 + k, 64);
+                const T h00 = c1 * blk[k][0] - s1 * blk[k][2], h01 = c1 * blk[k][1] - s1 * blk[k][3];
+                const T h10 = s1 * blk[k][0] + c1 * blk[k][2], h11 = s1 * blk[k][1] + c1 * blk[k][3];
+                T o00 = c2 * h00 - s2 * h01, o01 = s2 * h00 + c2 * h01;
+                T o10 = c2 * h10 - s2 * h11, o11 = s2 * h10 + c2 * h11;
+                if (own_diag && k == kd && ra) {
+                    // the diagonal group: the rotation zeroes g_pq exactly
+                    o00 = (T)(alp - ta * gap);
+                    o11 = (T)(bep + ta * gap);
+                    o01 = T(0); o10 = T(0);
                 }
-                ca[p] = (T)c; cb[p] = (T)(-s);
-                ca[q] = (T)c; cb[q] = (T)s;
-                tt[tid] = (T)t;
+                gn[p * LD + r[k]] = o00; gn[p * LD + s[k]] = o01;
+                gn[q * LD + r[k]] = o10; gn[q * LD + s[k]] = o11;
             }
             __syncthreads();
-            // G <- J^T G J on the 2x2 groups {p_a, q_a} x {p_b, q_b}, a <= b
-            int gi[TG][2], gj[TG][2];
-            T g[TG][2][2], ci[TG][2], si[TG][2], cj[TG][2], sj[TG][2];
-            bool act[TG], diag[TG];
+            cur ^= 1;
+            // next round: every schedule position advances by one (mod 2b-1),
+            // except the fixed partner 2b-1 of pair 0
+            ax = ax + 1 == M ? 0 : ax + 1;
+            if (a != 0) ay = ay + 1 == M ? 0 : ay + 1;
 #pragma unroll
-            for (int k = 0; k < TG; ++k) {
-                const int e = tid + k * NT, a = e % H, bq = e / H;
-                act[k] = a <= bq;
-                diag[k] = a == bq;
-                rr_slot(B2, rd, a, &gi[k][0], &gi[k][1]);
-                rr_slot(B2, rd, bq, &gj[k][0], &gj[k][1]);
-#pragma unroll
-                for (int x = 0; x < 2; ++x) {
-                    ci[k][x] = ca[gi[k][x]]; si[k][x] = cb[gi[k][x]];
-                    cj[k][x] = ca[gj[k][x]]; sj[k][x] = cb[gj[k][x]];
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) g[k][x][y] = G[gi[k][x] * LD + gj[k][y]];
-                }
+            for (int k = 0; k < GPT; ++k) {
+                cx[k] = cx[k] + 1 == M ? 0 : cx[k] + 1;
+                if (c0 + k != 0) cy[k] = cy[k] + 1 == M ? 0 : cy[k] + 1;
             }
-            // W column pairs
-            int wr[TW], wp[TW], wq[TW];
-            T w0[TW], w1[TW], cp[TW], sp[TW], cq[TW], sq[TW];
-#pragma unroll
-            for (int k = 0; k < TW; ++k) {
-                const int e = tid + k * NT;
-                wr[k] = e % B2;
-                rr_slot(B2, rd, e / B2, &wp[k], &wq[k]);
-                w0[k] = W[wr[k] * LD + wp[k]]; w1[k] = W[wr[k] * LD + wq[k]];
-                cp[k] = ca[wp[k]]; sp[k] = cb[wp[k]]; cq[k] = ca[wq[k]]; sq[k] = cb[wq[k]];
-            }
-            T tdiag[TG];
-#pragma unroll
-            for (int k = 0; k < TG; ++k) tdiag[k] = diag[k] ? tt[(tid + k * NT) % H] : T(0);
-            // each G / W entry is read and written by the same thread within a
-            // round, so no barrier is needed between the loads and the stores
-#pragma unroll
-            for (int k = 0; k < TG; ++k) {
-                if (!act[k]) continue;
-                if (diag[k]) {
-                    const T t = tdiag[k], gpq = g[k][0][1];
-                    if (t != T(0)) {
-                        G[gi[k][0] * LD + gi[k][0]] = g[k][0][0] - t * gpq;
-                        G[gi[k][1] * LD + gi[k][1]] = g[k][1][1] + t * gpq;
-                        G[gi[k][0] * LD + gi[k][1]] = T(0);
-                        G[gi[k][1] * LD + gi[k][0]] = T(0);
-                    }
-                    continue;
-                }
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) {
-                        const T o = ci[k][x] * cj[k][y] * g[k][x][y] + ci[k][x] * sj[k][y] * g[k][x][1 - y] +
-                                    si[k][x] * cj[k][y] * g[k][1 - x][y] + si[k][x] * sj[k][y] * g[k][1 - x][1 - y];
-                        G[gi[k][x] * LD + gj[k][y]] = o;
-                        G[gj[k][y] * LD + gi[k][x]] = o;
-                    }
-            }
-#pragma unroll
-            for (int k = 0; k < TW; ++k) {
-                W[wr[k] * LD + wp[k]] = cp[k] * w0[k] + sp[k] * w1[k];
-                W[wr[k] * LD + wq[k]] = sq[k] * w0[k] + cq[k] * w1[k];
-            }
-            __syncthreads();
         }
-        const int ar = any_rot;
-        if (!ar) break;
+        // positions after a full cycle are back where they started
+        if (!block_or<NT>(rotated, ired)) break;
     }
 
     smax = wave_max(smax);
@@ -297,20 +356,30 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
     }
 }
 
-// [Y_I Y_J] <- [Y_I Y_J] W (and V) on one row chunk: 32-row slabs through
-// LDS, the next slab loaded into registers during the MFMA of the current one.
+// [Y_I Y_J] <- [Y_I Y_J] W (and V) on one row chunk: slabs of SL rows are
+// loaded coalesced (one column segment per group of lanes), multiplied by W on
+// the matrix cores, staged back through LDS and stored coalesced.  The next
+// slab is loaded into registers while the current one is multiplied.
+template <typename T>
+struct UpdSlab { static constexpr int SL = 32; };
+template <>
+struct UpdSlab<float> { static constexpr int SL = 64; };
+
 template <typename T, int B2>
 __global__ __launch_bounds__(JR_NT) void jac_update(int N, int nblk, int r, T *__restrict__ Y,
                                                     int ldy, T *__restrict__ V, int ldv,
                                                     int nchY, const T *__restrict__ Wm,
                                                     const int *__restrict__ skip) {
+    constexpr int SL = UpdSlab<T>::SL;
     constexpr int b = B2 / 2;
-    constexpr int NTJ = B2 / 16;                 // column tiles
-    constexpr int NT = 2 * NTJ;                  // 2 row tiles (32 rows) x NTJ
-    constexpr int TPW = NT / 4;
-    constexpr int PER = B2 * JR_SLAB / JR_NT;
+    constexpr int NTI = SL / 16, NTJ = B2 / 16;  // row and column tiles of a slab
+    constexpr int NTL = NTI * NTJ;
+    constexpr int TPW = NTL / 4;
+    constexpr int PER = B2 * SL / JR_NT;
+    static_assert(TPW * 4 == NTL && PER * JR_NT == B2 * SL, "tiling");
     __shared__ T Ws[B2][B2 + 1];
-    __shared__ T Ps[B2][JR_SLAB + 1];
+    __shared__ T Ps[B2][SL + 1];
+    __shared__ T Os[B2][SL + 1];
     const int pair = blockIdx.x;
     if (skip[pair]) return;
     int I, J;
@@ -323,27 +392,34 @@ __global__ __launch_bounds__(JR_NT) void jac_update(int N, int nblk, int r, T *_
     if ((int)blockIdx.y < nchY) { M = Y; ld = ldy; chunk = blockIdx.y; }
     else { M = V; ld = ldv; chunk = blockIdx.y - nchY; }
     const int rbeg = chunk * JR_RG, rend = min(N, rbeg + JR_RG);
+    // this thread's slab elements: column e / SL, row e % SL
+    size_t coff[PER];
+    int crow[PER];
+#pragma unroll
+    for (int e0 = 0; e0 < PER; ++e0) {
+        const int e = tid + e0 * JR_NT;
+        coff[e0] = (size_t)blk_col(e / SL, b, I, J) * ld;
+        crow[e0] = e % SL;
+    }
     typedef typename acc4<T>::type V4;
     T pf[PER];
     auto fetch = [&](int r0) {
 #pragma unroll
         for (int e0 = 0; e0 < PER; ++e0) {
-            const int e = tid + e0 * JR_NT;
-            const int c = e / JR_SLAB, rr = e % JR_SLAB;
-            const int gi = r0 + rr;
-            pf[e0] = gi < rend ? M[(size_t)blk_col(c, b, I, J) * ld + gi] : T(0);
+            const int gi = r0 + crow[e0];
+            pf[e0] = gi < rend ? M[coff[e0] + gi] : T(0);
         }
     };
     fetch(rbeg);
-    for (int r0 = rbeg; r0 < rend; r0 += JR_SLAB) {
+    for (int r0 = rbeg; r0 < rend; r0 += SL) {
         __syncthreads();
 #pragma unroll
         for (int e0 = 0; e0 < PER; ++e0) {
             const int e = tid + e0 * JR_NT;
-            Ps[e / JR_SLAB][e % JR_SLAB] = pf[e0];
+            Ps[e / SL][e % SL] = pf[e0];
         }
         __syncthreads();
-        if (r0 + JR_SLAB < rend) fetch(r0 + JR_SLAB);
+        if (r0 + SL < rend) fetch(r0 + SL);
         V4 acc[TPW];
 #pragma unroll
         for (int q = 0; q < TPW; ++q) acc[q] = V4{0, 0, 0, 0};
@@ -352,7 +428,7 @@ __global__ __launch_bounds__(JR_NT) void jac_update(int N, int nblk, int r, T *_
 #pragma unroll
             for (int q = 0; q < TPW; ++q) {
                 const int tile = w + 4 * q;
-                const int ti = tile % 2, tj = tile / 2;
+                const int ti = tile % NTI, tj = tile / NTI;
                 const T a = Ps[kk + lane / 16][16 * ti + lane % 16];
                 const T bb = Ws[kk + lane / 16][16 * tj + lane % 16];
                 acc[q] = mfma16(a, bb, acc[q]);
@@ -361,14 +437,17 @@ __global__ __launch_bounds__(JR_NT) void jac_update(int N, int nblk, int r, T *_
 #pragma unroll
         for (int q = 0; q < TPW; ++q) {
             const int tile = w + 4 * q;
-            const int ti = tile % 2, tj = tile / 2;
+            const int ti = tile % NTI, tj = tile / NTI;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int i = 16 * ti + mfma_row<T>(lane, e);
-                const int j = 16 * tj + lane % 16;
-                const int gi = r0 + i;
-                if (gi < rend) M[(size_t)blk_col(j, b, I, J) * ld + gi] = acc[q][e];
-            }
+            for (int e = 0; e < 4; ++e)
+                Os[16 * tj + lane % 16][16 * ti + mfma_row<T>(lane, e)] = acc[q][e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e0 = 0; e0 < PER; ++e0) {
+            const int e = tid + e0 * JR_NT;
+            const int gi = r0 + crow[e0];
+            if (gi < rend) M[coff[e0] + gi] = Os[e / SL][e % SL];
         }
     }
 }
@@ -452,7 +531,7 @@ template <typename T>
 int jacobi_sweeps(hipStream_t s, int N, int b, T *Y, T *V, double eps, int maxsweep, int max_inner,
                   JacobiWork &jw, int *conv) {
     if (b == 16) return sweeps_impl<T, 32, 256>(s, N, Y, V, eps, maxsweep, max_inner, jw, conv);
-    return sweeps_impl<T, 64, 1024>(s, N, Y, V, eps, maxsweep, max_inner, jw, conv);
+    return sweeps_impl<T, 64, 256>(s, N, Y, V, eps, maxsweep, max_inner, jw, conv);
 }
 
 template int jacobi_sweeps<float>(hipStream_t, int, int, float *, float *, double, int, int,

@@ -154,72 +154,40 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_step(int j, int mp, int nb, in
     panel_store(L, P, ld, mp, g, j, nb);
 }
 
-// Partial V^T V over this workgroup's rows; V unit lower trapezoidal.  One
-// wavefront per (a, b) pair, lanes over rows.
-__global__ __launch_bounds__(QR_RC) void qr_vtv_partial(int mp, int nb, const double *P, int ld,
-                                                       double *vtv) {
-    __shared__ double L[QR_NB * LROW];
-    const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
-    {
-        const int i = g * QR_RC + t;
-        double v[QR_NB];
-#pragma unroll
-        for (int k = 0; k < QR_NB; ++k)
-            v[k] = (k < nb && i < mp && i > k) ? P[(size_t)k * ld + i] : 0.0;
-#pragma unroll
-        for (int k = 0; k < QR_NB; ++k) L[k * LROW + t] = (i == k && i < mp && k < nb) ? 1.0 : v[k];
-    }
-    __syncthreads();
-    for (int e = w; e < QR_NB * QR_NB; e += QR_RC / 64) {
-        const int a = e % QR_NB, b = e / QR_NB;
-        double s = 0.0;
-        if (a <= b && b < nb) {
-#pragma unroll
-            for (int q = 0; q < QR_RC / 64; ++q) {
-                const int r = lane + 64 * q;
-                s += L[a * LROW + r] * L[b * LROW + r];
-            }
-            s = wave_sum(s);
-        }
-        if (lane == 0) vtv[(size_t)g * QR_NB * QR_NB + e] = s;
-    }
-}
-
-// T (nb x nb upper, ld QR_NB): T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) V(:, 0:j)^T v_j.
-__global__ __launch_bounds__(256) void qr_build_t(int nb, int ngroups, const double *vtv,
-                                                  const double *tau, double *T) {
+// T (nb x nb upper, ld QR_NB) from G = V^T V (ld QR_NB) and tau:
+// T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j).  One wavefront;
+// lane t keeps row t of T in registers.
+__global__ __launch_bounds__(64) void qr_build_t(int nb, const double *vtv, const double *tau,
+                                                 double *T) {
     __shared__ double G[QR_NB * QR_NB];
-    __shared__ double Ts[QR_NB * QR_NB];
+    __shared__ double ts[QR_NB];
     __shared__ double z[QR_NB];
     const int t = threadIdx.x;
-    // 4 entries per thread, all chunk loads of an entry in flight together
-    for (int e = t; e < QR_NB * QR_NB; e += 256) {
-        double s = 0.0;
-        int q = 0;
-        for (; q + 4 <= ngroups; q += 4) {
-            const double a0 = vtv[(size_t)q * QR_NB * QR_NB + e];
-            const double a1 = vtv[(size_t)(q + 1) * QR_NB * QR_NB + e];
-            const double a2 = vtv[(size_t)(q + 2) * QR_NB * QR_NB + e];
-            const double a3 = vtv[(size_t)(q + 3) * QR_NB * QR_NB + e];
-            s += a0; s += a1; s += a2; s += a3;
-        }
-        for (; q < ngroups; ++q) s += vtv[(size_t)q * QR_NB * QR_NB + e];
-        G[e] = s;
-        Ts[e] = 0.0;
-    }
+#pragma unroll
+    for (int k = 0; k < QR_NB * QR_NB / 64; ++k) G[t + 64 * k] = vtv[t + 64 * k];
+    if (t < QR_NB) ts[t] = t < nb ? tau[t] : 0.0;
     __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        if (t < j) z[t] = -tau[j] * G[j * QR_NB + t];  // G(t, j), t < j
-        __syncthreads();
-        if (t < j) {
-            double s = 0.0;
-            for (int l = t; l < j; ++l) s += Ts[l * QR_NB + t] * z[l];
-            Ts[j * QR_NB + t] = s;
+    double tr[QR_NB];
+#pragma unroll
+    for (int l = 0; l < QR_NB; ++l) tr[l] = 0.0;
+#pragma unroll
+    for (int j = 0; j < QR_NB; ++j) {
+        if (j < nb) {
+            const double tj = ts[j];
+            if (t < j) z[t] = -tj * G[j * QR_NB + t];
+            __syncthreads();
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l < j; ++l)
+                if (l >= t) acc += tr[l] * z[l];
+            tr[j] = t < j ? acc : (t == j ? tj : 0.0);
+            __syncthreads();
         }
-        if (t == j) Ts[j * QR_NB + j] = tau[j];
-        __syncthreads();
     }
-    for (int e = t; e < QR_NB * QR_NB; e += 256) T[e] = Ts[e];
+    if (t < QR_NB) {
+#pragma unroll
+        for (int l = 0; l < QR_NB; ++l) T[l * QR_NB + t] = tr[l];
+    }
 }
 
 // Vb (mp x nb, ld ldv) = explicit unit lower trapezoidal V of the panel.
@@ -255,7 +223,14 @@ void qr_scratch_carve(QRScratch &q, double *base, int m, int ncols_max) {
     q.split_elems = se;
 }
 
-// Factor one panel (mp x nb at P) and build its T; leaves Vb filled.
+static void extract_v(hipStream_t s, int mp, int nb, const double *P, int ld, QRScratch &q) {
+    const size_t tot = (size_t)mp * nb;
+    hipLaunchKernelGGL(qr_extract_v, dim3((unsigned)cdivl((long long)tot, 256)), dim3(256), 0, s,
+                       mp, nb, P, ld, q.vb, mp);
+}
+
+// Factor one panel (mp x nb at P), leave its explicit V in Vb and build its T
+// from V^T V (FP64 matrix-core product).
 static void panel_factor(hipStream_t s, int mp, int nb, double *P, int ld, double *tau,
                          double *T, QRScratch &q) {
     const int G = cdiv(mp, QR_RC);
@@ -263,14 +238,10 @@ static void panel_factor(hipStream_t s, int mp, int nb, double *P, int ld, doubl
     for (int j = 0; j < nb; ++j)
         hipLaunchKernelGGL(qr_panel_step, dim3(G), dim3(QR_RC), 0, s, j, mp, nb, G, P, ld,
                            q.part, q.head, tau);
-    hipLaunchKernelGGL(qr_vtv_partial, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.vtv);
-    hipLaunchKernelGGL(qr_build_t, dim3(1), dim3(256), 0, s, nb, G, q.vtv, tau, T);
-}
-
-static void extract_v(hipStream_t s, int mp, int nb, const double *P, int ld, QRScratch &q) {
-    const size_t tot = (size_t)mp * nb;
-    hipLaunchKernelGGL(qr_extract_v, dim3((unsigned)cdivl((long long)tot, 256)), dim3(256), 0, s,
-                       mp, nb, P, ld, q.vb, mp);
+    extract_v(s, mp, nb, P, ld, q);
+    gemm<double>(s, true, false, nb, nb, mp, 1.0, q.vb, mp, q.vb, mp, 0.0, q.vtv, QR_NB, q.split,
+                 q.split_elems);
+    hipLaunchKernelGGL(qr_build_t, dim3(1), dim3(64), 0, s, nb, q.vtv, tau, T);
 }
 
 // C (mp x ncol) <- (I - V T' V^T) C with T' = T (trans = false) or T^T.
@@ -291,10 +262,7 @@ void qr_factor(hipStream_t s, int m, int n, double *A, int lda, double *tau, dou
         double *T = Tall + (size_t)blk * QR_NB * QR_NB;
         panel_factor(s, mp, nb, P, lda, tau + c0, T, q);
         const int nt = n - c0 - nb;
-        if (nt > 0) {
-            extract_v(s, mp, nb, P, lda, q);
-            apply_block(s, true, mp, nb, T, nt, P + (size_t)nb * lda, lda, q);
-        }
+        if (nt > 0) apply_block(s, true, mp, nb, T, nt, P + (size_t)nb * lda, lda, q);
     }
 }
 
