@@ -83,6 +83,7 @@ struct QRScratch {
     double *w2;     // QR_NB * ncols_max
     double *split;  // split-K scratch
     size_t split_elems;
+    int *flags;     // max_groups step flags of the one-launch panel
 };
 size_t qr_scratch_doubles(int m, int ncols_max, size_t *split_elems);
 void qr_scratch_carve(QRScratch &q, double *base, int m, int ncols_max);

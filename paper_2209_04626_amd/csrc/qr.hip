@@ -13,6 +13,8 @@
 // a value another one is writing.
 // Trailing matrix: compact WY form H_0..H_{nb-1} = I - V T V^T with the LAPACK
 // xLARFT recurrence for T, applied with MFMA GEMMs.
+#include <utility>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -154,6 +156,141 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_step(int j, int mp, int nb, in
     panel_store(L, P, ld, mp, g, j, nb);
 }
 
+// The whole panel in one launch (at most QR_COOP_MAXG workgroups, all
+// resident at once): thread t of workgroup g keeps row g*QR_RC + t of the
+// panel in registers for all nb columns.  For column j every workgroup
+// reduces its rows' products a_ij a_ik (i > j) in LDS, publishes the sums
+// (and workgroup 0 the head row j), then waits until every workgroup has
+// published step j; all workgroups add the sums in the same order, so they
+// build the same reflector, and apply it to their rows.  Publication is a
+// release (fence, then a flag raised to base + j + 1); waiting is a bounded
+// poll of the flags followed by an acquire fence.  A wait that runs out
+// poisons tau[j] with NaN instead of hanging.
+constexpr int QR_COOP_MAXG = 256;
+constexpr int QR_COOP_SPIN = 1 << 22;
+
+struct CoopShared {
+    double red[QR_RC * (QR_NB + 1)];
+    double s8[(QR_RC / QR_NB) * QR_NB];
+    double S[QR_NB], H[QR_NB];
+    int bad;
+};
+
+// Column J of the one-launch panel (J is a compile-time constant so that the
+// row stays in registers).
+template <int J>
+__device__ __forceinline__ void coop_column(double (&a)[QR_NB], CoopShared &sh, int mp, int nb,
+                                            double *part, double *head, double *tau, int *flags,
+                                            int base) {
+    if (J >= nb) return;
+    constexpr int GR = QR_RC / QR_NB;
+    const int G = gridDim.x;
+    const int g = blockIdx.x, t = threadIdx.x, i = g * QR_RC + t;
+    const bool live = i < mp;
+    // 1. this workgroup's sums of a_iJ a_ik over its rows i > J
+    {
+        const double xj = (live && i > J) ? a[J] : 0.0;
+#pragma unroll
+        for (int k = J; k < QR_NB; ++k) sh.red[t * (QR_NB + 1) + k] = xj * a[k];
+    }
+    __syncthreads();
+    {
+        const int k = t % QR_NB, q = t / QR_NB;
+        double sacc = 0.0;
+#pragma unroll
+        for (int r = 0; r < QR_RC / GR; ++r) sacc += sh.red[(q * (QR_RC / GR) + r) * (QR_NB + 1) + k];
+        sh.s8[q * QR_NB + k] = sacc;
+    }
+    __syncthreads();
+    double *po = part + (size_t)(J & 1) * G * QR_NB;
+    double *ho = head + (J & 1) * QR_NB;
+    if (t < QR_NB) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int q = 0; q < GR; ++q) sacc += sh.s8[q * QR_NB + t];
+        po[(size_t)g * QR_NB + t] = sacc;
+    }
+    if (g == 0 && t == J) {
+#pragma unroll
+        for (int k = 0; k < QR_NB; ++k) ho[k] = a[k];
+    }
+    // 2. publish, then wait for every workgroup's column J
+    __threadfence();
+    __syncthreads();
+    if (t == 0) __hip_atomic_store(flags + g, base + J + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (t < G) {
+        int it = 0;
+        while (__hip_atomic_load(flags + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < base + J + 1) {
+            if (++it > QR_COOP_SPIN) { sh.bad = 1; break; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // 3. sums over workgroups in a fixed order, and the head row
+    {
+        const double *pi = part + (size_t)(J & 1) * G * QR_NB;
+        const int k = t % QR_NB, q0 = t / QR_NB;
+        double sacc = 0.0;
+        for (int q = q0; q < G; q += GR) sacc += pi[(size_t)q * QR_NB + k];
+        sh.s8[q0 * QR_NB + k] = sacc;
+        if (t < QR_NB) sh.H[t] = head[(J & 1) * QR_NB + t];
+    }
+    __syncthreads();
+    if (t < QR_NB) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int q = 0; q < GR; ++q) sacc += sh.s8[q * QR_NB + t];
+        sh.S[t] = sacc;
+    }
+    __syncthreads();
+    // 4. the reflector of column J (every thread computes the same one)
+    const double x0 = sh.H[J], s2 = sh.S[J];
+    double beta = x0, tv = 0.0, scale = 0.0;
+    if (s2 != 0.0) {
+        beta = -copysign(sqrt(x0 * x0 + s2), x0);
+        tv = (beta - x0) / beta;
+        scale = 1.0 / (x0 - beta);
+    }
+    if (g == 0 && t == 0) tau[J] = sh.bad ? __builtin_nan("") : tv;
+    // 5. apply it to this thread's row
+    if (live && i >= J) {
+        const double v = i == J ? 1.0 : a[J] * scale;
+#pragma unroll
+        for (int k = J + 1; k < QR_NB; ++k) a[k] -= tv * (sh.H[k] + scale * sh.S[k]) * v;
+        a[J] = i == J ? beta : v;
+    }
+}
+
+template <int... J>
+__device__ __forceinline__ void coop_columns(std::integer_sequence<int, J...>, double (&a)[QR_NB],
+                                             CoopShared &sh, int mp, int nb, double *part,
+                                             double *head, double *tau, int *flags, int base) {
+    (coop_column<J>(a, sh, mp, nb, part, head, tau, flags, base), ...);
+}
+
+__global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P, int ld,
+                                                      double *part, double *head, double *tau,
+                                                      int *flags, int base) {
+    __shared__ CoopShared sh;
+    const int i = blockIdx.x * QR_RC + threadIdx.x;
+    const bool live = i < mp;
+    double a[QR_NB];
+#pragma unroll
+    for (int k = 0; k < QR_NB; ++k) a[k] = (live && k < nb) ? P[(size_t)k * ld + i] : 0.0;
+    if (threadIdx.x == 0) sh.bad = 0;
+    coop_columns(std::make_integer_sequence<int, QR_NB>{}, a, sh, mp, nb, part, head, tau, flags,
+                 base);
+#pragma unroll
+    for (int k = 0; k < QR_NB; ++k)
+        if (live && k < nb) P[(size_t)k * ld + i] = a[k];
+}
+
+__global__ void qr_flags_zero(int n, int *flags) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) flags[e] = 0;
+}
+
 // T (nb x nb upper, ld QR_NB) from G = V^T V (ld QR_NB) and tau:
 // T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j).  One wavefront;
 // lane t keeps row t of T in registers.
@@ -205,7 +342,7 @@ size_t qr_scratch_doubles(int m, int ncols_max, size_t *split_elems) {
     const size_t se = (size_t)8 * QR_NB * (size_t)ncols_max;
     if (split_elems) *split_elems = se;
     return (size_t)2 * G * QR_NB + 2 * QR_NB + (size_t)G * QR_NB * QR_NB + (size_t)m * QR_NB +
-           2 * (size_t)QR_NB * ncols_max + se + 64;
+           2 * (size_t)QR_NB * ncols_max + se + (size_t)(G + 63) / 2 + 128;
 }
 
 void qr_scratch_carve(QRScratch &q, double *base, int m, int ncols_max) {
@@ -219,8 +356,9 @@ void qr_scratch_carve(QRScratch &q, double *base, int m, int ncols_max) {
     q.vb = p; p += (size_t)m * QR_NB;
     q.w1 = p; p += (size_t)QR_NB * ncols_max;
     q.w2 = p; p += (size_t)QR_NB * ncols_max;
-    q.split = p;
+    q.split = p; p += se;
     q.split_elems = se;
+    q.flags = (int *)(p + 32);
 }
 
 static void extract_v(hipStream_t s, int mp, int nb, const double *P, int ld, QRScratch &q) {
@@ -232,12 +370,17 @@ static void extract_v(hipStream_t s, int mp, int nb, const double *P, int ld, QR
 // Factor one panel (mp x nb at P), leave its explicit V in Vb and build its T
 // from V^T V (FP64 matrix-core product).
 static void panel_factor(hipStream_t s, int mp, int nb, double *P, int ld, double *tau,
-                         double *T, QRScratch &q) {
+                         double *T, QRScratch &q, int panel) {
     const int G = cdiv(mp, QR_RC);
-    hipLaunchKernelGGL(qr_panel_init, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.part, q.head);
-    for (int j = 0; j < nb; ++j)
-        hipLaunchKernelGGL(qr_panel_step, dim3(G), dim3(QR_RC), 0, s, j, mp, nb, G, P, ld,
-                           q.part, q.head, tau);
+    if (G <= QR_COOP_MAXG) {
+        hipLaunchKernelGGL(qr_panel_coop, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.part, q.head,
+                           tau, q.flags, panel * 64);
+    } else {
+        hipLaunchKernelGGL(qr_panel_init, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.part, q.head);
+        for (int j = 0; j < nb; ++j)
+            hipLaunchKernelGGL(qr_panel_step, dim3(G), dim3(QR_RC), 0, s, j, mp, nb, G, P, ld,
+                               q.part, q.head, tau);
+    }
     extract_v(s, mp, nb, P, ld, q);
     gemm<double>(s, true, false, nb, nb, mp, 1.0, q.vb, mp, q.vb, mp, 0.0, q.vtv, QR_NB, q.split,
                  q.split_elems);
@@ -255,12 +398,15 @@ static void apply_block(hipStream_t s, bool transT, int mp, int nb, const double
 
 void qr_factor(hipStream_t s, int m, int n, double *A, int lda, double *tau, double *Tall,
                QRScratch &q) {
+    const int gmax = cdiv(m, QR_RC);
+    if (gmax <= QR_COOP_MAXG)
+        hipLaunchKernelGGL(qr_flags_zero, dim3(cdiv(gmax, 256)), dim3(256), 0, s, gmax, q.flags);
     for (int c0 = 0, blk = 0; c0 < n; c0 += QR_NB, ++blk) {
         const int nb = min(QR_NB, n - c0);
         const int mp = m - c0;
         double *P = A + (size_t)c0 * lda + c0;
         double *T = Tall + (size_t)blk * QR_NB * QR_NB;
-        panel_factor(s, mp, nb, P, lda, tau + c0, T, q);
+        panel_factor(s, mp, nb, P, lda, tau + c0, T, q, blk);
         const int nt = n - c0 - nb;
         if (nt > 0) apply_block(s, true, mp, nb, T, nt, P + (size_t)nb * lda, lda, q);
     }
