@@ -240,10 +240,11 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     // kernel_timing 1: the pass is one interval of n back-to-back step launches
     if (o.kernel_timing == 1)
         kclock.begin(s, SVD_K_QRCP, 0.0);
+    int piv_launches;
     if (o.pivot_precision == 32)
-        qrcp_pivots<float>(s, n, A1, n, (float *)D(L.off_wp), w + L.off_nrm2, piv, jw.kc);
+        piv_launches = qrcp_pivots<float>(s, n, A1, n, (float *)D(L.off_wp), w + L.off_nrm2, piv, jw.kc);
     else
-        qrcp_pivots<double>(s, n, A1, n, D(L.off_wp), w + L.off_nrm2, piv, jw.kc);
+        piv_launches = qrcp_pivots<double>(s, n, A1, n, D(L.off_wp), w + L.off_nrm2, piv, jw.kc);
     if (o.kernel_timing == 1) {
         kclock.end(s);
         // launches and algorithmic bytes of the whole pass (see qrcp_pivots)
@@ -254,7 +255,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
             bytes += (2.0 * mm * (mm - 1) + mm) * es;
         }
         kclock.bytes[0] = bytes;
-        kclock.pass_calls = n;
+        kclock.pass_calls = piv_launches;
     }
     tm.mark(1);
     // a3: FP64 QR of A1 P

@@ -66,6 +66,21 @@ __device__ __forceinline__ int block_or(int v, int *red) {
     return s;
 }
 
+// Loads and stores that are coherent across the chip's L2 caches (relaxed
+// atomics at device scope).  Workgroups of one launch exchange data through
+// them: the writer stores, waits for its stores to complete (a
+// workgroup-scope release fence), then raises a flag with coh_store; the
+// reader polls the flag with coh_load and reads the data with coh_load.  No
+// cache-wide write-back or invalidate is involved.
+template <typename U>
+__device__ __forceinline__ void coh_store(U *p, U v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename U>
+__device__ __forceinline__ U coh_load(const U *p) {
+    return __hip_atomic_load(const_cast<U *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // 16x16x4 MFMA, FP64 and FP32.  Operand layout for lane l of the wavefront:
 //   A (16 x 4):  A[l % 16][l / 16]
 //   B (4 x 16):  B[l / 16][l % 16]

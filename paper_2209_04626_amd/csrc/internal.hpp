@@ -102,10 +102,11 @@ void qr_apply_left(hipStream_t s, bool trans, int m, int k, const double *Qf,
 // ---------------------------------------------------------------- QRCP
 // Businger-Golub pivot selection on a working copy of the n x n matrix A1:
 // piv[k] = column chosen at step k.  W holds n*n elements of T; scratch holds
-// qrcp_scratch_bytes(n, sizeof(T)) bytes.
+// qrcp_scratch_bytes(n, sizeof(T)) bytes.  Returns the number of launches
+// the pass took (1 for the one-launch FP32 pass, else n).
 size_t qrcp_scratch_bytes(int n, int elem);
 template <typename T>
-void qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W,
+int qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W,
                  void *scratch, int *piv, KernelClock *kc = nullptr);
 
 // ---------------------------------------------------------------- Jacobi

@@ -162,10 +162,10 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_step(int j, int mp, int nb, in
 // reduces its rows' products a_ij a_ik (i > j) in LDS, publishes the sums
 // (and workgroup 0 the head row j), then waits until every workgroup has
 // published step j; all workgroups add the sums in the same order, so they
-// build the same reflector, and apply it to their rows.  Publication is a
-// release (fence, then a flag raised to base + j + 1); waiting is a bounded
-// poll of the flags followed by an acquire fence.  A wait that runs out
-// poisons tau[j] with NaN instead of hanging.
+// build the same reflector, and apply it to their rows.  The sums, the head
+// row and the flags (raised to base + j + 1) go through device-coherent
+// stores and loads; waiting is a bounded poll.  A wait that runs out poisons
+// tau[j] with NaN instead of hanging.
 constexpr int QR_COOP_MAXG = 256;
 constexpr int QR_COOP_SPIN = 1 << 22;
 
@@ -208,33 +208,33 @@ __device__ __forceinline__ void coop_column(double (&a)[QR_NB], CoopShared &sh, 
         double sacc = 0.0;
 #pragma unroll
         for (int q = 0; q < GR; ++q) sacc += sh.s8[q * QR_NB + t];
-        po[(size_t)g * QR_NB + t] = sacc;
+        coh_store(po + (size_t)g * QR_NB + t, sacc);
     }
     if (g == 0 && t == J) {
 #pragma unroll
-        for (int k = 0; k < QR_NB; ++k) ho[k] = a[k];
+        for (int k = 0; k < QR_NB; ++k) coh_store(ho + k, a[k]);
     }
-    // 2. publish, then wait for every workgroup's column J
-    __threadfence();
+    // 2. publish (stores complete, then the flag), then wait for every
+    // workgroup's column J
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
-    if (t == 0) __hip_atomic_store(flags + g, base + J + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (t == 0) coh_store(flags + g, base + J + 1);
     if (t < G) {
         int it = 0;
-        while (__hip_atomic_load(flags + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < base + J + 1) {
+        while (coh_load(flags + t) < base + J + 1) {
             if (++it > QR_COOP_SPIN) { sh.bad = 1; break; }
             __builtin_amdgcn_s_sleep(1);
         }
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     // 3. sums over workgroups in a fixed order, and the head row
     {
         const double *pi = part + (size_t)(J & 1) * G * QR_NB;
         const int k = t % QR_NB, q0 = t / QR_NB;
         double sacc = 0.0;
-        for (int q = q0; q < G; q += GR) sacc += pi[(size_t)q * QR_NB + k];
+        for (int q = q0; q < G; q += GR) sacc += coh_load(pi + (size_t)q * QR_NB + k);
         sh.s8[q0 * QR_NB + k] = sacc;
-        if (t < QR_NB) sh.H[t] = head[(J & 1) * QR_NB + t];
+        if (t < QR_NB) sh.H[t] = coh_load(head + (J & 1) * QR_NB + t);
     }
     __syncthreads();
     if (t < QR_NB) {

@@ -303,18 +303,254 @@ __global__ __launch_bounds__(Q2_NT) void qrcp_step2(int k, int n, T *__restrict_
     }
 }
 
+// Whole pass in one launch (FP32, n <= 4096): the working matrix never
+// leaves registers.  Wavefront w of workgroup b owns column 16 b + w for the
+// whole pass (rows lane + 64 r in x[r]); used columns drop out.  Step k:
+//   1. each workgroup takes its best live column (largest trailing norm, ties
+//      to the smallest index) as its candidate and publishes the candidate
+//      and that column's rows k..n-1 (double-buffered by step parity) with
+//      device-coherent stores, waits for them to complete, then raises its
+//      flag to k + 1;
+//   2. it polls, with a bound, until every flag reads k + 1, and reads the
+//      candidates and the pivot column with device-coherent loads;
+//   3. every workgroup picks the same pivot from the candidates, stages its
+//      published rows in LDS and applies the reflector to its live columns,
+//      recomputing their trailing norms (rows k+1..n-1).
+// A wait that runs out sets *err and the host redoes the pass step by step.
+// Requires all workgroups resident at once: one per compute unit, launched
+// only when the device has a unit for each.
+constexpr int QP_NT = 1024;
+constexpr int QP_W = QP_NT / 64;
+constexpr int QP_SPIN = 1 << 22;
+
+template <typename T, int RPL>
+__global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__restrict__ A1,
+                                                     int lda, T *__restrict__ cbuf,
+                                                     Cand<T> *__restrict__ cand,
+                                                     int *__restrict__ flags, int *err,
+                                                     int *__restrict__ piv) {
+    constexpr int NP = 64 * RPL;          // padded column length (rows >= n stay zero)
+    __shared__ T pc[NP];
+    __shared__ T rv[QP_W];
+    __shared__ int rc[QP_W], rb[QP_W];
+    __shared__ int bad;
+    const int nwg = gridDim.x;
+    const int b = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int j = b * QP_W + w;
+    bool live = j < n;
+    T x[RPL];
+    T nv;
+    {
+        T ns = 0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = lane + 64 * r;
+            x[r] = (live && i < n) ? (T)A1[(size_t)j * lda + i] : T(0);
+            ns += x[r] * x[r];
+        }
+        nv = live ? tsqrt(wave_sum(ns)) : T(-1);
+    }
+    for (int i = t; i < NP; i += QP_NT) pc[i] = T(0);
+    if (t == 0) bad = 0;
+    for (int k = 0; k < n; ++k) {
+        const int buf = k & 1;
+        const int r0 = k >> 6, kl = k & 63;
+        // 1. this workgroup's candidate and its rows k..NP-1
+        if (lane == 0) { rv[w] = nv; rc[w] = live ? j : INT_MAX; }
+        __syncthreads();
+        // every wavefront reduces the QP_W entries across its first lanes
+        T bv = lane < QP_W ? rv[lane] : T(-2);
+        int bc = lane < QP_W ? rc[lane] : INT_MAX, bw = lane;
+#pragma unroll
+        for (int o = QP_W / 2; o > 0; o >>= 1) {
+            const T ov = __shfl_xor(bv, o, 64);
+            const int oc = __shfl_xor(bc, o, 64), ow = __shfl_xor(bw, o, 64);
+            if (cand_better(ov, oc, bv, bc)) { bv = ov; bc = oc; bw = ow; }
+        }
+        bv = __shfl(bv, 0, 64); bc = __shfl(bc, 0, 64); bw = __shfl(bw, 0, 64);
+        // the winning wavefront stages its column in LDS (pc is free here),
+        // then the whole workgroup copies rows k..n-1 out
+        if (w == bw && bv >= T(0)) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) pc[lane + 64 * r] = x[r];
+        }
+        if (t == 0) {
+            Cand<T> *cs = cand + (size_t)buf * nwg + b;
+            coh_store(&cs->v, bv);
+            coh_store(&cs->pos, b);
+            coh_store(&cs->col, bc);
+        }
+        __syncthreads();
+        if (bv >= T(0)) {
+            T *cb = cbuf + ((size_t)buf * nwg + b) * NP;
+            for (int i = k + t; i < n; i += QP_NT) coh_store(cb + i, pc[i]);
+        }
+        // every wavefront's stores are complete before the flag goes up
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        if (t == 0) coh_store(flags + b, k + 1);
+        // 2. wait for every workgroup's step k
+        if (t < nwg) {
+            int it = 0;
+            while (coh_load(flags + t) < k + 1) {
+                if (++it > QP_SPIN) { bad = 1; break; }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __syncthreads();
+        // 3. the pivot
+        T gv = T(-2);
+        int gc = INT_MAX, gb = 0;
+        if (t < nwg) {
+            const Cand<T> *cs = cand + (size_t)buf * nwg + t;
+            gv = coh_load(&cs->v); gb = coh_load(&cs->pos); gc = coh_load(&cs->col);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const T ov = __shfl_xor(gv, o, 64);
+            const int ob = __shfl_xor(gb, o, 64);
+            const int oc = __shfl_xor(gc, o, 64);
+            if (cand_better(ov, oc, gv, gc)) { gv = ov; gb = ob; gc = oc; }
+        }
+        if (lane == 0) { rv[w] = gv; rc[w] = gc; rb[w] = gb; }
+        __syncthreads();
+        gv = lane < QP_W ? rv[lane] : T(-2);
+        gc = lane < QP_W ? rc[lane] : INT_MAX;
+        gb = lane < QP_W ? rb[lane] : 0;
+#pragma unroll
+        for (int o = QP_W / 2; o > 0; o >>= 1) {
+            const T ov = __shfl_xor(gv, o, 64);
+            const int oc = __shfl_xor(gc, o, 64), ob = __shfl_xor(gb, o, 64);
+            if (cand_better(ov, oc, gv, gc)) { gv = ov; gc = oc; gb = ob; }
+        }
+        gv = __shfl(gv, 0, 64); gc = __shfl(gc, 0, 64); gb = __shfl(gb, 0, 64);
+        const int p = min(max(gc, 0), n - 1);
+        gb = min(max(gb, 0), nwg - 1);
+        const T pnorm = gv;
+        {
+            const T *src = cbuf + ((size_t)buf * nwg + gb) * NP;
+            for (int i = k + t; i < n; i += QP_NT) pc[i] = coh_load(src + i);
+        }
+        if (b == 0 && t == 0) {
+            piv[k] = p;
+            if (bad) *err = 1;
+        }
+        __syncthreads();
+        // 4. reflector H = I - tau v v^T, v = [1; x(k+1:)/(x_k - beta)], and update
+        T tau = 0, scale = 0;
+        {
+            const T x0 = pc[k];
+            if (pnorm > T(0)) {
+                const T beta = -copysign(pnorm, x0);
+                tau = (beta - x0) / beta;
+                scale = T(1) / (x0 - beta);
+            }
+        }
+        if (live && j == p) {
+            live = false;
+            nv = T(-1);
+        } else if (live) {
+            // (groups of 8 registers: the empty asm statements keep the
+            // compiler from holding RPL staged pivot entries live at once)
+            T d = 0, xk = 0;
+#pragma unroll
+            for (int rg = 0; rg < RPL; rg += 8) {
+#pragma unroll
+                for (int r = rg; r < rg + 8; ++r) {
+                    if (r > r0) {
+                        d += pc[lane + 64 * r] * x[r];
+                    } else if (r == r0) {
+                        xk = x[r];
+                        if (lane > kl) d += pc[lane + 64 * r] * x[r];
+                    }
+                }
+                __asm__ volatile("" ::: "memory");
+            }
+            d = wave_sum(d);
+            xk = __shfl(xk, kl, 64);
+            const T f = tau * (xk + scale * d) * scale;
+            T ns = 0;
+#pragma unroll
+            for (int rg = 0; rg < RPL; rg += 8) {
+#pragma unroll
+                for (int r = rg; r < rg + 8; ++r) {
+                    if (r > r0 || (r == r0 && lane > kl)) {
+                        x[r] -= f * pc[lane + 64 * r];
+                        ns += x[r] * x[r];
+                    }
+                }
+                __asm__ volatile("" ::: "memory");
+            }
+            nv = tsqrt(wave_sum(ns));
+        }
+    }
+}
+
+__global__ void qrcp_persist_reset(int nwg, int *flags, int *err) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nwg) flags[e] = 0;
+    if (e == 0) *err = 0;
+}
+
 size_t qrcp_scratch_bytes(int n, int elem) {
     // fallback: two norm vectors; compacted step: perm + two candidate arrays
     const size_t a = (size_t)2 * n * elem;
     const size_t ncand = (size_t)cdiv(n, Q2_W) + 1;
     const size_t b = (size_t)n * sizeof(int) + 64 + 2 * ncand * sizeof(Cand<double>);
-    return a > b ? a : b;
+    const size_t nwg = (size_t)cdiv(n, QP_W);
+    const size_t c = 2 * nwg * sizeof(Cand<double>) + nwg * sizeof(int) + 256;
+    size_t m = a > b ? a : b;
+    return m > c ? m : c;
+}
+
+// The one-launch FP32 pass; false when it does not apply or could not run
+// (then nothing observable has changed and the caller takes the step path).
+static bool qrcp_persist_pass(hipStream_t s, int n, const double *A1, int lda, float *W,
+                              void *scratch, int *piv) {
+    if (n < 128 || n > 64 * 64) return false;
+    const int nwg = cdiv(n, QP_W);
+    Cand<float> *cand = (Cand<float> *)scratch;
+    int *flags = (int *)((char *)scratch + 2 * (size_t)nwg * sizeof(Cand<double>));
+    int *err = flags + nwg;
+    float *cbuf = W;   // 2 * nwg * 64 RPL floats <= n * n doubles (the working copy is not needed)
+    const void *fn;
+    if (n <= 64 * 16) fn = (const void *)qrcp_persist<float, 16>;
+    else if (n <= 64 * 32) fn = (const void *)qrcp_persist<float, 32>;
+    else fn = (const void *)qrcp_persist<float, 64>;
+    // every workgroup must be resident at once: at most one per compute unit
+    // here, and only if the kernel fits one per unit
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, QP_NT, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (per_cu < 1 || nwg > ncu) return false;
+    hipLaunchKernelGGL(qrcp_persist_reset, dim3(cdiv(nwg, 256)), dim3(256), 0, s, nwg, flags, err);
+    if (n <= 64 * 16)
+        hipLaunchKernelGGL((qrcp_persist<float, 16>), dim3(nwg), dim3(QP_NT), 0, s, n, A1, lda, cbuf,
+                           cand, flags, err, piv);
+    else if (n <= 64 * 32)
+        hipLaunchKernelGGL((qrcp_persist<float, 32>), dim3(nwg), dim3(QP_NT), 0, s, n, A1, lda, cbuf,
+                           cand, flags, err, piv);
+    else
+        hipLaunchKernelGGL((qrcp_persist<float, 64>), dim3(nwg), dim3(QP_NT), 0, s, n, A1, lda, cbuf,
+                           cand, flags, err, piv);
+    if (hipGetLastError() != hipSuccess) return false;
+    int h_err = 1;
+    if (hipMemcpyAsync(&h_err, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return h_err == 0;
 }
 
 template <typename T>
-void qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, void *scratch, int *piv,
-                 KernelClock *kc) {
-    if (n <= 0) return;
+int qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, void *scratch, int *piv,
+                KernelClock *kc) {
+    if (n <= 0) return 0;
     if (n > 64 * 64) {
         T *norms2 = (T *)scratch;
         hipLaunchKernelGGL((qrcp_init<T>), dim3(cdiv(n, CP_NT / 64)), dim3(CP_NT), 0, s, n, A1, lda,
@@ -328,8 +564,10 @@ void qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, void *sc
                                nout, piv);
             if (kc) kc->end(s);
         }
-        return;
+        return n;
     }
+    if (sizeof(T) == 4 && !kc && qrcp_persist_pass(s, n, A1, lda, (float *)W, scratch, piv))
+        return 1;
     int *perm = (int *)scratch;
     const size_t ncand = (size_t)cdiv(n, Q2_W) + 1;
     Cand<T> *cand = (Cand<T> *)((char *)scratch + (((size_t)n * sizeof(int) + 63) / 64) * 64);
@@ -356,11 +594,12 @@ void qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, void *sc
                                ncin, cout, piv);
         if (kc) kc->end(s);
     }
+    return n;
 }
 
-template void qrcp_pivots<float>(hipStream_t, int, const double *, int, float *, void *, int *,
+template int qrcp_pivots<float>(hipStream_t, int, const double *, int, float *, void *, int *,
+                                KernelClock *);
+template int qrcp_pivots<double>(hipStream_t, int, const double *, int, double *, void *, int *,
                                  KernelClock *);
-template void qrcp_pivots<double>(hipStream_t, int, const double *, int, double *, void *, int *,
-                                  KernelClock *);
 
 } // namespace mpj
