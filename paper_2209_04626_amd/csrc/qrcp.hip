@@ -307,32 +307,38 @@ __global__ __launch_bounds__(Q2_NT) void qrcp_step2(int k, int n, T *__restrict_
 // leaves registers.  Wavefront w of workgroup b owns column 16 b + w for the
 // whole pass (rows lane + 64 r in x[r]); used columns drop out.  Step k:
 //   1. each workgroup takes its best live column (largest trailing norm, ties
-//      to the smallest index) as its candidate and publishes the candidate
-//      and that column's rows k..n-1 (double-buffered by step parity) with
-//      device-coherent stores, waits for them to complete, then raises its
-//      flag to k + 1;
-//   2. it polls, with a bound, until every flag reads k + 1, and reads the
-//      candidates and the pivot column with device-coherent loads;
-//   3. every workgroup picks the same pivot from the candidates, stages its
-//      published rows in LDS and applies the reflector to its live columns,
-//      recomputing their trailing norms (rows k+1..n-1).
+//      to the smallest index) as its candidate, publishes that column's rows
+//      k..n-1 (double-buffered by step parity) with device-coherent stores,
+//      waits for them to complete, then publishes its candidate as one
+//      64-bit key: step k + 1 | norm bits | 8191 - column (0 for none), so
+//      that the largest key of a step is the pivot with the tie rule;
+//   2. it polls, with a bound, until every key of the step is in, takes the
+//      largest, and reads the pivot column from its owner's slot;
+//   3. it applies the reflector to its live columns and recomputes their
+//      trailing norms (rows k+1..n-1).
 // A wait that runs out sets *err and the host redoes the pass step by step.
 // Requires all workgroups resident at once: one per compute unit, launched
 // only when the device has a unit for each.
 constexpr int QP_NT = 1024;
 constexpr int QP_W = QP_NT / 64;
 constexpr int QP_SPIN = 1 << 22;
+constexpr int QP_TAG = 45;            // key bits [45, 64): step tag
 
-template <typename T, int RPL>
+__device__ __forceinline__ unsigned long long qp_key(int step, float v, int col) {
+    if (!(v >= 0.f)) return (unsigned long long)step << QP_TAG;
+    return ((unsigned long long)step << QP_TAG) |
+           ((unsigned long long)__float_as_uint(v) << 13) | (unsigned long long)(8191 - col);
+}
+
+template <int RPL>
 __global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__restrict__ A1,
-                                                     int lda, T *__restrict__ cbuf,
-                                                     Cand<T> *__restrict__ cand,
-                                                     int *__restrict__ flags, int *err,
-                                                     int *__restrict__ piv) {
+                                                     int lda, float *__restrict__ cbuf,
+                                                     unsigned long long *__restrict__ keys,
+                                                     int *err, int *__restrict__ piv) {
+    typedef float T;
     constexpr int NP = 64 * RPL;          // padded column length (rows >= n stay zero)
     __shared__ T pc[NP];
-    __shared__ T rv[QP_W];
-    __shared__ int rc[QP_W], rb[QP_W];
+    __shared__ unsigned long long rk[QP_W];
     __shared__ int bad;
     const int nwg = gridDim.x;
     const int b = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -355,80 +361,61 @@ __global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__res
     for (int k = 0; k < n; ++k) {
         const int buf = k & 1;
         const int r0 = k >> 6, kl = k & 63;
-        // 1. this workgroup's candidate and its rows k..NP-1
-        if (lane == 0) { rv[w] = nv; rc[w] = live ? j : INT_MAX; }
+        // 1. this workgroup's candidate, its rows k..n-1, then its key
+        if (lane == 0) rk[w] = live ? qp_key(k + 1, nv, j) : qp_key(k + 1, -1.f, 0);
         __syncthreads();
-        // every wavefront reduces the QP_W entries across its first lanes
-        T bv = lane < QP_W ? rv[lane] : T(-2);
-        int bc = lane < QP_W ? rc[lane] : INT_MAX, bw = lane;
+        unsigned long long bk = lane < QP_W ? rk[lane] : 0ull;
+        int bw = lane;
 #pragma unroll
         for (int o = QP_W / 2; o > 0; o >>= 1) {
-            const T ov = __shfl_xor(bv, o, 64);
-            const int oc = __shfl_xor(bc, o, 64), ow = __shfl_xor(bw, o, 64);
-            if (cand_better(ov, oc, bv, bc)) { bv = ov; bc = oc; bw = ow; }
+            const unsigned long long ok = __shfl_xor(bk, o, 64);
+            const int ow = __shfl_xor(bw, o, 64);
+            if (ok > bk) { bk = ok; bw = ow; }
         }
-        bv = __shfl(bv, 0, 64); bc = __shfl(bc, 0, 64); bw = __shfl(bw, 0, 64);
-        // the winning wavefront stages its column in LDS (pc is free here),
-        // then the whole workgroup copies rows k..n-1 out
-        if (w == bw && bv >= T(0)) {
+        bk = __shfl(bk, 0, 64); bw = __shfl(bw, 0, 64);
+        const bool any = (bk & ((1ull << QP_TAG) - 1)) != 0;
+        if (w == bw && any) {
 #pragma unroll
             for (int r = 0; r < RPL; ++r) pc[lane + 64 * r] = x[r];
         }
-        if (t == 0) {
-            Cand<T> *cs = cand + (size_t)buf * nwg + b;
-            coh_store(&cs->v, bv);
-            coh_store(&cs->pos, b);
-            coh_store(&cs->col, bc);
-        }
         __syncthreads();
-        if (bv >= T(0)) {
+        if (any) {
             T *cb = cbuf + ((size_t)buf * nwg + b) * NP;
             for (int i = k + t; i < n; i += QP_NT) coh_store(cb + i, pc[i]);
         }
-        // every wavefront's stores are complete before the flag goes up
+        // every wavefront's stores are complete before the key goes out
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
-        if (t == 0) coh_store(flags + b, k + 1);
-        // 2. wait for every workgroup's step k
+        if (t == 0) coh_store(keys + (size_t)buf * nwg + b, bk);
+        // 2. every workgroup's key of step k; the largest is the pivot
+        unsigned long long gk = 0ull;
         if (t < nwg) {
             int it = 0;
-            while (coh_load(flags + t) < k + 1) {
-                if (++it > QP_SPIN) { bad = 1; break; }
+            for (;;) {
+                gk = coh_load(keys + (size_t)buf * nwg + t);
+                if ((int)(gk >> QP_TAG) == k + 1) break;
+                if (++it > QP_SPIN) { bad = 1; gk = 0ull; break; }
                 __builtin_amdgcn_s_sleep(1);
             }
         }
-        __syncthreads();
-        // 3. the pivot
-        T gv = T(-2);
-        int gc = INT_MAX, gb = 0;
-        if (t < nwg) {
-            const Cand<T> *cs = cand + (size_t)buf * nwg + t;
-            gv = coh_load(&cs->v); gb = coh_load(&cs->pos); gc = coh_load(&cs->col);
-        }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
-            const T ov = __shfl_xor(gv, o, 64);
-            const int ob = __shfl_xor(gb, o, 64);
-            const int oc = __shfl_xor(gc, o, 64);
-            if (cand_better(ov, oc, gv, gc)) { gv = ov; gb = ob; gc = oc; }
+            const unsigned long long ok = __shfl_xor(gk, o, 64);
+            if (ok > gk) gk = ok;
         }
-        if (lane == 0) { rv[w] = gv; rc[w] = gc; rb[w] = gb; }
+        if (lane == 0) rk[w] = gk;   // rk was last read before the previous barrier
         __syncthreads();
-        gv = lane < QP_W ? rv[lane] : T(-2);
-        gc = lane < QP_W ? rc[lane] : INT_MAX;
-        gb = lane < QP_W ? rb[lane] : 0;
+        gk = lane < QP_W ? rk[lane] : 0ull;
 #pragma unroll
         for (int o = QP_W / 2; o > 0; o >>= 1) {
-            const T ov = __shfl_xor(gv, o, 64);
-            const int oc = __shfl_xor(gc, o, 64), ob = __shfl_xor(gb, o, 64);
-            if (cand_better(ov, oc, gv, gc)) { gv = ov; gc = oc; gb = ob; }
+            const unsigned long long ok = __shfl_xor(gk, o, 64);
+            if (ok > gk) gk = ok;
         }
-        gv = __shfl(gv, 0, 64); gc = __shfl(gc, 0, 64); gb = __shfl(gb, 0, 64);
-        const int p = min(max(gc, 0), n - 1);
-        gb = min(max(gb, 0), nwg - 1);
-        const T pnorm = gv;
+        gk = __shfl(gk, 0, 64);
+        const int p = min(max(8191 - (int)(gk & 8191ull), 0), n - 1);
+        const T pnorm = __uint_as_float((unsigned)((gk >> 13) & 0xffffffffull));
         {
-            const T *src = cbuf + ((size_t)buf * nwg + gb) * NP;
+            const T *src = cbuf + ((size_t)buf * nwg + p / QP_W) * NP;
             for (int i = k + t; i < n; i += QP_NT) pc[i] = coh_load(src + i);
         }
         if (b == 0 && t == 0) {
@@ -436,7 +423,7 @@ __global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__res
             if (bad) *err = 1;
         }
         __syncthreads();
-        // 4. reflector H = I - tau v v^T, v = [1; x(k+1:)/(x_k - beta)], and update
+        // 3. reflector H = I - tau v v^T, v = [1; x(k+1:)/(x_k - beta)], and update
         T tau = 0, scale = 0;
         {
             const T x0 = pc[k];
@@ -486,9 +473,9 @@ __global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__res
     }
 }
 
-__global__ void qrcp_persist_reset(int nwg, int *flags, int *err) {
+__global__ void qrcp_persist_reset(int nkeys, unsigned long long *keys, int *err) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < nwg) flags[e] = 0;
+    if (e < nkeys) keys[e] = 0ull;
     if (e == 0) *err = 0;
 }
 
@@ -498,7 +485,7 @@ size_t qrcp_scratch_bytes(int n, int elem) {
     const size_t ncand = (size_t)cdiv(n, Q2_W) + 1;
     const size_t b = (size_t)n * sizeof(int) + 64 + 2 * ncand * sizeof(Cand<double>);
     const size_t nwg = (size_t)cdiv(n, QP_W);
-    const size_t c = 2 * nwg * sizeof(Cand<double>) + nwg * sizeof(int) + 256;
+    const size_t c = 2 * nwg * sizeof(unsigned long long) + 256;
     size_t m = a > b ? a : b;
     return m > c ? m : c;
 }
@@ -509,14 +496,13 @@ static bool qrcp_persist_pass(hipStream_t s, int n, const double *A1, int lda, f
                               void *scratch, int *piv) {
     if (n < 128 || n > 64 * 64) return false;
     const int nwg = cdiv(n, QP_W);
-    Cand<float> *cand = (Cand<float> *)scratch;
-    int *flags = (int *)((char *)scratch + 2 * (size_t)nwg * sizeof(Cand<double>));
-    int *err = flags + nwg;
+    unsigned long long *keys = (unsigned long long *)scratch;
+    int *err = (int *)(keys + 2 * (size_t)nwg);
     float *cbuf = W;   // 2 * nwg * 64 RPL floats <= n * n doubles (the working copy is not needed)
     const void *fn;
-    if (n <= 64 * 16) fn = (const void *)qrcp_persist<float, 16>;
-    else if (n <= 64 * 32) fn = (const void *)qrcp_persist<float, 32>;
-    else fn = (const void *)qrcp_persist<float, 64>;
+    if (n <= 64 * 16) fn = (const void *)qrcp_persist<16>;
+    else if (n <= 64 * 32) fn = (const void *)qrcp_persist<32>;
+    else fn = (const void *)qrcp_persist<64>;
     // every workgroup must be resident at once: at most one per compute unit
     // here, and only if the kernel fits one per unit
     int dev = 0, ncu = 0, per_cu = 0;
@@ -527,16 +513,17 @@ static bool qrcp_persist_pass(hipStream_t s, int n, const double *A1, int lda, f
         return false;
     }
     if (per_cu < 1 || nwg > ncu) return false;
-    hipLaunchKernelGGL(qrcp_persist_reset, dim3(cdiv(nwg, 256)), dim3(256), 0, s, nwg, flags, err);
+    hipLaunchKernelGGL(qrcp_persist_reset, dim3(cdiv(2 * nwg, 256)), dim3(256), 0, s, 2 * nwg, keys,
+                       err);
     if (n <= 64 * 16)
-        hipLaunchKernelGGL((qrcp_persist<float, 16>), dim3(nwg), dim3(QP_NT), 0, s, n, A1, lda, cbuf,
-                           cand, flags, err, piv);
+        hipLaunchKernelGGL((qrcp_persist<16>), dim3(nwg), dim3(QP_NT), 0, s, n, A1, lda, cbuf, keys,
+                           err, piv);
     else if (n <= 64 * 32)
-        hipLaunchKernelGGL((qrcp_persist<float, 32>), dim3(nwg), dim3(QP_NT), 0, s, n, A1, lda, cbuf,
-                           cand, flags, err, piv);
+        hipLaunchKernelGGL((qrcp_persist<32>), dim3(nwg), dim3(QP_NT), 0, s, n, A1, lda, cbuf, keys,
+                           err, piv);
     else
-        hipLaunchKernelGGL((qrcp_persist<float, 64>), dim3(nwg), dim3(QP_NT), 0, s, n, A1, lda, cbuf,
-                           cand, flags, err, piv);
+        hipLaunchKernelGGL((qrcp_persist<64>), dim3(nwg), dim3(QP_NT), 0, s, n, A1, lda, cbuf, keys,
+                           err, piv);
     if (hipGetLastError() != hipSuccess) return false;
     int h_err = 1;
     if (hipMemcpyAsync(&h_err, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
