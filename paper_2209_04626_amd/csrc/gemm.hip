@@ -4,53 +4,62 @@
 // U = Q0 Q1 U_X, V = P Q2^T V_X, and the FP32 orthogonality test
 // max|X_t^T X_t - I| of Section 3.5.
 //
-// Tiling: 64 x 64 output tile per 256-thread workgroup, 4 wavefronts in a
-// 2 x 2 arrangement, each owning 32 x 32 = 2 x 2 MFMA tiles; K staged through
-// LDS in slices of 16.  Split-K writes partial products to scratch and a
-// second kernel sums them in a fixed order (deterministic).
+// Tiling: 64 x 64 (or 32 x 64) output tile per 256-thread workgroup, K
+// staged through LDS in slices of 32 with the next slice prefetched into
+// registers.  Split-K writes partial products to scratch and a second kernel
+// sums them in a fixed order (deterministic).
 #include "common.hpp"
 #include "internal.hpp"
 
 namespace mpj {
 
-constexpr int GBM = 64, GBN = 64, GBK = 16;
+constexpr int GBN = 64, GBK = 32;
 
 enum { EPI_STORE = 0, EPI_PART = 1, EPI_MAXDEV = 2 };
 
-template <typename T, bool TA, bool TB, int EPI>
+// BM x 64 output tile per 256-thread workgroup (BM = 64: 2 x 2 wavefronts of
+// 32 x 32; BM = 32, for the 32-row products of the blocked Householder
+// updates: 1 x 4 wavefronts of 32 x 16).  K advances in slices of 32: the
+// next slice is loaded into registers while the matrix cores work on the
+// current one from LDS.
+template <typename T, bool TA, bool TB, int EPI, int BM>
 __global__ __launch_bounds__(256) void gemm_kernel(
     int M, int N, int K, T alpha, const T *__restrict__ A, int lda,
     const T *__restrict__ B, int ldb, T beta, T *C, int ldc, int kchunk,
     T *part, float *maxdev) {
-    __shared__ T As[GBK][GBM + 1];
+    constexpr int WN = BM == 64 ? 2 : 4;           // wavefronts along N
+    constexpr int TI = 2, TJ = BM == 64 ? 2 : 1;   // MFMA tiles per wavefront
+    constexpr int PA = BM * GBK / 256, PB = GBK * GBN / 256;
+    __shared__ T As[GBK][BM + 1];
     __shared__ T Bs[GBK][GBN + 1];
     __shared__ float red[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w & 1, wn = w >> 1;
-    const int i0 = blockIdx.x * GBM, j0 = blockIdx.y * GBN;
+    const int wm = w / WN, wn = w % WN;
+    const int i0 = blockIdx.x * BM, j0 = blockIdx.y * GBN;
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(K, kbeg + kchunk);
     typedef typename acc4<T>::type V4;
-    V4 acc[2][2];
+    V4 acc[TI][TJ];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < TI; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = V4{0, 0, 0, 0};
+        for (int b = 0; b < TJ; ++b) acc[a][b] = V4{0, 0, 0, 0};
 
-    for (int k0 = kbeg; k0 < kend; k0 += GBK) {
+    T ra[PA], rb[PB];
+    auto load = [&](int k0) {
 #pragma unroll
-        for (int rep = 0; rep < 4; ++rep) {
+        for (int rep = 0; rep < PA; ++rep) {
             const int e = tid + 256 * rep;
             int i, k;
-            if (!TA) { i = e % GBM; k = e / GBM; } else { k = e % GBK; i = e / GBK; }
+            if (!TA) { i = e % BM; k = e / BM; } else { k = e % GBK; i = e / GBK; }
             const int gi = i0 + i, gk = k0 + k;
             T v = 0;
             if (gi < M && gk < kend)
                 v = TA ? A[(size_t)gi * lda + gk] : A[(size_t)gk * lda + gi];
-            As[k][i] = v;
+            ra[rep] = v;
         }
 #pragma unroll
-        for (int rep = 0; rep < 4; ++rep) {
+        for (int rep = 0; rep < PB; ++rep) {
             const int e = tid + 256 * rep;
             int j, k;
             if (!TB) { k = e % GBK; j = e / GBK; } else { j = e % GBN; k = e / GBN; }
@@ -58,34 +67,51 @@ __global__ __launch_bounds__(256) void gemm_kernel(
             T v = 0;
             if (gj < N && gk < kend)
                 v = TB ? B[(size_t)gk * ldb + gj] : B[(size_t)gj * ldb + gk];
-            Bs[k][j] = v;
+            rb[rep] = v;
+        }
+    };
+    if (kbeg < kend) load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += GBK) {
+        __syncthreads();
+#pragma unroll
+        for (int rep = 0; rep < PA; ++rep) {
+            const int e = tid + 256 * rep;
+            int i, k;
+            if (!TA) { i = e % BM; k = e / BM; } else { k = e % GBK; i = e / GBK; }
+            As[k][i] = ra[rep];
+        }
+#pragma unroll
+        for (int rep = 0; rep < PB; ++rep) {
+            const int e = tid + 256 * rep;
+            int j, k;
+            if (!TB) { k = e % GBK; j = e / GBK; } else { j = e % GBN; k = e / GBN; }
+            Bs[k][j] = rb[rep];
         }
         __syncthreads();
+        if (k0 + GBK < kend) load(k0 + GBK);
 #pragma unroll
         for (int kk = 0; kk < GBK; kk += 4) {
-            T a[2], b[2];
+            T a[TI], b[TJ];
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                a[t] = As[kk + lane / 16][wm * 32 + t * 16 + lane % 16];
-                b[t] = Bs[kk + lane / 16][wn * 32 + t * 16 + lane % 16];
-            }
+            for (int t = 0; t < TI; ++t) a[t] = As[kk + lane / 16][wm * 32 + t * 16 + lane % 16];
 #pragma unroll
-            for (int ti = 0; ti < 2; ++ti)
+            for (int t = 0; t < TJ; ++t) b[t] = Bs[kk + lane / 16][wn * 16 * TJ + t * 16 + lane % 16];
 #pragma unroll
-                for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = mfma16(a[ti], b[tj], acc[ti][tj]);
+            for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < TJ; ++tj) acc[ti][tj] = mfma16(a[ti], b[tj], acc[ti][tj]);
         }
-        __syncthreads();
     }
 
     float dmax = 0.f;
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
+    for (int ti = 0; ti < TI; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
+        for (int tj = 0; tj < TJ; ++tj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int gi = i0 + wm * 32 + ti * 16 + mfma_row<T>(lane, r);
-                const int gj = j0 + wn * 32 + tj * 16 + lane % 16;
+                const int gj = j0 + wn * 16 * TJ + tj * 16 + lane % 16;
                 if (gi < M && gj < N) {
                     const T v = alpha * acc[ti][tj][r];
                     if (EPI == EPI_STORE) {
@@ -125,18 +151,18 @@ __global__ __launch_bounds__(256) void splitk_reduce(int M, int N, int nz,
     *c = (beta == T(0)) ? s : s + beta * (*c);
 }
 
-template <typename T, bool TA, bool TB>
-static void gemm_launch(hipStream_t s, int M, int N, int K, T alpha, const T *A, int lda,
-                        const T *B, int ldb, T beta, T *C, int ldc, T *split,
-                        size_t split_elems) {
-    if (M <= 0 || N <= 0) return;
-    const int tm = cdiv(M, GBM), tn = cdiv(N, GBN);
+template <typename T, bool TA, bool TB, int BM>
+static void gemm_launch_bm(hipStream_t s, int M, int N, int K, T alpha, const T *A, int lda,
+                           const T *B, int ldb, T beta, T *C, int ldc, T *split,
+                           size_t split_elems) {
+    const int tm = cdiv(M, BM), tn = cdiv(N, GBN);
     const int tiles = tm * tn;
     int nz = 1;
     if (K <= 0) {
         // C = beta C
-        hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_STORE>), dim3(tm, tn, 1), dim3(256), 0, s,
-                           M, N, 0, alpha, A, lda, B, ldb, beta, C, ldc, 16, (T *)nullptr, (float *)nullptr);
+        hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_STORE, BM>), dim3(tm, tn, 1), dim3(256), 0, s,
+                           M, N, 0, alpha, A, lda, B, ldb, beta, C, ldc, GBK, (T *)nullptr,
+                           (float *)nullptr);
         return;
     }
     if (split && tiles < 512 && K >= 512) {
@@ -148,15 +174,28 @@ static void gemm_launch(hipStream_t s, int M, int N, int K, T alpha, const T *A,
     int kchunk = cdiv(cdiv(K, nz), GBK) * GBK;
     nz = cdiv(K, kchunk);
     if (nz == 1) {
-        hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_STORE>), dim3(tm, tn, 1), dim3(256), 0, s,
-                           M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, (T *)nullptr, (float *)nullptr);
+        hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_STORE, BM>), dim3(tm, tn, 1), dim3(256), 0, s,
+                           M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, (T *)nullptr,
+                           (float *)nullptr);
     } else {
-        hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_PART>), dim3(tm, tn, nz), dim3(256), 0, s,
-                           M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, split, (float *)nullptr);
+        hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_PART, BM>), dim3(tm, tn, nz), dim3(256), 0, s,
+                           M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, split,
+                           (float *)nullptr);
         const size_t MN = (size_t)M * N;
         hipLaunchKernelGGL((splitk_reduce<T>), dim3((unsigned)cdivl((long long)MN, 256)), dim3(256), 0, s,
                            M, N, nz, split, beta, C, ldc);
     }
+}
+
+template <typename T, bool TA, bool TB>
+static void gemm_launch(hipStream_t s, int M, int N, int K, T alpha, const T *A, int lda,
+                        const T *B, int ldb, T beta, T *C, int ldc, T *split,
+                        size_t split_elems) {
+    if (M <= 0 || N <= 0) return;
+    if (M <= 32)
+        gemm_launch_bm<T, TA, TB, 32>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, split, split_elems);
+    else
+        gemm_launch_bm<T, TA, TB, 64>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, split, split_elems);
 }
 
 template <typename T>
@@ -175,8 +214,8 @@ template void gemm<float>(hipStream_t, bool, bool, int, int, int, float, const f
 
 void gemm_orth_maxdev(hipStream_t s, int n, const float *X, int ldx, float *maxdev) {
     if (n <= 0) return;
-    const int t = cdiv(n, GBM);
-    hipLaunchKernelGGL((gemm_kernel<float, true, false, EPI_MAXDEV>), dim3(t, t, 1), dim3(256), 0, s,
+    const int t = cdiv(n, 64);
+    hipLaunchKernelGGL((gemm_kernel<float, true, false, EPI_MAXDEV, 64>), dim3(t, t, 1), dim3(256), 0, s,
                        n, n, n, 1.0f, X, ldx, X, ldx, 0.0f, (float *)nullptr, n, cdiv(n, GBK) * GBK,
                        (float *)nullptr, maxdev);
 }
