@@ -30,8 +30,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(
     constexpr int WN = BM == 64 ? 2 : 4;           // wavefronts along N
     constexpr int TI = 2, TJ = BM == 64 ? 2 : 1;   // MFMA tiles per wavefront
     constexpr int PA = BM * GBK / 256, PB = GBK * GBN / 256;
-    __shared__ T As[GBK][BM + 1];
-    __shared__ T Bs[GBK][GBN + 1];
+    // LDS: the K slices of A and B, reused after the K loop for the output
+    // tile so that C is read and written along its columns
+    constexpr size_t SZ_AB = sizeof(T) * (GBK * (BM + 1) + GBK * (GBN + 1));
+    constexpr size_t SZ_C = sizeof(T) * GBN * (BM + 1);
+    __shared__ __align__(16) char smem[SZ_AB > SZ_C ? SZ_AB : SZ_C];
+    T (*As)[BM + 1] = reinterpret_cast<T (*)[BM + 1]>(smem);
+    T (*Bs)[GBN + 1] = reinterpret_cast<T (*)[GBN + 1]>(smem + sizeof(T) * GBK * (BM + 1));
+    T (*Cs)[BM + 1] = reinterpret_cast<T (*)[BM + 1]>(smem);
     __shared__ float red[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w / WN, wn = w % WN;
@@ -104,27 +110,47 @@ __global__ __launch_bounds__(256) void gemm_kernel(
     }
 
     float dmax = 0.f;
+    if (EPI == EPI_MAXDEV) {
 #pragma unroll
-    for (int ti = 0; ti < TI; ++ti)
+        for (int ti = 0; ti < TI; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < TJ; ++tj)
+            for (int tj = 0; tj < TJ; ++tj)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gi = i0 + wm * 32 + ti * 16 + mfma_row<T>(lane, r);
-                const int gj = j0 + wn * 16 * TJ + tj * 16 + lane % 16;
-                if (gi < M && gj < N) {
-                    const T v = alpha * acc[ti][tj][r];
-                    if (EPI == EPI_STORE) {
-                        T *c = C + (size_t)gj * ldc + gi;
-                        *c = (beta == T(0)) ? v : v + beta * (*c);
-                    } else if (EPI == EPI_PART) {
-                        part[(size_t)blockIdx.z * M * N + (size_t)gj * M + gi] = v;
-                    } else {
-                        const float d = fabsf((float)v - (gi == gj ? 1.f : 0.f));
+                for (int r = 0; r < 4; ++r) {
+                    const int gi = i0 + wm * 32 + ti * 16 + mfma_row<T>(lane, r);
+                    const int gj = j0 + wn * 16 * TJ + tj * 16 + lane % 16;
+                    if (gi < M && gj < N) {
+                        const float d = fabsf((float)(alpha * acc[ti][tj][r]) - (gi == gj ? 1.f : 0.f));
                         dmax = fmaxf(dmax, d);
                     }
                 }
+    } else {
+        __syncthreads();   // the last slice's reads of As / Bs are done
+#pragma unroll
+        for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < TJ; ++tj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    Cs[wn * 16 * TJ + tj * 16 + lane % 16][wm * 32 + ti * 16 + mfma_row<T>(lane, r)] =
+                        acc[ti][tj][r];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < BM * GBN / 256; ++q) {
+            const int e = tid + 256 * q;
+            const int i = e % BM, j = e / BM;
+            const int gi = i0 + i, gj = j0 + j;
+            if (gi < M && gj < N) {
+                const T v = alpha * Cs[j][i];
+                if (EPI == EPI_STORE) {
+                    T *c = C + (size_t)gj * ldc + gi;
+                    *c = (beta == T(0)) ? v : v + beta * (*c);
+                } else {
+                    part[(size_t)blockIdx.z * M * N + (size_t)gj * M + gi] = v;
+                }
             }
+        }
+    }
     if (EPI == EPI_MAXDEV) {
         dmax = wave_max(dmax);
         if (lane == 0) red[w] = dmax;
