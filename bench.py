@@ -18,7 +18,7 @@ Prints one JSON line.  Options: --gpus (only 1), --steps K, --warmup W,
 for profiling runs), --no-cpu-baseline, --cpu-sample-n.
 
 roofline.traffic is the HBM traffic per launch of the dominant kernel from
-the counter runs recorded in profiles/qrcp_step_reg_f32_n4096_traffic.md; it
+the counter runs recorded in profiles/qrcp_persist_f32_n4096_traffic.md; it
 is reported only while the kernel's sources hash to the value recorded there.
 """
 from __future__ import annotations
@@ -53,7 +53,7 @@ def algorithmic_flops(n: int, info: dict, mixed: bool) -> float:
     return f
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "qrcp_step_reg_f32_n4096_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "qrcp_persist_f32_n4096_traffic.md")
 TRAFFIC_SOURCES = ["paper_2209_04626_amd/csrc/qrcp.hip", "paper_2209_04626_amd/csrc/common.hpp"]
 
 
@@ -83,6 +83,41 @@ def recorded_traffic(n: int):
         return float(rec["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+# per-class roofline: which roof bounds the class and the peak it is priced
+# against (HBM 8 TB/s; dense FP32 / FP64 157.3 / 78.6 TFLOP/s)
+CLASS_ROOF = {
+    "jac_gram<f32>": ("hbm", None), "jac_update<f32>": ("hbm", None),
+    "jac_gram<f64>": ("hbm", None), "jac_update<f64>": ("hbm", None),
+    "jac_inner<f32>": ("latency", FP64_PEAK_TF), "jac_inner<f64>": ("latency", FP64_PEAK_TF),
+    "qrcp": ("hbm", None), "qr_panel": ("latency", FP64_PEAK_TF), "gemm": ("mfma", FP64_PEAK_TF),
+}
+
+
+def kernel_table(info: dict, mp) -> list:
+    """Per kernel class of one clocked SVD: launches, time, algorithmic bytes
+    and flops per launch, achieved rates and the fraction of the roof that
+    bounds the class (hbm: bytes against 8 TB/s; mfma: flops against the FP64
+    matrix peak; latency: flops against the FP64 peak, for scale only)."""
+    rows = []
+    for c, name in enumerate(mp.KERNEL_CLASSES):
+        calls = info["kern_calls"][c]
+        if name == "-" or calls <= 0:
+            continue
+        ms = info["kern_ms"][c]
+        byts, flops = info["kern_bytes"][c], info["kern_flops"][c]
+        sec = ms / 1e3
+        gbs = byts / sec / 1e9 if sec > 0 else 0.0
+        tfs = flops / sec / 1e12 if sec > 0 else 0.0
+        bound, fpk = CLASS_ROOF.get(name, ("hbm", None))
+        frac = gbs / HBM_PEAK_GBS if bound == "hbm" else tfs / (fpk or FP64_PEAK_TF)
+        rows.append({"kernel": name, "launches": calls, "ms": round(ms, 3),
+                     "avg_us": round(ms * 1e3 / calls, 2), "bytes_per_launch": round(byts / calls),
+                     "flops_per_launch": round(flops / calls), "GB_s": round(gbs, 1),
+                     "TFLOP_s": round(tfs, 3), "bound": bound, "frac": round(frac, 4)})
+    rows.sort(key=lambda r: -r["ms"])
+    return rows
 
 
 def gates_gpu(A, U, S, V, s_ref, kappa_s):
@@ -212,25 +247,60 @@ def main() -> int:
     g_mixed = gates_gpu(A, Um, Sm, Vm, s_ref, kappa or 1.0) if do_mixed else None
     g_plain = gates_gpu(A, Up, Sp, Vp, s_ref, kappa or 1.0) if do_plain else None
 
-    # dominant kernel of the timed region (the FP32 pivot step of the mixed
-    # path) and its roofline
+    # per-class kernel clocks from one extra SVD of each kind (untimed, every
+    # launch bracketed by HIP events on the library's stream)
+    kernels = {}
+    if do_mixed:
+        oc = mp.default_opts(True)
+        oc.kernel_timing = 2
+        kernels["mixed"] = kernel_table(mp.svd(A, "mixed", workspace=ws, opts=oc)[3], mp)
+    if do_plain:
+        oc = mp.default_opts(False)
+        oc.kernel_timing = 2
+        kernels["plain"] = kernel_table(mp.svd(A, "plain", workspace=ws, opts=oc)[3], mp)
+    torch.cuda.synchronize()
+
+    # roofline of the dominant kernel of the step (largest class of the mixed
+    # SVD): the pivot pass is clocked inside the timed region (one interval
+    # per pass); another class would come from the clocked SVD
     roofline = None
     if do_mixed:
-        ms = np.sum([i["kern_ms"] for i in infos], axis=0)
-        calls = np.sum([i["kern_calls"] for i in infos], axis=0)
-        byts = np.sum([i["kern_bytes"] for i in infos], axis=0)
-        dom = mp.KERNEL_CLASSES.index("qrcp_step")
-        avg_s = ms[dom] / 1e3 / max(calls[dom], 1)
-        bytes_per_launch = byts[dom] / max(calls[dom], 1)
-        achieved = bytes_per_launch / avg_s / 1e9
-        traffic = recorded_traffic(n)
-        roofline = {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+        # the GEMM class gathers kernels of many shapes; the dominant kernel is
+        # the largest of the single-kernel classes
+        dom = [k for k in kernels["mixed"] if k["kernel"] != "gemm"][0]
+        if dom["kernel"] == "qrcp":
+            c = mp.KERNEL_CLASSES.index("qrcp")
+            ms = float(np.sum([i["kern_ms"][c] for i in infos]))
+            calls = int(np.sum([i["kern_calls"][c] for i in infos]))
+            byts = float(np.sum([i["kern_bytes"][c] for i in infos]))
+            avg_s = ms / 1e3 / max(calls, 1)
+            bytes_per_launch = byts / max(calls, 1)
+            src = "timed region"
+        else:
+            avg_s = dom["avg_us"] / 1e6
+            bytes_per_launch = dom["bytes_per_launch"]
+            calls = dom["launches"]
+            src = "clocked SVD after the timed region"
+        traffic = recorded_traffic(n) if dom["kernel"] == "qrcp" else None
+        if dom["bound"] == "mfma":
+            ach = dom["TFLOP_s"]
+            roofline = {"bound": "mfma", "achieved": round(ach, 2), "peak": FP64_PEAK_TF,
+                        "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TF, 4)}
+        elif dom["bound"] == "latency":
+            # a chain of dependent LDS rounds: priced against the FP64 vector
+            # ALU peak (256 CUs x 128 FP64 flop/clk x 2.4 GHz)
+            ach = dom["TFLOP_s"]
+            roofline = {"bound": "alu", "achieved": round(ach, 3), "peak": FP64_PEAK_TF,
+                        "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TF, 4)}
+        else:
+            ach = bytes_per_launch / avg_s / 1e9
+            roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4)}
+        roofline.update({
             "traffic": None if traffic is None else round(traffic),
-            "kernel": "qrcp_step_reg<float,64>", "avg_us": round(avg_s * 1e6, 2),
-            "launches": int(calls[dom]), "bytes_per_launch": round(bytes_per_launch),
-        }
+            "kernel": dom["kernel"], "avg_us": round(avg_s * 1e6, 2), "launches": calls,
+            "bytes_per_launch": round(bytes_per_launch), "measured": src,
+        })
 
     line = {
         "metric": "n=4096 SVD time: mixed vs plain FP64 Jacobi, same GPU, sigma rel err <=1e-13",
@@ -266,6 +336,7 @@ def main() -> int:
             "gates_plain": g_plain,
         })
     line["roofline"] = roofline
+    line["kernels"] = kernels
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_sample_n)

@@ -86,23 +86,27 @@ typedef struct {
                               Gram block per block pair; 0 = auto (1) */
     int kernel_timing;     /* 1: time the QRCP pivot pass as one interval
                               (class SVD_K_QRCP, negligible overhead);
-                              2: bracket every launch of every hot kernel with
-                              HIP events (per-class totals; adds host work).
-                              Results in svd_info.kern_ms / kern_calls. */
+                              2: bracket every launch of the Jacobi, pivot,
+                              QR panel and GEMM kernels with HIP events
+                              (per-class totals; adds host work and a little
+                              time).  Results in svd_info.kern_*. */
     double low_stop_off;   /* end the FP32 stage once a sweep starts with
                               every |g_pq| <= low_stop_off sqrt(g_pp g_qq);
                               0 = only the eps_low rule.  Default 0. */
 } svd_opts;
 
-/* Kernel classes reported by svd_info.kern_ms when kernel_timing = 1 */
+/* Kernel classes reported by svd_info.kern_* (kernel_timing 1: SVD_K_QRCP
+   only; 2: all of them) */
 #define SVD_K_GRAM32 0     /* Jacobi Gram blocks, FP32 stage          */
 #define SVD_K_INNER32 1    /* Jacobi 2b x 2b inner solve, FP32 stage  */
 #define SVD_K_UPDATE32 2   /* Jacobi block rotation update, FP32      */
 #define SVD_K_GRAM64 3
 #define SVD_K_INNER64 4
 #define SVD_K_UPDATE64 5
-#define SVD_K_QRCP 6       /* one pivot step of the QRCP pass         */
-#define SVD_K_NCLASS 8
+#define SVD_K_QRCP 6       /* pivot pass launches (one, or one per step) */
+#define SVD_K_QRPANEL 7    /* Householder panel factorisations        */
+#define SVD_K_GEMM 8       /* matrix-core GEMMs (with their split-K sums) */
+#define SVD_K_NCLASS 12
 
 typedef struct {
     int status;            /* SVD_OK / SVD_WARN_* / SVD_ERR_* */
@@ -118,8 +122,9 @@ typedef struct {
                               on the fresh Gram blocks (convergence trace) */
     float off_work[32];    /* the same for the FP64 sweeps */
     float kern_ms[SVD_K_NCLASS];   /* summed kernel durations per class */
-    int kern_calls[SVD_K_NCLASS];  /* launches per class (kernel_timing = 1) */
+    int kern_calls[SVD_K_NCLASS];  /* launches per class */
     double kern_bytes[SVD_K_NCLASS]; /* algorithmic HBM bytes of those launches */
+    double kern_flops[SVD_K_NCLASS]; /* algorithmic flops of those launches */
 } svd_info;
 
 /* Fill *o with the defaults above; mixed = 1 selects pivot_precision 32,

@@ -26,7 +26,8 @@ EXPORTS = [
 
 SVD_OK, SVD_WARN_NOCONV, SVD_ERR_NONFINITE, SVD_WARN_RANK_DEFICIENT = 0, 1, 2, 3
 KERNEL_CLASSES = ["jac_gram<f32>", "jac_inner<f32>", "jac_update<f32>", "jac_gram<f64>",
-                  "jac_inner<f64>", "jac_update<f64>", "qrcp_step", "-"]
+                  "jac_inner<f64>", "jac_update<f64>", "qrcp", "qr_panel", "gemm", "-", "-", "-"]
+NCLASS = 12
 BRANCH_AUTO, BRANCH_LOW, BRANCH_SKIP = 0, 1, 2
 
 
@@ -50,8 +51,8 @@ class SvdInfo(ctypes.Structure):
         ("sweeps_work", ctypes.c_int), ("n_small", ctypes.c_int), ("orth", ctypes.c_double),
         ("cond_r", ctypes.c_double), ("stage_ms", ctypes.c_float * 8),
         ("off_low", ctypes.c_float * 32), ("off_work", ctypes.c_float * 32),
-        ("kern_ms", ctypes.c_float * 8), ("kern_calls", ctypes.c_int * 8),
-        ("kern_bytes", ctypes.c_double * 8),
+        ("kern_ms", ctypes.c_float * NCLASS), ("kern_calls", ctypes.c_int * NCLASS),
+        ("kern_bytes", ctypes.c_double * NCLASS), ("kern_flops", ctypes.c_double * NCLASS),
     ]
 
     def as_dict(self) -> dict:
@@ -63,7 +64,7 @@ class SvdInfo(ctypes.Structure):
             "off_low": list(self.off_low)[:max(self.sweeps_low, 0)],
             "off_work": list(self.off_work)[:max(self.sweeps_work, 0)],
             "kern_ms": list(self.kern_ms), "kern_calls": list(self.kern_calls),
-            "kern_bytes": list(self.kern_bytes),
+            "kern_bytes": list(self.kern_bytes), "kern_flops": list(self.kern_flops),
         }
 
 

@@ -214,6 +214,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     KernelClock kclock;
     kclock.on = o.kernel_timing != 0;
     jw.kc = o.kernel_timing >= 2 ? &kclock : nullptr;
+    q.kc = jw.kc;
     float off_low[32] = {0}, off_work[32] = {0};
 
     Timer tm(s);
@@ -247,14 +248,10 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         piv_launches = qrcp_pivots<double>(s, n, A1, n, D(L.off_wp), w + L.off_nrm2, piv, jw.kc);
     if (o.kernel_timing == 1) {
         kclock.end(s);
-        // launches and algorithmic bytes of the whole pass (see qrcp_pivots)
-        const size_t es = o.pivot_precision == 32 ? 4 : 8;
-        double bytes = 0.0;
-        for (int k = 0; k < n; ++k) {
-            const double mm = n - k;
-            bytes += (2.0 * mm * (mm - 1) + mm) * es;
-        }
-        kclock.bytes[0] = bytes;
+        // launches and algorithmic work of the whole pass (see qrcp_pivots)
+        const int es = o.pivot_precision == 32 ? 4 : 8;
+        kclock.bytes[0] = qrcp_pass_bytes(n, es);
+        kclock.flops[0] = qrcp_pass_flops(n);
         kclock.pass_calls = piv_launches;
     }
     tm.mark(1);
@@ -313,13 +310,13 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         tm.mark(5);
         // a7: switch (Section 3.3, method of Algorithm 4): X^T U_low = Q R2, Y = X Q
         gemm<double>(s, true, false, n, n, n, 1.0, X, N, Ulow, N, 0.0, Bm, n, q.split,
-                     q.split_elems);
+                     q.split_elems, jw.kc);
         qr_factor(s, n, n, Bm, n, tau3, T3, q);
         set_identity(s, N, Vacc, N);
         qr_apply_left(s, false, n, n, Bm, n, T3, n, Vacc, N, q);
         zero_pad_fill(s, N, N, Y, N);
         gemm<double>(s, false, false, n, n, n, 1.0, X, N, Vacc, N, 0.0, Y, N, q.split,
-                     q.split_elems);
+                     q.split_elems, jw.kc);
         tm.mark(6);
     } else {
         MPJ_CHECK(hipMemcpyAsync(Y, X, (size_t)N * N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -357,6 +354,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
             info->kern_ms[c] = kclock.ms[c];
             info->kern_calls[c] = kclock.calls[c];
             info->kern_bytes[c] = kclock.tot_bytes[c];
+            info->kern_flops[c] = kclock.tot_flops[c];
         }
         if (o.kernel_timing == 1) info->kern_calls[SVD_K_QRCP] = kclock.pass_calls;
         for (int i = 0; i < 32; ++i) { info->off_low[i] = off_low[i]; info->off_work[i] = off_work[i]; }

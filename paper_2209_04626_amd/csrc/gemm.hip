@@ -226,17 +226,25 @@ static void gemm_launch(hipStream_t s, int M, int N, int K, T alpha, const T *A,
 
 template <typename T>
 void gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, T alpha, const T *A, int lda,
-          const T *B, int ldb, T beta, T *C, int ldc, T *split, size_t split_elems) {
+          const T *B, int ldb, T beta, T *C, int ldc, T *split, size_t split_elems,
+          KernelClock *kc) {
+    // algorithmic work: 2MNK flops; A, B read once, C written (and read
+    // when beta != 0)
+    if (kc)
+        kc->begin(s, 8, ((double)M * K + (double)K * N + (beta == T(0) ? 1.0 : 2.0) * M * N) * sizeof(T),
+                  2.0 * M * N * K);
     if (!ta && !tb) gemm_launch<T, false, false>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, split, split_elems);
     else if (ta && !tb) gemm_launch<T, true, false>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, split, split_elems);
     else if (!ta && tb) gemm_launch<T, false, true>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, split, split_elems);
     else gemm_launch<T, true, true>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, split, split_elems);
+    if (kc) kc->end(s);
 }
 
 template void gemm<double>(hipStream_t, bool, bool, int, int, int, double, const double *, int,
-                           const double *, int, double, double *, int, double *, size_t);
+                           const double *, int, double, double *, int, double *, size_t,
+                           KernelClock *);
 template void gemm<float>(hipStream_t, bool, bool, int, int, int, float, const float *, int,
-                          const float *, int, float, float *, int, float *, size_t);
+                          const float *, int, float, float *, int, float *, size_t, KernelClock *);
 
 void gemm_orth_maxdev(hipStream_t s, int n, const float *X, int ldx, float *maxdev) {
     if (n <= 0) return;

@@ -11,16 +11,18 @@ namespace mpj {
 // are taken from a pool, recorded around each launch and read after the
 // caller synchronises.
 struct KernelClock {
+    static constexpr int NC = 12;
     std::vector<hipEvent_t> ev;
     std::vector<int> cls;
-    std::vector<double> bytes;
+    std::vector<double> bytes, flops;
     size_t used = 0;
     bool on = false;
-    float ms[8] = {0};
-    int calls[8] = {0};
+    float ms[NC] = {0};
+    int calls[NC] = {0};
     int pass_calls = 0;
-    double tot_bytes[8] = {0};
-    void begin(hipStream_t s, int c, double b) {
+    double tot_bytes[NC] = {0};
+    double tot_flops[NC] = {0};
+    void begin(hipStream_t s, int c, double b, double f = 0.0) {
         if (!on) return;
         if (used + 2 > ev.size()) {
             hipEvent_t e0, e1;
@@ -30,9 +32,11 @@ struct KernelClock {
             ev.push_back(e1);
             cls.push_back(c);
             bytes.push_back(b);
+            flops.push_back(f);
         }
         cls[used / 2] = c;
         bytes[used / 2] = b;
+        flops[used / 2] = f;
         hipEventRecord(ev[used], s);
     }
     void end(hipStream_t s) {
@@ -49,6 +53,7 @@ struct KernelClock {
             ms[cls[i / 2]] += t;
             calls[cls[i / 2]] += 1;
             tot_bytes[cls[i / 2]] += bytes[i / 2];
+            tot_flops[cls[i / 2]] += flops[i / 2];
         }
         used = 0;
     }
@@ -64,7 +69,7 @@ struct KernelClock {
 template <typename T>
 void gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, T alpha,
           const T *A, int lda, const T *B, int ldb, T beta, T *C, int ldc,
-          T *split, size_t split_elems);
+          T *split, size_t split_elems, KernelClock *kc = nullptr);
 
 // maxdev = max_{i,j < n} |(X^T X)_ij - delta_ij| for the n x n FP32 matrix
 // X (ld ldx), accumulated into *maxdev (float bits, caller zeroes it).
@@ -84,6 +89,7 @@ struct QRScratch {
     double *split;  // split-K scratch
     size_t split_elems;
     int *flags;     // max_groups step flags of the one-launch panel
+    KernelClock *kc = nullptr;   // optional per-launch timing
 };
 size_t qr_scratch_doubles(int m, int ncols_max, size_t *split_elems);
 void qr_scratch_carve(QRScratch &q, double *base, int m, int ncols_max);
@@ -105,6 +111,10 @@ void qr_apply_left(hipStream_t s, bool trans, int m, int k, const double *Qf,
 // qrcp_scratch_bytes(n, sizeof(T)) bytes.  Returns the number of launches
 // the pass took (1 for the one-launch FP32 pass, else n).
 size_t qrcp_scratch_bytes(int n, int elem);
+double qrcp_step_bytes(int n, int k, int elem);
+double qrcp_step_flops(int n, int k);
+double qrcp_pass_bytes(int n, int elem);
+double qrcp_pass_flops(int n);
 template <typename T>
 int qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W,
                  void *scratch, int *piv, KernelClock *kc = nullptr);

@@ -373,8 +373,11 @@ static void panel_factor(hipStream_t s, int mp, int nb, double *P, int ld, doubl
                          double *T, QRScratch &q, int panel) {
     const int G = cdiv(mp, QR_RC);
     if (G <= QR_COOP_MAXG) {
+        // algorithmic work: the panel read and written once, 2 mp nb^2 flops
+        if (q.kc) q.kc->begin(s, 7, 2.0 * mp * nb * sizeof(double), 2.0 * mp * nb * nb);
         hipLaunchKernelGGL(qr_panel_coop, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.part, q.head,
                            tau, q.flags, panel * 64);
+        if (q.kc) q.kc->end(s);
     } else {
         hipLaunchKernelGGL(qr_panel_init, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.part, q.head);
         for (int j = 0; j < nb; ++j)
@@ -383,7 +386,7 @@ static void panel_factor(hipStream_t s, int mp, int nb, double *P, int ld, doubl
     }
     extract_v(s, mp, nb, P, ld, q);
     gemm<double>(s, true, false, nb, nb, mp, 1.0, q.vb, mp, q.vb, mp, 0.0, q.vtv, QR_NB, q.split,
-                 q.split_elems);
+                 q.split_elems, q.kc);
     hipLaunchKernelGGL(qr_build_t, dim3(1), dim3(64), 0, s, nb, q.vtv, tau, T);
 }
 
@@ -391,9 +394,11 @@ static void panel_factor(hipStream_t s, int mp, int nb, double *P, int ld, doubl
 static void apply_block(hipStream_t s, bool transT, int mp, int nb, const double *T, int ncol,
                         double *C, int ldc, QRScratch &q) {
     gemm<double>(s, true, false, nb, ncol, mp, 1.0, q.vb, mp, C, ldc, 0.0, q.w1, nb, q.split,
-                 q.split_elems);
-    gemm<double>(s, transT, false, nb, ncol, nb, 1.0, T, QR_NB, q.w1, nb, 0.0, q.w2, nb, nullptr, 0);
-    gemm<double>(s, false, false, mp, ncol, nb, -1.0, q.vb, mp, q.w2, nb, 1.0, C, ldc, nullptr, 0);
+                 q.split_elems, q.kc);
+    gemm<double>(s, transT, false, nb, ncol, nb, 1.0, T, QR_NB, q.w1, nb, 0.0, q.w2, nb, nullptr, 0,
+                 q.kc);
+    gemm<double>(s, false, false, mp, ncol, nb, -1.0, q.vb, mp, q.w2, nb, 1.0, C, ldc, nullptr, 0,
+                 q.kc);
 }
 
 void qr_factor(hipStream_t s, int m, int n, double *A, int lda, double *tau, double *Tall,

@@ -479,6 +479,28 @@ __global__ void qrcp_persist_reset(int nkeys, unsigned long long *keys, int *err
     if (e == 0) *err = 0;
 }
 
+// Algorithmic work of pivot step k (the trailing-matrix pass of Businger-
+// Golub QRCP): the m x (m-1) trailing block read once (m = n - k), and
+// 4 m (m-1) flops (the dot products and the rank-one update).
+double qrcp_step_bytes(int n, int k, int elem) {
+    const double m = n - k;
+    return m * (m - 1) * elem;
+}
+double qrcp_step_flops(int n, int k) {
+    const double m = n - k;
+    return 4.0 * m * (m - 1);
+}
+double qrcp_pass_bytes(int n, int elem) {
+    double b = 0.0;
+    for (int k = 0; k < n; ++k) b += qrcp_step_bytes(n, k, elem);
+    return b;
+}
+double qrcp_pass_flops(int n) {
+    double f = 0.0;
+    for (int k = 0; k < n; ++k) f += qrcp_step_flops(n, k);
+    return f;
+}
+
 size_t qrcp_scratch_bytes(int n, int elem) {
     // fallback: two norm vectors; compacted step: perm + two candidate arrays
     const size_t a = (size_t)2 * n * elem;
@@ -493,7 +515,7 @@ size_t qrcp_scratch_bytes(int n, int elem) {
 // The one-launch FP32 pass; false when it does not apply or could not run
 // (then nothing observable has changed and the caller takes the step path).
 static bool qrcp_persist_pass(hipStream_t s, int n, const double *A1, int lda, float *W,
-                              void *scratch, int *piv) {
+                              void *scratch, int *piv, KernelClock *kc) {
     if (n < 128 || n > 64 * 64) return false;
     const int nwg = cdiv(n, QP_W);
     unsigned long long *keys = (unsigned long long *)scratch;
@@ -515,6 +537,7 @@ static bool qrcp_persist_pass(hipStream_t s, int n, const double *A1, int lda, f
     if (per_cu < 1 || nwg > ncu) return false;
     hipLaunchKernelGGL(qrcp_persist_reset, dim3(cdiv(2 * nwg, 256)), dim3(256), 0, s, 2 * nwg, keys,
                        err);
+    if (kc) kc->begin(s, SVD_K_QRCP, qrcp_pass_bytes(n, sizeof(float)), qrcp_pass_flops(n));
     if (n <= 64 * 16)
         hipLaunchKernelGGL((qrcp_persist<16>), dim3(nwg), dim3(QP_NT), 0, s, n, A1, lda, cbuf, keys,
                            err, piv);
@@ -524,6 +547,7 @@ static bool qrcp_persist_pass(hipStream_t s, int n, const double *A1, int lda, f
     else
         hipLaunchKernelGGL((qrcp_persist<64>), dim3(nwg), dim3(QP_NT), 0, s, n, A1, lda, cbuf, keys,
                            err, piv);
+    if (kc) kc->end(s);
     if (hipGetLastError() != hipSuccess) return false;
     int h_err = 1;
     if (hipMemcpyAsync(&h_err, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -545,15 +569,14 @@ int qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, void *scr
         for (int k = 0; k < n; ++k) {
             const T *nin = norms2 + (size_t)(k & 1) * n;
             T *nout = norms2 + (size_t)((k + 1) & 1) * n;
-            const double m = n - k;
-            if (kc) kc->begin(s, SVD_K_QRCP, (2.0 * m * (m - 1) + m) * sizeof(T));
+            if (kc) kc->begin(s, SVD_K_QRCP, qrcp_step_bytes(n, k, sizeof(T)), qrcp_step_flops(n, k));
             hipLaunchKernelGGL((qrcp_step<T>), dim3(cdiv(n, CP_CPW)), dim3(CP_NT), 0, s, k, n, W, nin,
                                nout, piv);
             if (kc) kc->end(s);
         }
         return n;
     }
-    if (sizeof(T) == 4 && !kc && qrcp_persist_pass(s, n, A1, lda, (float *)W, scratch, piv))
+    if (sizeof(T) == 4 && qrcp_persist_pass(s, n, A1, lda, (float *)W, scratch, piv, kc))
         return 1;
     int *perm = (int *)scratch;
     const size_t ncand = (size_t)cdiv(n, Q2_W) + 1;
@@ -565,11 +588,7 @@ int qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, void *scr
         Cand<T> *cout = cand + (size_t)((k + 1) & 1) * ncand;
         const int ncin = cdiv(n - k, Q2_W);
         const int nwg = n - k - 1 > 0 ? cdiv(n - k - 1, Q2_W) : 1;
-        // algorithmic bytes of step k: the active trailing block (rows k..n-1
-        // of the n-k-1 remaining columns) read and written once, the pivot
-        // column read once
-        const double m = n - k;
-        if (kc) kc->begin(s, SVD_K_QRCP, (2.0 * m * (m - 1) + m) * sizeof(T));
+        if (kc) kc->begin(s, SVD_K_QRCP, qrcp_step_bytes(n, k, sizeof(T)), qrcp_step_flops(n, k));
         if (n <= 64 * 16)
             hipLaunchKernelGGL((qrcp_step2<T, 16>), dim3(nwg), dim3(Q2_NT), 0, s, k, n, W, perm, cin,
                                ncin, cout, piv);
