@@ -537,16 +537,24 @@ static int sweeps_impl(hipStream_t s, int N, T *Y, T *V, double eps, int maxswee
         // kernel-class ids for the optional per-launch clock
         const int kbase = sizeof(T) == 4 ? 0 : 3;
         const double E = sizeof(T);
-        const double gram_bytes = (double)N * N * E;                      // Y read once
-        const double upd_bytes = 2.0 * (double)N * N * E * (V ? 2 : 1);   // Y (and V) read + written
+        // algorithmic work per round: the Gram blocks read Y once and cost
+        // N (2b)^2 flops per pair for the symmetric product; the update reads
+        // and writes Y (and V) once and costs 2 N (2b)^2 flops per pair and
+        // matrix; the inner solve is (2b - 1) rounds of b rotations applied
+        // two-sided to the 2b x 2b block and one-sided to W (12 (2b)^2 b flops)
+        const double gram_bytes = (double)N * N * E;
+        const double gram_flops = (double)npairs * N * B2 * B2;
+        const double upd_bytes = 2.0 * (double)N * N * E * (V ? 2 : 1);
+        const double upd_flops = 2.0 * (double)npairs * N * B2 * B2 * (V ? 2 : 1);
+        const double inner_flops = 12.0 * (double)npairs * B2 * B2 * b;
         for (int r = 0; r < nblk - 1; ++r) {
-            if (jw.kc) jw.kc->begin(s, kbase + 0, gram_bytes);
+            if (jw.kc) jw.kc->begin(s, kbase + 0, gram_bytes, gram_flops);
             hipLaunchKernelGGL((jac_gram<T, B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, N, nblk, r, Y,
                                N, (T *)jw.gram, nchG);
-            if (jw.kc) { jw.kc->end(s); jw.kc->begin(s, kbase + 1, 0.0); }
+            if (jw.kc) { jw.kc->end(s); jw.kc->begin(s, kbase + 1, 0.0, inner_flops); }
             hipLaunchKernelGGL((jac_inner<T, B2, INNER_NT>), dim3(npairs), dim3(INNER_NT), 0, s, nchG,
                                (const T *)jw.gram, (T *)jw.wmat, jw.skip, jw.flag, eps, max_inner);
-            if (jw.kc) { jw.kc->end(s); jw.kc->begin(s, kbase + 2, upd_bytes); }
+            if (jw.kc) { jw.kc->end(s); jw.kc->begin(s, kbase + 2, upd_bytes, upd_flops); }
             hipLaunchKernelGGL((jac_update<T, B2>), dim3(npairs, nch + nchV), dim3(JR_NT), 0, s, N,
                                nblk, r, Y, N, V, N, nch, (const T *)jw.wmat, jw.skip);
             if (jw.kc) jw.kc->end(s);
