@@ -95,24 +95,27 @@ CLASS_ROOF = {
 }
 
 
-def kernel_table(info: dict, mp) -> list:
+def kernel_table(info: dict, mp, overhead_s: float = 0.0) -> list:
     """Per kernel class of one clocked SVD: launches, time, algorithmic bytes
     and flops per launch, achieved rates and the fraction of the roof that
     bounds the class (hbm: bytes against 8 TB/s; mfma: flops against the FP64
-    matrix peak; latency: flops against the FP64 peak, for scale only)."""
+    matrix peak; latency: flops against the FP64 peak, for scale only).
+    overhead_s, the time the event brackets add to one launch, is taken off
+    each launch (ms_raw keeps the bracketed total)."""
     rows = []
     for c, name in enumerate(mp.KERNEL_CLASSES):
         calls = info["kern_calls"][c]
         if name == "-" or calls <= 0:
             continue
-        ms = info["kern_ms"][c]
+        ms_raw = info["kern_ms"][c]
+        ms = max(ms_raw - calls * overhead_s * 1e3, 0.5 * ms_raw)
         byts, flops = info["kern_bytes"][c], info["kern_flops"][c]
         sec = ms / 1e3
         gbs = byts / sec / 1e9 if sec > 0 else 0.0
         tfs = flops / sec / 1e12 if sec > 0 else 0.0
         bound, fpk = CLASS_ROOF.get(name, ("hbm", None))
         frac = gbs / HBM_PEAK_GBS if bound == "hbm" else tfs / (fpk or FP64_PEAK_TF)
-        rows.append({"kernel": name, "launches": calls, "ms": round(ms, 3),
+        rows.append({"kernel": name, "launches": calls, "ms": round(ms, 3), "ms_raw": round(ms_raw, 3),
                      "avg_us": round(ms * 1e3 / calls, 2), "bytes_per_launch": round(byts / calls),
                      "flops_per_launch": round(flops / calls), "GB_s": round(gbs, 1),
                      "TFLOP_s": round(tfs, 3), "bound": bound, "frac": round(frac, 4)})
@@ -249,15 +252,24 @@ def main() -> int:
 
     # per-class kernel clocks from one extra SVD of each kind (untimed, every
     # launch bracketed by HIP events on the library's stream)
-    kernels = {}
-    if do_mixed:
-        oc = mp.default_opts(True)
+    # The brackets add a little to each launch; the added time per launch is
+    # estimated from the clocked SVD's wall time against the timed one and
+    # taken off each class before the dominant kernel is chosen.
+    kernels, clock_overhead_us = {}, {}
+    for mode, t_ref, on in (("mixed", t_mixed, do_mixed), ("plain", t_plain, do_plain)):
+        if not on:
+            continue
+        oc = mp.default_opts(mode == "mixed")
         oc.kernel_timing = 2
-        kernels["mixed"] = kernel_table(mp.svd(A, "mixed", workspace=ws, opts=oc)[3], mp)
-    if do_plain:
-        oc = mp.default_opts(False)
-        oc.kernel_timing = 2
-        kernels["plain"] = kernel_table(mp.svd(A, "plain", workspace=ws, opts=oc)[3], mp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info_c = mp.svd(A, mode, workspace=ws, opts=oc)[3]
+        torch.cuda.synchronize()
+        t_c = time.perf_counter() - t0
+        ncalls = sum(info_c["kern_calls"])
+        ovh = max(0.0, (t_c - t_ref) / max(ncalls, 1))
+        clock_overhead_us[mode] = round(ovh * 1e6, 3)
+        kernels[mode] = kernel_table(info_c, mp, ovh)
     torch.cuda.synchronize()
 
     # roofline of the dominant kernel of the step (largest class of the mixed
@@ -337,6 +349,7 @@ def main() -> int:
         })
     line["roofline"] = roofline
     line["kernels"] = kernels
+    line["kernel_clock_overhead_us"] = clock_overhead_us
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_sample_n)
