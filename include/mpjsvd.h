@@ -81,7 +81,8 @@ typedef struct {
     int sign_normalize;    /* 1: make the largest |V(k, i)| of each column
                               positive (first k on ties), negating U(:, i)
                               with it */
-    int block_cols;        /* Jacobi block width b (16 or 32); 0 = auto */
+    int block_cols;        /* Jacobi block width b (16 or 32) of both stages;
+                              0 = per stage (block_cols_low / _work) */
     int inner_sweeps;      /* cap on the Jacobi sweeps run on each 2b x 2b
                               Gram block per block pair; 0 = auto (1) */
     int kernel_timing;     /* 1: time the QRCP pivot pass as one interval
@@ -93,6 +94,11 @@ typedef struct {
     double low_stop_off;   /* end the FP32 stage once a sweep starts with
                               every |g_pq| <= low_stop_off sqrt(g_pp g_qq);
                               0 = only the eps_low rule.  Default 0. */
+    int block_cols_low;    /* b of the FP32 stage (16 or 32), over block_cols;
+                              0 = block_cols, else the tuning table, else 16 */
+    int block_cols_work;   /* b of the FP64 stage (16 or 32), over block_cols;
+                              0 = block_cols, else the tuning table, else
+                              32 for n >= 512 and 16 below */
 } svd_opts;
 
 /* Kernel classes reported by svd_info.kern_* (kernel_timing 1: SVD_K_QRCP
@@ -126,6 +132,23 @@ typedef struct {
     double kern_bytes[SVD_K_NCLASS]; /* algorithmic HBM bytes of those launches */
     double kern_flops[SVD_K_NCLASS]; /* algorithmic flops of those launches */
 } svd_info;
+
+/* Load the tuning table measured by the autotuner (not part of the paper's
+   method): JSON text of the form
+     {"arch": "gfx950",
+      "single":  [{"nmax": N, "b_low": 16|32, "b_work": 16|32}, ...],
+      "batched": [{"nmax": N, "wg_per_cu": W}, ...]}
+   An entry applies to problems with n <= nmax; the smallest such nmax wins.
+   "single" sets the Jacobi block widths of the two stages where svd_opts
+   leaves them at 0; "batched" sets the persistent grid of svd_batched (W
+   workgroups per compute unit, 1..16; default 2).  json = NULL clears the
+   table.  Returns 0, -2 on malformed JSON, -3 on an invalid entry (the
+   table is then unchanged).  The text is copied; thread-safe. */
+int svd_set_tuning(const char *json);
+
+/* The table's entries for size n (0 where the table has none).  Returns 1
+   if any entry applies, else 0.  Any output pointer may be NULL. */
+int svd_tuning_lookup(int n, int *b_low, int *b_work, int *wg_per_cu);
 
 /* Fill *o with the defaults above; mixed = 1 selects pivot_precision 32,
    mixed = 0 selects 64. */

@@ -17,11 +17,14 @@ from dataclasses import dataclass, field
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpjsvd.so")
+# tuning table measured on the target GPU by paper_2209_04626_amd/autotune.py
+TUNE_PATH = os.path.join(_HERE, "tune_gfx950.json")
 
 EXPORTS = [
     "svd_default_opts", "svd_workspace_size", "svd_plain", "svd_mixed",
     "svd_batched_plan_create", "svd_batched", "svd_batched_plan_destroy",
     "svd_backward_workspace_size", "svd_backward", "svd_status_string", "svd_last_error",
+    "svd_set_tuning", "svd_tuning_lookup",
 ]
 
 SVD_OK, SVD_WARN_NOCONV, SVD_ERR_NONFINITE, SVD_WARN_RANK_DEFICIENT = 0, 1, 2, 3
@@ -42,6 +45,7 @@ class SvdOpts(ctypes.Structure):
         ("pivot_precision", ctypes.c_int), ("sign_normalize", ctypes.c_int),
         ("block_cols", ctypes.c_int), ("inner_sweeps", ctypes.c_int),
         ("kernel_timing", ctypes.c_int), ("low_stop_off", ctypes.c_double),
+        ("block_cols_low", ctypes.c_int), ("block_cols_work", ctypes.c_int),
     ]
 
 
@@ -116,8 +120,34 @@ def load():
     lib.svd_status_string.restype = ctypes.c_char_p
     lib.svd_last_error.argtypes = []
     lib.svd_last_error.restype = ctypes.c_char_p
+    lib.svd_set_tuning.argtypes = [ctypes.c_char_p]
+    lib.svd_set_tuning.restype = ctypes.c_int
+    _ip = ctypes.POINTER(ctypes.c_int)
+    lib.svd_tuning_lookup.argtypes = [ctypes.c_int, _ip, _ip, _ip]
+    lib.svd_tuning_lookup.restype = ctypes.c_int
     _lib = lib
+    if os.path.exists(TUNE_PATH):
+        with open(TUNE_PATH) as fh:
+            rc = lib.svd_set_tuning(fh.read().encode())
+        if rc != 0:
+            raise RuntimeError(f"{TUNE_PATH}: tuning table rejected ({rc})")
     return lib
+
+
+def set_tuning(table) -> None:
+    """Load a tuning table (dict or JSON text; None clears it)."""
+    import json
+    text = None if table is None else (table if isinstance(table, str) else json.dumps(table))
+    rc = load().svd_set_tuning(None if text is None else text.encode())
+    if rc != 0:
+        raise ValueError(f"tuning table rejected ({rc})")
+
+
+def tuning_lookup(n: int) -> dict:
+    """The loaded table's entries for size n (0 = none)."""
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    load().svd_tuning_lookup(n, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    return {"b_low": a.value, "b_work": b.value, "wg_per_cu": c.value}
 
 
 def default_opts(mixed: bool = True, **kw) -> SvdOpts:

@@ -40,6 +40,8 @@ extern "C" void svd_default_opts(svd_opts *o, int mixed) {
     o->inner_sweeps = 0;
     o->kernel_timing = 0;
     o->low_stop_off = 0.0;
+    o->block_cols_low = 0;
+    o->block_cols_work = 0;
 }
 
 namespace {
@@ -58,7 +60,12 @@ struct Layout {
 // the inner 2b x 2b solves (b = 16 keeps them short), the FP64 stage with V by
 // the traffic of the block updates (b = 32 halves the rounds per sweep).
 int pick_b(int n, const svd_opts &o, bool low) {
-    if (o.block_cols == 16 || o.block_cols == 32) return o.block_cols;
+    auto ok = [](int b) { return b == 16 || b == 32; };
+    const int stage = low ? o.block_cols_low : o.block_cols_work;
+    if (ok(stage)) return stage;
+    if (ok(o.block_cols)) return o.block_cols;
+    const int t = tuned_block_cols(n, low);
+    if (ok(t)) return t;
     if (low) return 16;
     return n >= 512 ? 32 : 16;
 }

@@ -550,7 +550,9 @@ extern "C" int svd_batched_plan_create(int batch, const int *h_m, const int *h_n
         delete P;
         return SVD_ERR_HIP;
     }
-    P->nwg = std::max(1, std::min(batch, 2 * ncu));
+    int wpc = tuned_wg_per_cu(P->maxn);
+    if (wpc < 1) wpc = 2;
+    P->nwg = std::max(1, std::min(batch, wpc * ncu));
     P->prm.tol_orth = o.tol_orth;
     P->prm.tol_cond_coef = o.tol_cond_coef;
     P->prm.small_col_rel = o.small_col_rel;

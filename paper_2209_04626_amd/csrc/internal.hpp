@@ -62,6 +62,11 @@ struct KernelClock {
     }
 };
 
+// ---------------------------------------------------------------- tuning
+// Entries of the loaded tuning table for size n (0 = none).
+int tuned_block_cols(int n, bool low);
+int tuned_wg_per_cu(int nmax);
+
 // ---------------------------------------------------------------- GEMM
 // C (M x N, column-major, ldc) = alpha op(A) op(B) + beta C, op = transpose
 // when ta / tb.  `split` (may be NULL) is scratch for split-K partial

@@ -67,3 +67,44 @@ def test_status_strings():
     assert lib.svd_status_string(0) == b"ok"
     assert b"NaN" in lib.svd_status_string(2)
     assert b"invalid" in lib.svd_status_string(-3)
+
+
+def test_tuning_table_parse_lookup_and_reject():
+    """svd_set_tuning: the smallest nmax >= n applies, unknown members are
+    ignored, malformed or invalid tables are rejected and leave the loaded
+    table unchanged; the committed table (if any) is restored afterwards."""
+    lib = mp.load()
+    saved = open(mp.TUNE_PATH).read() if os.path.exists(mp.TUNE_PATH) else None
+    try:
+        mp.set_tuning('{"arch": "gfx950", "note": [1, {"x": "y"}], "flag": true,'
+                      ' "single": [{"nmax": 4096, "b_low": 16, "b_work": 32},'
+                      '            {"nmax": 128, "b_low": 32, "b_work": 16, "ms": 1.5}],'
+                      ' "batched": [{"nmax": 256, "wg_per_cu": 3}]}')
+        assert mp.tuning_lookup(100) == {"b_low": 32, "b_work": 16, "wg_per_cu": 3}
+        assert mp.tuning_lookup(128) == {"b_low": 32, "b_work": 16, "wg_per_cu": 3}
+        assert mp.tuning_lookup(129) == {"b_low": 16, "b_work": 32, "wg_per_cu": 3}
+        assert mp.tuning_lookup(257) == {"b_low": 16, "b_work": 32, "wg_per_cu": 0}
+        assert mp.tuning_lookup(5000) == {"b_low": 0, "b_work": 0, "wg_per_cu": 0}
+        for bad, code in (('{', -2), ('{"single": [1, 2]}', -2), ('{"a": tru}', -2),
+                          ('{"single": [{"nmax": 0, "b_low": 16, "b_work": 16}]}', -3),
+                          ('{"single": [{"nmax": 9, "b_low": 8, "b_work": 16}]}', -3),
+                          ('{"batched": [{"nmax": 9, "wg_per_cu": 99}]}', -3)):
+            assert lib.svd_set_tuning(bad.encode()) == code, bad
+        assert mp.tuning_lookup(100)["b_low"] == 32          # unchanged
+        mp.set_tuning(None)
+        assert lib.svd_tuning_lookup(100, None, None, None) == 0
+    finally:
+        mp.set_tuning(saved)
+
+
+def test_committed_tuning_table_is_loaded():
+    if not os.path.exists(mp.TUNE_PATH):
+        pytest.skip("no tuning table committed")
+    import json
+    table = json.load(open(mp.TUNE_PATH))
+    mp.load()
+    for e in table["single"]:
+        got = mp.tuning_lookup(e["nmax"])
+        assert (got["b_low"], got["b_work"]) == (e["b_low"], e["b_work"])
+    o = mp.default_opts(True)
+    assert o.block_cols == 0 and o.block_cols_low == 0 and o.block_cols_work == 0
