@@ -64,3 +64,17 @@ def test_c1_config(lib, mode):
     U, S, V, info = run(lib, A, mode)
     g = metrics.gates(A, U, S, V, So)
     assert info["status"] == 0 and g["pass"], (g, info)
+
+
+@pytest.mark.parametrize("b_low,b_work", [(16, 16), (16, 32), (32, 16), (32, 32)])
+def test_parity_block_widths(lib, b_low, b_work):
+    """Every Jacobi block-width choice the tuning table may select (both
+    stages) meets the gates: 300 x 300, five 64-column tiles with a ragged
+    tail, log-uniform sigma over 10 decades."""
+    print(f"case b_low={b_low} b_work={b_work}", flush=True)
+    A = known(300, 300, seed=31, e=10.0, kind="log")
+    Uo, So, Vo, _ = oracle.svd(A)
+    for mode in ("mixed", "plain"):
+        U, S, V, info = run(lib, A, mode, block_cols_low=b_low, block_cols_work=b_work)
+        g = metrics.gates(A, U, S, V, So)
+        assert info["status"] == 0 and g["pass"], (mode, g, info)
