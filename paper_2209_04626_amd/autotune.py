@@ -98,7 +98,10 @@ def tune_batched(torch, mp, testmats, batch, reps, log):
         log(f"[autotune] batched {batch} matrices, {w} workgroups per CU: {times[w]:.2f} ms")
         del plan
     mp.set_tuning(None)
-    best = min(times, key=times.get)
+    # the fewest workgroups per unit within 2 % of the fastest (each one holds
+    # its own workspace slice)
+    fastest = min(times.values())
+    best = min(w for w, t in times.items() if t <= 1.02 * fastest)
     return [{"nmax": max(nmax, 256), "wg_per_cu": best}], {"batch": batch,
                                                           "ms": {str(k): round(v, 2) for k, v in times.items()}}
 

@@ -21,8 +21,8 @@ __global__ __launch_bounds__(BW_NT) void k_svd_backward(
     int m, int n, const double *U, long long sU, const double *S, long long sS, const double *V,
     long long sV, const double *gU, const double *gS, const double *gV, double *gA, long long sA,
     double eps_deg, double *work) {
-    __shared__ double As[16][65];
-    __shared__ double Bs[16][65];
+    __shared__ double As[1][16][65];
+    __shared__ double Bs[1][16][65];
     const int bidx = blockIdx.x, tid = threadIdx.x;
     const double *u = U + bidx * sU, *s = S + bidx * sS, *v = V + bidx * sV;
     const double *gu = gU ? gU + bidx * sU : nullptr;

@@ -27,7 +27,7 @@
 
 namespace mpj {
 
-constexpr int BT_NT = WG_NT;           // 256 threads = 4 wavefronts
+constexpr int BT_NT = 1024;            // 16 wavefronts: 16 column pairs at a time
 constexpr int BT_W = BT_NT / 64;
 constexpr int BT_MAXN = 256;
 
@@ -261,8 +261,8 @@ __global__ __launch_bounds__(BT_NT) void bt_svd(int batch, const BatchMeta *__re
                                                 double *S_base, double *U_base, double *V_base,
                                                 double *work, svd_batch_info *info, int *counter) {
     __shared__ double red[BT_W];
-    __shared__ double As[16][65];
-    __shared__ double Bs[16][65];
+    __shared__ double As[BT_NT / 256][16][65];
+    __shared__ double Bs[BT_NT / 256][16][65];
     __shared__ int ish[4];
     __shared__ int flag;
     __shared__ double dsh[4];
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(BT_NT) void bt_svd(int batch, const BatchMeta *__re
                         Ulow[(size_t)j * n + i] = (double)((float)X[(size_t)j * n + i] * inv);
                 }
                 __syncthreads();
-                wg_gemm<true, false>(n, n, n, Ulow, n, Ulow, n, Bm, n, false, As, Bs);
+                wg_gemm<true, false, BT_NT>(n, n, n, Ulow, n, Ulow, n, Bm, n, false, As, Bs);
                 double dm = 0.0;
                 for (int e = tid; e < n * n; e += BT_NT)
                     dm = fmax(dm, fabs(Bm[e] - ((e % n) == (e / n) ? 1.0 : 0.0)));
@@ -406,10 +406,10 @@ __global__ __launch_bounds__(BT_NT) void bt_svd(int batch, const BatchMeta *__re
             }
             __syncthreads();
             // a7: X^T U_low = Q R2, Q formed explicitly, Y = X Q
-            wg_gemm<true, false>(n, n, n, X, n, Ulow, n, Bm, n, false, As, Bs);
+            wg_gemm<true, false, BT_NT>(n, n, n, X, n, Ulow, n, Bm, n, false, As, Bs);
             wg_qr(n, n, Bm, n, tau3, red);
             wg_apply_q(false, n, n, Bm, n, tau3, n, Vacc, n);
-            wg_gemm<false, false>(n, n, n, X, n, Vacc, n, Y, n, false, As, Bs);
+            wg_gemm<false, false, BT_NT>(n, n, n, X, n, Vacc, n, Y, n, false, As, Bs);
         } else {
             for (int e = tid; e < n * n; e += BT_NT) Y[e] = X[e];
             __syncthreads();
