@@ -76,7 +76,11 @@ typedef struct {
     int want_u;            /* 1: form U (m x n) */
     int want_v;            /* 1: form V (n x n); 0 skips V accumulation */
     int branch;            /* SVD_BRANCH_AUTO / _LOW / _SKIP */
-    int switch_method;     /* 1: Q = qr(X^T U_low) (Section 3.3, default) */
+    int switch_method;     /* 1: Q = qr(X^T U_low), the switch of Algorithm 4
+                              (Section 3.3, default); 2: Q = qr(fp64(V_low))
+                              with V_low accumulated in the FP32 stage (the
+                              switch of Algorithm 3, compared in Section 6);
+                              the workspace query depends on it */
     int pivot_precision;   /* 32 (Algorithm 5) or 64 (plain xGEQP3) */
     int sign_normalize;    /* 1: make the largest |V(k, i)| of each column
                               positive (first k on ties), negating U(:, i)

@@ -53,7 +53,7 @@ struct Layout {
     size_t off_atall, off_tau0, off_t0, off_a1, off_wp, off_nrm2, off_piv, off_a1p, off_tau1,
         off_t1, off_rt, off_tau2, off_t2, off_x, off_y, off_vacc, off_y32, off_xt, off_ulow, off_bm,
         off_tau3, off_t3, off_ux, off_vx, off_sig, off_rank, off_nrmx, off_small, off_qr, off_jac,
-        total;
+        off_v32, total;
 };
 
 // Jacobi block width per stage: the FP32 stage is bound by the latency of
@@ -99,6 +99,7 @@ Layout layout(int m, int n, const svd_opts &o) {
     L.off_y = take(NN * d);
     L.off_vacc = take(NN * d);
     L.off_y32 = take(NN * f);
+    L.off_v32 = take(o.switch_method == 2 ? NN * f : 0);   // V_low for switch method 2
     L.off_xt = take(nn * f);
     L.off_ulow = take(NN * d);
     L.off_bm = take(nn * d);
@@ -304,20 +305,32 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     const double eps_work = o.eps_work > 0 ? o.eps_work : sqrt((double)n) * ldexp(1.0, -53);
     int sweeps_low = 0, conv_low = 1;
     if (branch == SVD_BRANCH_LOW) {
-        // a6: FP32 one-sided Jacobi on low(X), no V (Section 3.2)
+        // a6: FP32 one-sided Jacobi on low(X) (Section 3.2); V_low is only
+        // accumulated for switch method 2
+        const bool vlow = o.switch_method == 2;
+        float *V32 = vlow ? (float *)(w + L.off_v32) : nullptr;
         convert_f64_f32(s, N, N, X, N, Y32, N);
+        if (vlow) {
+            set_identity(s, N, Ulow, N);
+            convert_f64_f32(s, N, N, Ulow, N, V32, N);
+        }
         jacobi_carve(jw, w + L.off_jac, N, L.b32, (int)sizeof(float));
         jw.off_hist = off_low;
         jw.stop_off = o.low_stop_off;
-        sweeps_low = jacobi_sweeps<float>(s, N, L.b32, Y32, nullptr, eps_low, o.maxsweep_low, inner,
+        sweeps_low = jacobi_sweeps<float>(s, N, L.b32, Y32, V32, eps_low, o.maxsweep_low, inner,
                                           jw, &conv_low);
         jw.stop_off = 0.0;
         if (sweeps_low < 0) return SVD_ERR_HIP;
-        normalize_f32_to_f64(s, N, N, Y32, N, Ulow, N);
         tm.mark(5);
-        // a7: switch (Section 3.3, method of Algorithm 4): X^T U_low = Q R2, Y = X Q
-        gemm<double>(s, true, false, n, n, n, 1.0, X, N, Ulow, N, 0.0, Bm, n, q.split,
-                     q.split_elems, jw.kc);
+        // a7: switch (Section 3.3).  Method 1 (Algorithm 4): B = X^T U_low;
+        // method 2: B = fp64(V_low).  Then B = Q R2, Y = X Q.
+        if (vlow) {
+            convert_f32_f64(s, n, n, V32, N, Bm, n);
+        } else {
+            normalize_f32_to_f64(s, N, N, Y32, N, Ulow, N);
+            gemm<double>(s, true, false, n, n, n, 1.0, X, N, Ulow, N, 0.0, Bm, n, q.split,
+                         q.split_elems, jw.kc);
+        }
         qr_factor(s, n, n, Bm, n, tau3, T3, q);
         set_identity(s, N, Vacc, N);
         qr_apply_left(s, false, n, n, Bm, n, T3, n, Vacc, N, q);

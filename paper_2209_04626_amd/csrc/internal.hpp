@@ -162,6 +162,7 @@ void col_norms(hipStream_t s, int rows, int n, const double *X, int ldx, double 
 void count_small(hipStream_t s, int n, const double *nrm, double rel, int *out);
 void make_xt32(hipStream_t s, int n, const double *X, int ldx, float *Xt, int ldt);
 void convert_f64_f32(hipStream_t s, int rows, int cols, const double *X, int ldx, float *Y, int ldy);
+void convert_f32_f64(hipStream_t s, int rows, int cols, const float *X, int ldx, double *Y, int ldy);
 void normalize_f32_to_f64(hipStream_t s, int rows, int cols, const float *Y, int ldy, double *U, int ldu);
 void finalize_sort(hipStream_t s, int n, int N, const double *Y, const double *V,
                    double *sig, int *rank, double *UX, double *VX, double *S, int *nzero,

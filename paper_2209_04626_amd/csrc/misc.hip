@@ -183,6 +183,17 @@ void convert_f64_f32(hipStream_t s, int rows, int cols, const double *X, int ldx
                        ldy);
 }
 
+__global__ void k_f32_f64(int rows, int cols, const float *X, int ldx, double *Y, int ldy) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)rows * cols) return;
+    const int i = (int)(e % rows), j = (int)(e / rows);
+    Y[(size_t)j * ldy + i] = (double)X[(size_t)j * ldx + i];
+}
+void convert_f32_f64(hipStream_t s, int rows, int cols, const float *X, int ldx, double *Y, int ldy) {
+    hipLaunchKernelGGL(k_f32_f64, grid1((size_t)rows * cols), dim3(256), 0, s, rows, cols, X, ldx, Y,
+                       ldy);
+}
+
 // U(:, j) = double(Y(:, j) / ||Y(:, j)||), the FP32 left vectors U_low lifted to FP64.
 __global__ __launch_bounds__(256) void k_norm_f32_f64(int rows, int cols, const float *Y, int ldy,
                                                       double *U, int ldu) {

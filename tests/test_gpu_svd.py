@@ -78,3 +78,18 @@ def test_parity_block_widths(lib, b_low, b_work):
         U, S, V, info = run(lib, A, mode, block_cols_low=b_low, block_cols_work=b_work)
         g = metrics.gates(A, U, S, V, So)
         assert info["status"] == 0 and g["pass"], (mode, g, info)
+
+
+@pytest.mark.parametrize("shape", [(300, 300), (200, 97)])
+def test_parity_switch_method_2(lib, shape):
+    """The switch through the QR of the accumulated FP32 V (method 2) meets
+    the gates with the FP32 stage taken."""
+    m, n = shape
+    print(f"case switch_method=2 shape={shape}", flush=True)
+    A = known(m, n, seed=41 + m, e=10.0, kind="log")
+    Uo, So, Vo, _ = oracle.svd(A)
+    U, S, V, info = run(lib, A, "mixed", switch_method=2, branch=1)
+    g = metrics.gates(A, U, S, V, So)
+    assert info["status"] == 0 and info["branch_taken"] == 1 and g["pass"], (g, info)
+    U1, S1, V1, info1 = run(lib, A, "mixed", switch_method=1, branch=1)
+    assert np.max(np.abs(S - S1) / S1) < 1e-12
