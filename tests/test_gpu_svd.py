@@ -93,3 +93,40 @@ def test_parity_switch_method_2(lib, shape):
     assert info["status"] == 0 and info["branch_taken"] == 1 and g["pass"], (g, info)
     U1, S1, V1, info1 = run(lib, A, "mixed", switch_method=1, branch=1)
     assert np.max(np.abs(S - S1) / S1) < 1e-12
+
+
+def test_parity_tall_panel_fallback(lib):
+    """66000 x 32: the tall QR's panels span more than 256 row groups, so the
+    per-column panel launches (not the one-launch panel) factor them."""
+    print("case tall 66000x32", flush=True)
+    A = known(66000, 32, seed=7, e=6.0)
+    Uo, So, Vo, _ = oracle.svd(A)
+    for mode in ("mixed", "plain"):
+        U, S, V, info = run(lib, A, mode)
+        g = metrics.gates(A, U, S, V, So)
+        assert info["status"] == 0 and g["pass"], (mode, g, info)
+
+
+def test_large_n_pivot_step_fallback(lib):
+    """n = 4160 > 4096: the pivot pass takes the step-by-step kernels (the
+    one-launch pass holds at most 4096 rows per column in registers).  sigma
+    geometric in [1e-3, 1], so the constructed sigma are exact to ~1e-13 and
+    stand in for the oracle's; orthogonality and residual gates as always."""
+    import torch
+    n = 4160
+    print(f"case square n={n}", flush=True)
+    rng = np.random.default_rng(4160)
+    s = testmats.sigma_geometric(n, 3.0)
+    A = testmats.compose(testmats.haar(rng, n, n), s, testmats.haar(rng, n, n))
+    At = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    eye = torch.eye(n, dtype=torch.float64, device="cuda")
+    for mode in ("mixed", "plain"):
+        U, S, V, info = lib.svd(At, mode, branch=1 if mode == "mixed" else 0)
+        torch.cuda.synchronize()
+        assert info["status"] == 0, info
+        orth_u = torch.linalg.norm(U.t() @ U - eye).item()
+        orth_v = torch.linalg.norm(V.t() @ V - eye).item()
+        res = (torch.linalg.norm(At - (U * S) @ V.t()) / torch.linalg.norm(At)).item()
+        rel = np.max(np.abs(S.cpu().numpy() - s) / s)
+        assert orth_u <= 1e-13 * n and orth_v <= 1e-13 * n and res <= 1e-14 * n, (mode, orth_u, orth_v, res)
+        assert rel < 1e-11, (mode, rel)
