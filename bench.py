@@ -43,13 +43,20 @@ def algorithmic_flops(n: int, info: dict, mixed: bool) -> float:
     """Algorithmic flop count of one SVD (square n, U and V formed), from the
     stage formulas: pivot pass 4n^3/3, QR of A1 P 4n^3/3, LQ 4n^3/3, branch
     SYRK n^3, FP32 sweeps 4n^2(n-1) each, switch 4.7 n^3, FP64 sweeps with V
-    7n^2(n-1) each, back-transforms 4n^3."""
+    7n^2(n-1) each (without V 4n^2(n-1) each, then the triangular solve for
+    V_X n^3; its fallback adds X^T U_X 2n^3, a QR 4n^3/3, X Q 2n^3 and sweeps
+    with V), back-transforms 4n^3."""
     f = 4 * n ** 3 / 3 * 3 + 4 * n ** 3
     if mixed:
         f += n ** 3
         if info["branch_taken"] == 1:
             f += info["sweeps_low"] * 4 * n * n * (n - 1) + 4.7 * n ** 3
-    f += info["sweeps_work"] * 7 * n * n * (n - 1)
+    if info.get("v_method_taken", 0) >= 1:
+        f += info["sweeps_work"] * 4 * n * n * (n - 1) + n ** 3
+        if info["v_method_taken"] == 2:
+            f += 2 * n ** 3 + 4 * n ** 3 / 3 + 2 * n ** 3 + info["sweeps_vfix"] * 7 * n * n * (n - 1)
+    else:
+        f += info["sweeps_work"] * 7 * n * n * (n - 1)
     return f
 
 
@@ -236,6 +243,20 @@ def main() -> int:
         t_plain = (time.perf_counter() - t0) / args.steps
         print(f"[bench] plain {t_plain * 1e3:.1f} ms/SVD", file=sys.stderr, flush=True)
 
+    # context, not the metric: the plain path with the triangular-solve V of
+    # Section 3.4 as well (a stronger FP64 baseline than accumulation)
+    t_plain_vs, info_pv, g_plain_vs = None, None, None
+    if do_plain and do_mixed:
+        opts_pv = mp.default_opts(False, v_method=1)
+        mp.svd(A, "plain", workspace=ws, opts=opts_pv)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            Upv, Spv, Vpv, info_pv = mp.svd(A, "plain", workspace=ws, opts=opts_pv)
+        torch.cuda.synchronize()
+        t_plain_vs = (time.perf_counter() - t0) / args.steps
+        print(f"[bench] plain with solved V {t_plain_vs * 1e3:.1f} ms/SVD", file=sys.stderr, flush=True)
+
     # gates against the stored oracle sigma (when this size has one)
     s_ref, kappa = None, None
     if n == 4096:
@@ -249,6 +270,8 @@ def main() -> int:
             s_ref = None
     g_mixed = gates_gpu(A, Um, Sm, Vm, s_ref, kappa or 1.0) if do_mixed else None
     g_plain = gates_gpu(A, Up, Sp, Vp, s_ref, kappa or 1.0) if do_plain else None
+    if t_plain_vs is not None:
+        g_plain_vs = gates_gpu(A, Upv, Spv, Vpv, s_ref, kappa or 1.0)
 
     # per-class kernel clocks from one extra SVD of each kind (untimed, every
     # launch bracketed by HIP events on the library's stream)
@@ -333,7 +356,8 @@ def main() -> int:
             "mixed_ms": round(t_mixed * 1e3, 2), "mixed_svd_per_s": round(1.0 / t_mixed, 4),
             "mixed_gflops": round(flops / t_mixed / 1e9, 1),
             "mixed_info": {k: info[k] for k in ("status", "branch_taken", "sweeps_low", "sweeps_work",
-                                                "orth", "cond_r")},
+                                                "orth", "cond_r", "v_method_taken", "orth_vx",
+                                                "sweeps_vfix")},
             "mixed_off_trace": {"fp32": [float("%.3g" % x) for x in info["off_low"]],
                                 "fp64": [float("%.3g" % x) for x in info["off_work"]]},
             "mixed_stage_ms": [round(x, 2) for x in info["stage_ms"]],
@@ -347,6 +371,12 @@ def main() -> int:
             "plain_stage_ms": [round(x, 2) for x in info_p["stage_ms"]],
             "gates_plain": g_plain,
         })
+    if t_plain_vs is not None:
+        line["plain_solved_v"] = {
+            "ms": round(t_plain_vs * 1e3, 2), "ratio_to_mixed": round(t_plain_vs / t_mixed, 4),
+            "info": {k: info_pv[k] for k in ("status", "sweeps_work", "v_method_taken", "orth_vx")},
+            "stage_ms": [round(x, 2) for x in info_pv["stage_ms"]], "gates": g_plain_vs,
+        }
     line["roofline"] = roofline
     line["kernels"] = kernels
     line["kernel_clock_overhead_us"] = clock_overhead_us

@@ -103,6 +103,17 @@ typedef struct {
     int block_cols_work;   /* b of the FP64 stage (16 or 32), over block_cols;
                               0 = block_cols, else the tuning table, else
                               32 for n >= 512 and 16 below */
+    int v_method;          /* right singular vectors (Section 3.4):
+                              0: rotations accumulated through every FP64
+                              sweep (the plain path's default);
+                              1: FP64 sweeps without V, then V_X = X^{-1} Y by
+                              a triangular solve with X = L, accepted when
+                              max|V_X^T V_X - I| <= tol_vsolve, else V_X from
+                              the QR of X^T U_X followed by FP64 sweeps with
+                              accumulation (the mixed path's default) */
+    int diagnostics;       /* 1: also measure svd_info.orth_y (one more FP64
+                              Gram product); 0 (default): skip */
+    double tol_vsolve;     /* acceptance bound of v_method 1; 0 -> n 2^-50 */
 } svd_opts;
 
 /* Kernel classes reported by svd_info.kern_* (kernel_timing 1: SVD_K_QRCP
@@ -135,6 +146,14 @@ typedef struct {
     int kern_calls[SVD_K_NCLASS];  /* launches per class */
     double kern_bytes[SVD_K_NCLASS]; /* algorithmic HBM bytes of those launches */
     double kern_flops[SVD_K_NCLASS]; /* algorithmic flops of those launches */
+    int v_method_taken;    /* -1: V not wanted; 0: accumulated; 1: triangular
+                              solve accepted; 2: solve rejected, V_X from the
+                              QR of X^T U_X and further sweeps */
+    int sweeps_vfix;       /* FP64 sweeps of that fallback */
+    double orth_vx;        /* max|V_X^T V_X - I| of the solve, -1 if none */
+    double orth_y;         /* diagnostics: max|D^-1 Y^T Y D^-1 - I| of Y
+                              after the switch (D = column norms), -1 if not
+                              measured */
 } svd_info;
 
 /* Load the tuning table measured by the autotuner (not part of the paper's

@@ -46,6 +46,7 @@ class SvdOpts(ctypes.Structure):
         ("block_cols", ctypes.c_int), ("inner_sweeps", ctypes.c_int),
         ("kernel_timing", ctypes.c_int), ("low_stop_off", ctypes.c_double),
         ("block_cols_low", ctypes.c_int), ("block_cols_work", ctypes.c_int),
+        ("v_method", ctypes.c_int), ("diagnostics", ctypes.c_int), ("tol_vsolve", ctypes.c_double),
     ]
 
 
@@ -57,6 +58,8 @@ class SvdInfo(ctypes.Structure):
         ("off_low", ctypes.c_float * 32), ("off_work", ctypes.c_float * 32),
         ("kern_ms", ctypes.c_float * NCLASS), ("kern_calls", ctypes.c_int * NCLASS),
         ("kern_bytes", ctypes.c_double * NCLASS), ("kern_flops", ctypes.c_double * NCLASS),
+        ("v_method_taken", ctypes.c_int), ("sweeps_vfix", ctypes.c_int),
+        ("orth_vx", ctypes.c_double), ("orth_y", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -69,6 +72,8 @@ class SvdInfo(ctypes.Structure):
             "off_work": list(self.off_work)[:max(self.sweeps_work, 0)],
             "kern_ms": list(self.kern_ms), "kern_calls": list(self.kern_calls),
             "kern_bytes": list(self.kern_bytes), "kern_flops": list(self.kern_flops),
+            "v_method_taken": self.v_method_taken, "sweeps_vfix": self.sweeps_vfix,
+            "orth_vx": self.orth_vx, "orth_y": self.orth_y,
         }
 
 

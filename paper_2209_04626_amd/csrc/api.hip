@@ -42,6 +42,9 @@ extern "C" void svd_default_opts(svd_opts *o, int mixed) {
     o->low_stop_off = 0.0;
     o->block_cols_low = 0;
     o->block_cols_work = 0;
+    o->v_method = mixed ? 1 : 0;
+    o->diagnostics = 0;
+    o->tol_vsolve = 0.0;
 }
 
 namespace {
@@ -126,6 +129,7 @@ struct Small {
     int nonfinite, nzero, nsmall, pad0;
     double cond;
     float orth;
+    float orthv, orthy;
     int pad1;
 };
 
@@ -187,9 +191,13 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     if (o.want_v && ldv < (n > 1 ? n : 1)) return -9;
     if (n > 8192) return -2;
     if (o.pivot_precision != 32 && o.pivot_precision != 64) return -12;
+    if (o.v_method != 0 && o.v_method != 1) return -12;
     if (info) {
         memset(info, 0, sizeof(*info));
         info->orth = -1.0;
+        info->orth_vx = -1.0;
+        info->orth_y = -1.0;
+        info->v_method_taken = o.want_v ? 0 : -1;
     }
     if (n == 0) return 0;
     mpj::g_last_error[0] = 0;
@@ -344,14 +352,59 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         tm.mark(6);
     }
     MPJ_CHECK(hipGetLastError());
+    double orth_y = -1.0;
+    if (o.diagnostics) {
+        // how far the columns of Y are from orthogonal when the FP64 sweeps start
+        normalize_cols64(s, n, n, Y, N, Ulow, N);
+        gemm_orth_maxdev64(s, n, Ulow, N, &sm->orthy);
+        if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
+        orth_y = hs.orthy;
+    }
 
-    // a8: FP64 one-sided Jacobi (Algorithm 1) with V accumulated from Q
+    // a8: FP64 one-sided Jacobi (Algorithm 1); V_X accumulated from Q
+    // (v_method 0) or formed afterwards (v_method 1, Section 3.4)
+    const bool vsolve = o.want_v && o.v_method == 1;
     int conv_work = 0;
     jacobi_carve(jw, w + L.off_jac, N, L.b64, (int)sizeof(double));
     jw.off_hist = off_work;
-    const int sweeps_work = jacobi_sweeps<double>(s, N, L.b64, Y, o.want_v ? Vacc : nullptr, eps_work,
-                                                  o.maxsweep_work, inner, jw, &conv_work);
+    const int sweeps_work = jacobi_sweeps<double>(s, N, L.b64, Y, (o.want_v && !vsolve) ? Vacc : nullptr,
+                                                  eps_work, o.maxsweep_work, inner, jw, &conv_work);
     if (sweeps_work < 0) return SVD_ERR_HIP;
+    int v_taken = o.want_v ? 0 : -1, sweeps_vfix = 0;
+    double orth_vx = -1.0;
+    if (vsolve) {
+        // Y = X V_X = U_X Sigma, so V_X = X^{-1} Y with X = L lower triangular
+        MPJ_CHECK(hipMemcpyAsync(Vacc, Y, (size_t)N * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        trsm_lower(s, n, n, X, N, Vacc, N, jw.kc);
+        gemm_orth_maxdev64(s, n, Vacc, N, &sm->orthv);
+        if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
+        orth_vx = hs.orthv;
+        // default: n 2^-50 = 8 n u, the size of the rounding error that the
+        // accumulated rotations of a few sweeps leave in V_X
+        const double tol_v = o.tol_vsolve > 0 ? o.tol_vsolve : n * ldexp(1.0, -50);
+        if (orth_vx <= tol_v) {
+            v_taken = 1;
+        } else {
+            // not accurate enough: V_X from the QR of X^T U_X (U_X = the
+            // normalised columns of Y), then sweeps with accumulation on X Q
+            normalize_cols64(s, n, n, Y, N, Ulow, N);
+            gemm<double>(s, true, false, n, n, n, 1.0, X, N, Ulow, N, 0.0, Bm, n, q.split,
+                         q.split_elems, jw.kc);
+            qr_factor(s, n, n, Bm, n, tau3, T3, q);
+            set_identity(s, N, Vacc, N);
+            qr_apply_left(s, false, n, n, Bm, n, T3, n, Vacc, N, q);
+            zero_pad_fill(s, N, N, Y, N);
+            gemm<double>(s, false, false, n, n, n, 1.0, X, N, Vacc, N, 0.0, Y, N, q.split,
+                         q.split_elems, jw.kc);
+            int conv_fix = 0;
+            jw.off_hist = nullptr;
+            sweeps_vfix = jacobi_sweeps<double>(s, N, L.b64, Y, Vacc, eps_work, o.maxsweep_work,
+                                                inner, jw, &conv_fix);
+            if (sweeps_vfix < 0) return SVD_ERR_HIP;
+            conv_work = conv_work && conv_fix;
+            v_taken = 2;
+        }
+    }
 
     // a9: sigma, U_X, V_X sorted; U = Q0 Q1 U_X, V = P Q2^T V_X
     finalize_sort(s, n, N, Y, Vacc, sig, rank, UX, VX, S, &sm->nzero, o.want_v != 0);
@@ -385,6 +438,10 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         info->n_small = nsmall;
         info->orth = orth;
         info->cond_r = mixed ? cond : 0.0;
+        info->v_method_taken = v_taken;
+        info->sweeps_vfix = sweeps_vfix;
+        info->orth_vx = orth_vx;
+        info->orth_y = orth_y;
         int st = SVD_OK;
         if (!conv_work) st = SVD_WARN_NOCONV;
         if (hs.nzero) st = SVD_WARN_RANK_DEFICIENT;

@@ -120,7 +120,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(
                     const int gi = i0 + wm * 32 + ti * 16 + mfma_row<T>(lane, r);
                     const int gj = j0 + wn * 16 * TJ + tj * 16 + lane % 16;
                     if (gi < M && gj < N) {
-                        const float d = fabsf((float)(alpha * acc[ti][tj][r]) - (gi == gj ? 1.f : 0.f));
+                        const T dv = alpha * acc[ti][tj][r] - (gi == gj ? T(1) : T(0));
+                        const float d = (float)(dv < T(0) ? -dv : dv);
                         dmax = fmaxf(dmax, d);
                     }
                 }
@@ -252,6 +253,16 @@ void gemm_orth_maxdev(hipStream_t s, int n, const float *X, int ldx, float *maxd
     hipLaunchKernelGGL((gemm_kernel<float, true, false, EPI_MAXDEV, 64>), dim3(t, t, 1), dim3(256), 0, s,
                        n, n, n, 1.0f, X, ldx, X, ldx, 0.0f, (float *)nullptr, n, cdiv(n, GBK) * GBK,
                        (float *)nullptr, maxdev);
+}
+
+// The same for FP64 columns (the deviation is formed in FP64, its maximum
+// kept in FP32).
+void gemm_orth_maxdev64(hipStream_t s, int n, const double *X, int ldx, float *maxdev) {
+    if (n <= 0) return;
+    const int t = cdiv(n, 64);
+    hipLaunchKernelGGL((gemm_kernel<double, true, false, EPI_MAXDEV, 64>), dim3(t, t, 1), dim3(256), 0,
+                       s, n, n, n, 1.0, X, ldx, X, ldx, 0.0, (double *)nullptr, n, cdiv(n, GBK) * GBK,
+                       (double *)nullptr, maxdev);
 }
 
 } // namespace mpj

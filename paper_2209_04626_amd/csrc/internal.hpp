@@ -79,6 +79,11 @@ void gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, T alpha,
 // maxdev = max_{i,j < n} |(X^T X)_ij - delta_ij| for the n x n FP32 matrix
 // X (ld ldx), accumulated into *maxdev (float bits, caller zeroes it).
 void gemm_orth_maxdev(hipStream_t s, int n, const float *X, int ldx, float *maxdev);
+void gemm_orth_maxdev64(hipStream_t s, int n, const double *X, int ldx, float *maxdev);
+void trsm_lower(hipStream_t s, int n, int nrhs, const double *L, int ldl, double *B, int ldb,
+                KernelClock *kc);
+void normalize_cols64(hipStream_t s, int rows, int cols, const double *Y, int ldy, double *U,
+                      int ldu);
 
 // ---------------------------------------------------------------- QR
 constexpr int QR_NB = 32;    // panel width of the blocked Householder QR

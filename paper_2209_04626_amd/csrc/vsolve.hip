@@ -1,0 +1,92 @@
+// Right singular vectors without accumulated rotations (Section 3.4).
+//
+// After the FP64 sweeps have run on Y without V, Y = X V_X holds U_X Sigma,
+// so V_X = X^{-1} Y: one triangular solve with the lower triangular X = L of
+// the LQ step.  Writing L = D_r Z_r (row scaling D_r), the solve's error
+// depends on the conditioning of Z_r, not of L (Section 3.1), which the
+// QRCP + LQ preconditioning keeps small.  The caller checks the result's
+// orthogonality and falls back to the QR of X^T U_X followed by sweeps with
+// accumulation when it is not good enough.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace mpj {
+
+constexpr int TRSM_NB = 64;   // rows per diagonal block
+
+// B(r0 : r0 + kb, c) <- L_kk^{-1} B(r0 : r0 + kb, c) for the kb x kb lower
+// triangular diagonal block L_kk (kb <= TB): one lane per right-hand side
+// column, the column in registers, the block in LDS (read as broadcasts).
+// Column-oriented forward substitution: after z_l is final, every later z_i
+// takes z_i - L_il z_l, so each lane has TB - l independent updates in flight.
+template <int TB>
+__global__ __launch_bounds__(64) void k_trsm_diag(int kb, int nrhs, const double *L, int ldl,
+                                                  double *B, int ldb) {
+    __shared__ double Ls[TB][TB];
+    const int t = threadIdx.x;
+    for (int l = 0; l < TB; ++l)
+        for (int i = t; i < TB; i += 64)
+            Ls[i][l] = (i < kb && l < kb && l <= i) ? L[(size_t)l * ldl + i] : 0.0;
+    __syncthreads();
+    const int c = blockIdx.x * 64 + t;
+    if (c >= nrhs) return;
+    double *b = B + (size_t)c * ldb;
+    double z[TB];
+#pragma unroll
+    for (int i = 0; i < TB; ++i) z[i] = i < kb ? b[i] : 0.0;
+#pragma unroll
+    for (int l = 0; l < TB; ++l) {
+        if (l < kb) {
+            z[l] = z[l] / Ls[l][l];
+#pragma unroll
+            for (int i = l + 1; i < TB; ++i) z[i] = fma(-Ls[i][l], z[l], z[i]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < TB; ++i)
+        if (i < kb) b[i] = z[i];
+}
+
+// B (n x nrhs, ld ldb) <- L^{-1} B for lower triangular L (n x n, ld ldl):
+// blocked right-looking forward substitution, a diagonal-block solve and an
+// FP64 matrix-core update of the rows below per block of TRSM_NB rows.
+void trsm_lower(hipStream_t s, int n, int nrhs, const double *L, int ldl, double *B, int ldb,
+                KernelClock *kc) {
+    if (n <= 0 || nrhs <= 0) return;
+    for (int r0 = 0; r0 < n; r0 += TRSM_NB) {
+        const int kb = n - r0 < TRSM_NB ? n - r0 : TRSM_NB;
+        hipLaunchKernelGGL((k_trsm_diag<TRSM_NB>), dim3(cdiv(nrhs, 64)), dim3(64), 0, s, kb, nrhs,
+                           L + (size_t)r0 * ldl + r0, ldl, B + r0, ldb);
+        const int r1 = r0 + kb;
+        if (r1 < n)
+            gemm<double>(s, false, false, n - r1, nrhs, kb, -1.0, L + (size_t)r0 * ldl + r1, ldl,
+                         B + r0, ldb, 1.0, B + r1, ldb, nullptr, 0, kc);
+    }
+}
+
+// U(:, j) = Y(:, j) / ||Y(:, j)|| in FP64 (zero columns stay zero).
+__global__ __launch_bounds__(256) void k_norm_cols64(int rows, int cols, const double *Y, int ldy,
+                                                     double *U, int ldu) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= cols) return;
+    double s = 0.0;
+    for (int i = lane; i < rows; i += 64) {
+        const double v = Y[(size_t)j * ldy + i];
+        s = fma(v, v, s);
+    }
+    s = wave_sum(s);
+    const double d = sqrt(s);
+    for (int i = lane; i < rows; i += 64) {
+        const double v = Y[(size_t)j * ldy + i];
+        U[(size_t)j * ldu + i] = d > 0.0 ? v / d : 0.0;
+    }
+}
+
+void normalize_cols64(hipStream_t s, int rows, int cols, const double *Y, int ldy, double *U,
+                      int ldu) {
+    hipLaunchKernelGGL(k_norm_cols64, dim3(cdiv(cols, 4)), dim3(256), 0, s, rows, cols, Y, ldy, U,
+                       ldu);
+}
+
+} // namespace mpj

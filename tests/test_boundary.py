@@ -33,6 +33,10 @@ def test_default_options_are_the_papers():
     assert o.tol_alg == 1e-2 and o.tol_orth == 1e-5 and o.tol_cond_coef == 1.5
     assert o.pivot_precision == 32 and o.want_u == 1 and o.want_v == 1
     assert mp.default_opts(mixed=False).pivot_precision == 64
+    # right singular vectors: Section 3.4's solve in the mixed path,
+    # accumulated rotations in the plain one
+    assert o.v_method == 1 and mp.default_opts(mixed=False).v_method == 0
+    assert o.tol_vsolve == 0.0 and o.diagnostics == 0
 
 
 def test_workspace_size_monotone_and_invalid():

@@ -130,3 +130,78 @@ def test_large_n_pivot_step_fallback(lib):
         rel = np.max(np.abs(S.cpu().numpy() - s) / s)
         assert orth_u <= 1e-13 * n and orth_v <= 1e-13 * n and res <= 1e-14 * n, (mode, orth_u, orth_v, res)
         assert rel < 1e-11, (mode, rel)
+
+
+def graded(m, n, seed, e=8.0, d=4.0):
+    """A = B diag(10^w), w ~ U(-d, 0): badly scaled columns over a B with
+    log-uniform sigma (the A = B D family)."""
+    rng = np.random.default_rng(seed)
+    B = testmats.compose(testmats.haar(rng, m, n), testmats.sigma_log_uniform(rng, n, e),
+                         testmats.haar(rng, n, n))
+    return B * (10.0 ** rng.uniform(-d, 0.0, n))[None, :]
+
+
+@pytest.mark.parametrize("mode", ["plain", "mixed"])
+@pytest.mark.parametrize("case", ["square", "tall", "graded"])
+def test_parity_v_solve(lib, mode, case):
+    """V_X = X^{-1} Y by the triangular solve (Section 3.4) after FP64 sweeps
+    without V: accepted on these preconditioned inputs and within the gates;
+    sigma agree with the accumulated path's."""
+    print(f"case v_method=1 mode={mode} {case}", flush=True)
+    if case == "square":
+        A = known(300, 300, seed=77, e=10.0, kind="log")
+    elif case == "tall":
+        A = known(200, 97, seed=78, e=10.0, kind="log")
+    else:
+        A = graded(260, 260, seed=79)
+    Uo, So, Vo, _ = oracle.svd(A)
+    U, S, V, info = run(lib, A, mode, v_method=1)
+    g = metrics.gates(A, U, S, V, So)
+    assert info["status"] == 0 and g["pass"], (g, info)
+    assert info["v_method_taken"] == 1 and 0.0 <= info["orth_vx"] <= A.shape[1] * 2.0 ** -50, info
+    U0, S0, V0, info0 = run(lib, A, mode, v_method=0)
+    assert info0["v_method_taken"] == 0 and info0["orth_vx"] == -1.0
+    assert np.max(np.abs(S - S0) / S0) < 1e-12
+
+
+@pytest.mark.parametrize("mode", ["plain", "mixed"])
+def test_v_solve_fallback(lib, mode):
+    """A bound no solve can meet forces the other route of Section 3.4: V_X
+    from the QR of X^T U_X, then FP64 sweeps with accumulation (one or two,
+    the start being accurate)."""
+    print(f"case v_method=1 fallback mode={mode}", flush=True)
+    A = known(300, 300, seed=80, e=10.0, kind="log")
+    Uo, So, Vo, _ = oracle.svd(A)
+    U, S, V, info = run(lib, A, mode, v_method=1, tol_vsolve=1e-300)
+    g = metrics.gates(A, U, S, V, So)
+    assert info["status"] == 0 and g["pass"], (g, info)
+    assert info["v_method_taken"] == 2 and 1 <= info["sweeps_vfix"] <= 3, info
+
+
+def test_v_not_wanted(lib):
+    """want_v = 0: no V work and no V output is touched."""
+    import torch
+    A = known(120, 90, seed=81)
+    At = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    U, S, V, info = lib.svd(At, "mixed", want_v=0)
+    torch.cuda.synchronize()
+    So = oracle.svd(A)[1]
+    assert info["v_method_taken"] == -1 and info["orth_vx"] == -1.0
+    e = metrics.e_sigma(S.cpu().numpy(), So, metrics.kappa_s(A))
+    assert e <= 1e-13, e
+    assert metrics.orth_err(U.cpu().numpy()) <= 1e-13 * A.shape[1]
+
+
+@pytest.mark.parametrize("method", [1, 2])
+def test_orthogonality_of_y_after_switch(lib, method):
+    """Diagnostics: how orthogonal Y is when the FP64 sweeps start, for both
+    switch methods (Section 6 compares them).  Either way the FP32 stage has
+    left its columns orthogonal to a few units of FP32 rounding, far from the
+    O(1) of the unswitched X."""
+    print(f"case orth_y switch_method={method}", flush=True)
+    A = known(256, 256, seed=82, e=10.0, kind="log")
+    U, S, V, info = run(lib, A, "mixed", branch=1, switch_method=method, diagnostics=1)
+    assert info["status"] == 0 and info["branch_taken"] == 1
+    assert 0.0 < info["orth_y"] < 1e-3, info
+    U, S, V, info_x = run(lib, A, "plain", diagnostics=1)
+    assert info_x["orth_y"] > 100 * info["orth_y"], (info_x, info)   # X itself
