@@ -79,8 +79,11 @@ typedef struct {
     int switch_method;     /* 1: Q = qr(X^T U_low), the switch of Algorithm 4
                               (Section 3.3, default); 2: Q = qr(fp64(V_low))
                               with V_low accumulated in the FP32 stage (the
-                              switch of Algorithm 3, compared in Section 6);
-                              the workspace query depends on it */
+                              switch of Algorithm 3, compared in Section 6),
+                              Y = X Q; 3: Algorithm 3 itself, Q =
+                              qr(P Q2^T fp64(V_low)) and the FP64 sweeps on
+                              Y = A1 Q (A1 = A, or R1 when m > n) with V
+                              accumulated; the workspace query depends on it */
     int pivot_precision;   /* 32 (Algorithm 5) or 64 (plain xGEQP3) */
     int sign_normalize;    /* 1: make the largest |V(k, i)| of each column
                               positive (first k on ties), negating U(:, i)
@@ -114,6 +117,12 @@ typedef struct {
     int diagnostics;       /* 1: also measure svd_info.orth_y (one more FP64
                               Gram product); 0 (default): skip */
     double tol_vsolve;     /* acceptance bound of v_method 1; 0 -> n 2^-50 */
+    int inner_pairs;       /* pairs rotated in a block pair's inner solve:
+                              0 (default): all pairs of its 2b columns in the
+                              first round of a sweep, then only the b^2 pairs
+                              between the two blocks (each pair of columns is
+                              rotated about once per sweep, as in Algorithm 1);
+                              1: all pairs in every round */
 } svd_opts;
 
 /* Kernel classes reported by svd_info.kern_* (kernel_timing 1: SVD_K_QRCP

@@ -47,6 +47,7 @@ class SvdOpts(ctypes.Structure):
         ("kernel_timing", ctypes.c_int), ("low_stop_off", ctypes.c_double),
         ("block_cols_low", ctypes.c_int), ("block_cols_work", ctypes.c_int),
         ("v_method", ctypes.c_int), ("diagnostics", ctypes.c_int), ("tol_vsolve", ctypes.c_double),
+        ("inner_pairs", ctypes.c_int),
     ]
 
 

@@ -45,6 +45,7 @@ extern "C" void svd_default_opts(svd_opts *o, int mixed) {
     o->v_method = mixed ? 1 : 0;
     o->diagnostics = 0;
     o->tol_vsolve = 0.0;
+    o->inner_pairs = 0;
 }
 
 namespace {
@@ -102,7 +103,7 @@ Layout layout(int m, int n, const svd_opts &o) {
     L.off_y = take(NN * d);
     L.off_vacc = take(NN * d);
     L.off_y32 = take(NN * f);
-    L.off_v32 = take(o.switch_method == 2 ? NN * f : 0);   // V_low for switch method 2
+    L.off_v32 = take(o.switch_method >= 2 ? NN * f : 0);   // V_low for switch methods 2 and 3
     L.off_xt = take(nn * f);
     L.off_ulow = take(NN * d);
     L.off_bm = take(nn * d);
@@ -192,6 +193,8 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     if (n > 8192) return -2;
     if (o.pivot_precision != 32 && o.pivot_precision != 64) return -12;
     if (o.v_method != 0 && o.v_method != 1) return -12;
+    if (o.switch_method < 1 || o.switch_method > 3) return -12;
+    if (o.inner_pairs != 0 && o.inner_pairs != 1) return -12;
     if (info) {
         memset(info, 0, sizeof(*info));
         info->orth = -1.0;
@@ -227,6 +230,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     int hflag[3] = {0, 0, 0};
     jw.hflag = hflag;
     jw.n_real = n;
+    jw.cross_pairs = o.inner_pairs == 0 ? 1 : 0;
     KernelClock kclock;
     kclock.on = o.kernel_timing != 0;
     jw.kc = o.kernel_timing >= 2 ? &kclock : nullptr;
@@ -314,8 +318,8 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     int sweeps_low = 0, conv_low = 1;
     if (branch == SVD_BRANCH_LOW) {
         // a6: FP32 one-sided Jacobi on low(X) (Section 3.2); V_low is only
-        // accumulated for switch method 2
-        const bool vlow = o.switch_method == 2;
+        // accumulated for switch methods 2 and 3
+        const bool vlow = o.switch_method >= 2;
         float *V32 = vlow ? (float *)(w + L.off_v32) : nullptr;
         convert_f64_f32(s, N, N, X, N, Y32, N);
         if (vlow) {
@@ -331,8 +335,14 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         if (sweeps_low < 0) return SVD_ERR_HIP;
         tm.mark(5);
         // a7: switch (Section 3.3).  Method 1 (Algorithm 4): B = X^T U_low;
-        // method 2: B = fp64(V_low).  Then B = Q R2, Y = X Q.
-        if (vlow) {
+        // method 2: B = fp64(V_low); then B = Q R2, Y = X Q.  Method 3
+        // (Algorithm 3): B = V_s = P Q2^T fp64(V_low), the right vectors of
+        // A itself, and Y = A1 Q with no preconditioning of the FP64 stage.
+        if (o.switch_method == 3) {
+            convert_f32_f64(s, n, n, V32, N, UX, n);
+            qr_apply_left(s, false, n, n, Rt, n, T2, n, UX, n, q);
+            permute_rows_v(s, n, UX, n, piv, Bm, n);
+        } else if (vlow) {
             convert_f32_f64(s, n, n, V32, N, Bm, n);
         } else {
             normalize_f32_to_f64(s, N, N, Y32, N, Ulow, N);
@@ -343,8 +353,9 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         set_identity(s, N, Vacc, N);
         qr_apply_left(s, false, n, n, Bm, n, T3, n, Vacc, N, q);
         zero_pad_fill(s, N, N, Y, N);
-        gemm<double>(s, false, false, n, n, n, 1.0, X, N, Vacc, N, 0.0, Y, N, q.split,
-                     q.split_elems, jw.kc);
+        gemm<double>(s, false, false, n, n, n, 1.0, o.switch_method == 3 ? A1 : X,
+                     o.switch_method == 3 ? n : N, Vacc, N, 0.0, Y, N, q.split, q.split_elems,
+                     jw.kc);
         tm.mark(6);
     } else {
         MPJ_CHECK(hipMemcpyAsync(Y, X, (size_t)N * N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -363,7 +374,10 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
 
     // a8: FP64 one-sided Jacobi (Algorithm 1); V_X accumulated from Q
     // (v_method 0) or formed afterwards (v_method 1, Section 3.4)
-    const bool vsolve = o.want_v && o.v_method == 1;
+    // Algorithm 3's Y = A1 Q has no triangular factor to solve with: V is
+    // accumulated there
+    const bool alg3 = branch == SVD_BRANCH_LOW && o.switch_method == 3;
+    const bool vsolve = o.want_v && o.v_method == 1 && !alg3;
     int conv_work = 0;
     jacobi_carve(jw, w + L.off_jac, N, L.b64, (int)sizeof(double));
     jw.off_hist = off_work;
@@ -409,13 +423,18 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     // a9: sigma, U_X, V_X sorted; U = Q0 Q1 U_X, V = P Q2^T V_X
     finalize_sort(s, n, N, Y, Vacc, sig, rank, UX, VX, S, &sm->nzero, o.want_v != 0);
     if (o.want_u) {
-        qr_apply_left(s, false, n, n, A1P, n, T1, n, UX, n, q);
+        if (!alg3) qr_apply_left(s, false, n, n, A1P, n, T1, n, UX, n, q);
         place_u(s, m, n, UX, n, U, ldu);
         if (m > n) qr_apply_left(s, false, m, n, Atall, m, T0, n, U, ldu, q);
     }
     if (o.want_v) {
-        qr_apply_left(s, false, n, n, Rt, n, T2, n, VX, n, q);
-        permute_rows_v(s, n, VX, n, piv, V, ldv);
+        if (!alg3) {
+            qr_apply_left(s, false, n, n, Rt, n, T2, n, VX, n, q);
+            permute_rows_v(s, n, VX, n, piv, V, ldv);
+        } else {
+            MPJ_CHECK(hipMemcpy2DAsync(V, (size_t)ldv * sizeof(double), VX, (size_t)n * sizeof(double),
+                                       (size_t)n * sizeof(double), n, hipMemcpyDeviceToDevice, s));
+        }
         if (o.sign_normalize) sign_normalize(s, m, n, U, ldu, o.want_u != 0, V, ldv);
     }
     MPJ_CHECK(hipGetLastError());

@@ -142,6 +142,8 @@ struct JacobiWork {
     KernelClock *kc = nullptr;
     float *off_hist = nullptr;  // per-sweep max relative off-diagonal (host, 32)
     double stop_off = 0.0;      // also stop once a sweep starts with off <= this
+    int cross_pairs = 0;        // 1: after a sweep's first round, rotate only the
+                                // pairs between the two blocks of each block pair
 };
 size_t jacobi_scratch_bytes(int N, int b, int elem);
 void jacobi_carve(JacobiWork &j, char *base, int N, int b, int elem);

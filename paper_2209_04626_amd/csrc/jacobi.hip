@@ -177,7 +177,10 @@ __device__ __forceinline__ bool jac_rot_test(double al, double be, double ga, do
 // rotation angle and threshold test is evaluated in FP64.
 //
 // Round rd rotates the column pairs of the round-robin schedule (pair k joins
-// (rd + k) mod (2b-1) and (rd - k) mod (2b-1); pair 0 joins rd and 2b-1).
+// (rd + k) mod (2b-1) and (rd - k) mod (2b-1); pair 0 joins rd and 2b-1);
+// 2b - 1 rounds reach every pair of the 2b columns.  With cross set, only the
+// b^2 pairs between the two blocks are rotated: round rd joins column k of
+// the first block with column (k + rd) mod b of the second, b rounds.
 // Thread (a, g) computes the rotation of pair a from the current G and owns
 // the 2x2 groups {p_a, q_a} x {p_c, q_c} of G for its GPT pairs c (the groups
 // tile G) and RPT rows of W's column pair a.  Pair c's rotation comes from the
@@ -187,7 +190,7 @@ __device__ __forceinline__ bool jac_rot_test(double al, double be, double ga, do
 template <typename T, int B2, int NT>
 __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict__ Gp,
                                                 T *__restrict__ Wm, int *skip, int *flag,
-                                                double eps, int max_inner) {
+                                                double eps, int max_inner, int cross) {
     constexpr int LD = B2 + 1;
     constexpr int H = B2 / 2;
     constexpr int M = B2 - 1;
@@ -292,7 +295,7 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
         if (uok[k] && p < q) {
             const double g = (double)G[0][p * LD + q];
             const double pq = (double)G[0][p * LD + p] * (double)G[0][q * LD + q];
-            if (g * g > eps2 * pq) need = 1;
+            if (g * g > eps2 * pq && (!cross || (p < H && q >= H))) need = 1;
             if (pq > 0.0) offmax = fmaxf(offmax, (float)(fabs(g) / sqrt(pq)));
         }
     }
@@ -311,19 +314,20 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
     const bool own_diag = a / GPT == cg;      // this thread holds group (a, a)
     const int kd = a % GPT;
     // schedule positions of pair a and of the thread's pairs c at round 0
-    int ax = a, ay = a == 0 ? M : M - a;
+    int ax = a, ay = cross ? H + a : (a == 0 ? M : M - a);
     int cx[GPT], cy[GPT];
 #pragma unroll
     for (int k = 0; k < GPT; ++k) {
         const int c = c0 + k;
         cx[k] = c;
-        cy[k] = c == 0 ? M : M - c;
+        cy[k] = cross ? H + c : (c == 0 ? M : M - c);
     }
+    const int nround = cross ? H : M;
     float smax = 0.f;   // largest |sin| of the rotations of pair a (owner only)
     int cur = 0;
     for (int sw = 0; sw < max_inner; ++sw) {
         int rotated = 0;
-        for (int rd = 0; rd < M; ++rd) {
+        for (int rd = 0; rd < nround; ++rd) {
             const T *g = G[cur];
             T *gn = G[cur ^ 1];
             const int p = min(ax, ay), q = max(ax, ay);
@@ -376,14 +380,21 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
             }
             __syncthreads();
             cur ^= 1;
-            // next round: every schedule position advances by one (mod 2b-1),
-            // except the fixed partner 2b-1 of pair 0
-            ax = ax + 1 == M ? 0 : ax + 1;
-            if (a != 0) ay = ay + 1 == M ? 0 : ay + 1;
+            if (cross) {
+                // next round: the second block's partner advances by one (mod b)
+                ay = ay + 1 == B2 ? H : ay + 1;
 #pragma unroll
-            for (int k = 0; k < GPT; ++k) {
-                cx[k] = cx[k] + 1 == M ? 0 : cx[k] + 1;
-                if (c0 + k != 0) cy[k] = cy[k] + 1 == M ? 0 : cy[k] + 1;
+                for (int k = 0; k < GPT; ++k) cy[k] = cy[k] + 1 == B2 ? H : cy[k] + 1;
+            } else {
+                // next round: every schedule position advances by one (mod
+                // 2b-1), except the fixed partner 2b-1 of pair 0
+                ax = ax + 1 == M ? 0 : ax + 1;
+                if (a != 0) ay = ay + 1 == M ? 0 : ay + 1;
+#pragma unroll
+                for (int k = 0; k < GPT; ++k) {
+                    cx[k] = cx[k] + 1 == M ? 0 : cx[k] + 1;
+                    if (c0 + k != 0) cy[k] = cy[k] + 1 == M ? 0 : cy[k] + 1;
+                }
             }
         }
         // positions after a full cycle are back where they started
@@ -553,7 +564,8 @@ static int sweeps_impl(hipStream_t s, int N, T *Y, T *V, double eps, int maxswee
                                N, (T *)jw.gram, nchG);
             if (jw.kc) { jw.kc->end(s); jw.kc->begin(s, kbase + 1, 0.0, inner_flops); }
             hipLaunchKernelGGL((jac_inner<T, B2, INNER_NT>), dim3(npairs), dim3(INNER_NT), 0, s, nchG,
-                               (const T *)jw.gram, (T *)jw.wmat, jw.skip, jw.flag, eps, max_inner);
+                               (const T *)jw.gram, (T *)jw.wmat, jw.skip, jw.flag, eps, max_inner,
+                               (jw.cross_pairs && r > 0) ? 1 : 0);
             if (jw.kc) { jw.kc->end(s); jw.kc->begin(s, kbase + 2, upd_bytes, upd_flops); }
             hipLaunchKernelGGL((jac_update<T, B2>), dim3(npairs, nch + nchV), dim3(JR_NT), 0, s, N,
                                nblk, r, Y, N, V, N, nch, (const T *)jw.wmat, jw.skip);

@@ -36,7 +36,7 @@ def test_default_options_are_the_papers():
     # right singular vectors: Section 3.4's solve in the mixed path,
     # accumulated rotations in the plain one
     assert o.v_method == 1 and mp.default_opts(mixed=False).v_method == 0
-    assert o.tol_vsolve == 0.0 and o.diagnostics == 0
+    assert o.tol_vsolve == 0.0 and o.diagnostics == 0 and o.inner_pairs == 0
 
 
 def test_workspace_size_monotone_and_invalid():

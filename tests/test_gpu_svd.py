@@ -80,6 +80,20 @@ def test_parity_block_widths(lib, b_low, b_work):
         assert info["status"] == 0 and g["pass"], (mode, g, info)
 
 
+@pytest.mark.parametrize("mode", ["plain", "mixed"])
+@pytest.mark.parametrize("inner_pairs", [0, 1])
+def test_parity_inner_pairs(lib, mode, inner_pairs):
+    """Both inner schedules of a block pair (all 2b columns every round, or
+    only the pairs between the two blocks after a sweep's first round) meet
+    the gates on a ragged size."""
+    print(f"case inner_pairs={inner_pairs} mode={mode}", flush=True)
+    A = known(330, 330, seed=91, e=10.0, kind="log")
+    Uo, So, Vo, _ = oracle.svd(A)
+    U, S, V, info = run(lib, A, mode, inner_pairs=inner_pairs)
+    g = metrics.gates(A, U, S, V, So)
+    assert info["status"] == 0 and g["pass"], (g, info)
+
+
 @pytest.mark.parametrize("shape", [(300, 300), (200, 97)])
 def test_parity_switch_method_2(lib, shape):
     """The switch through the QR of the accumulated FP32 V (method 2) meets
@@ -93,6 +107,23 @@ def test_parity_switch_method_2(lib, shape):
     assert info["status"] == 0 and info["branch_taken"] == 1 and g["pass"], (g, info)
     U1, S1, V1, info1 = run(lib, A, "mixed", switch_method=1, branch=1)
     assert np.max(np.abs(S - S1) / S1) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(300, 300), (200, 97)])
+def test_parity_algorithm_3(lib, shape):
+    """Algorithm 3 (switch_method = 3): the FP64 sweeps run on A1 Q with Q
+    from the FP32 right vectors, V accumulated; it meets the gates, and its
+    refinement takes at least as many sweeps as Algorithm 4's (Section 6)."""
+    m, n = shape
+    print(f"case switch_method=3 shape={shape}", flush=True)
+    A = known(m, n, seed=43 + m, e=10.0, kind="log")
+    Uo, So, Vo, _ = oracle.svd(A)
+    U, S, V, info = run(lib, A, "mixed", switch_method=3, branch=1, diagnostics=1)
+    g = metrics.gates(A, U, S, V, So)
+    assert info["status"] == 0 and info["branch_taken"] == 1 and g["pass"], (g, info)
+    assert info["v_method_taken"] == 0, info
+    U1, S1, V1, info1 = run(lib, A, "mixed", switch_method=1, branch=1, diagnostics=1)
+    assert info["sweeps_work"] >= info1["sweeps_work"], (info["sweeps_work"], info1["sweeps_work"])
 
 
 def test_parity_tall_panel_fallback(lib):
