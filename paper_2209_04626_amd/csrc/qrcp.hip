@@ -336,8 +336,13 @@ __global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__res
                                                      unsigned long long *__restrict__ keys,
                                                      int *err, int *__restrict__ piv) {
     typedef float T;
-    constexpr int NP = 64 * RPL;          // padded column length (rows >= n stay zero)
-    __shared__ T pc[NP];
+    // The step's pivot column in LDS, lane-major: row lane + 64 r of the
+    // column sits at pc[lane * PL + r], so a lane reads the entries of its
+    // own rows four at a time (128-bit reads; the row pad of 4 entries puts
+    // the lanes of each read on distinct banks).
+    constexpr int NP = 64 * RPL;          // candidate slot length in cbuf (rows >= n unused)
+    constexpr int PL = RPL + 4;
+    __shared__ __align__(16) T pc[64 * PL];
     __shared__ unsigned long long rk[QP_W];
     __shared__ int bad;
     const int nwg = gridDim.x;
@@ -356,7 +361,8 @@ __global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__res
         }
         nv = live ? tsqrt(wave_sum(ns)) : T(-1);
     }
-    for (int i = t; i < NP; i += QP_NT) pc[i] = T(0);
+    for (int i = t; i < 64 * PL; i += QP_NT) pc[i] = T(0);
+    auto pidx = [](int i) { return (i & 63) * PL + (i >> 6); };
     if (t == 0) bad = 0;
     for (int k = 0; k < n; ++k) {
         const int buf = k & 1;
@@ -376,12 +382,13 @@ __global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__res
         const bool any = (bk & ((1ull << QP_TAG) - 1)) != 0;
         if (w == bw && any) {
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) pc[lane + 64 * r] = x[r];
+            for (int r = 0; r < RPL; r += 4)
+                *reinterpret_cast<flt4 *>(pc + lane * PL + r) = flt4{x[r], x[r + 1], x[r + 2], x[r + 3]};
         }
         __syncthreads();
         if (any) {
             T *cb = cbuf + ((size_t)buf * nwg + b) * NP;
-            for (int i = k + t; i < n; i += QP_NT) coh_store(cb + i, pc[i]);
+            for (int i = k + t; i < n; i += QP_NT) coh_store(cb + i, pc[pidx(i)]);
         }
         // every wavefront's stores are complete before the key goes out
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -416,7 +423,7 @@ __global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__res
         const T pnorm = __uint_as_float((unsigned)((gk >> 13) & 0xffffffffull));
         {
             const T *src = cbuf + ((size_t)buf * nwg + p / QP_W) * NP;
-            for (int i = k + t; i < n; i += QP_NT) pc[i] = coh_load(src + i);
+            for (int i = k + t; i < n; i += QP_NT) pc[pidx(i)] = coh_load(src + i);
         }
         if (b == 0 && t == 0) {
             piv[k] = p;
@@ -426,7 +433,7 @@ __global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__res
         // 3. reflector H = I - tau v v^T, v = [1; x(k+1:)/(x_k - beta)], and update
         T tau = 0, scale = 0;
         {
-            const T x0 = pc[k];
+            const T x0 = pc[pidx(k)];
             if (pnorm > T(0)) {
                 const T beta = -copysign(pnorm, x0);
                 tau = (beta - x0) / beta;
@@ -439,16 +446,24 @@ __global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__res
         } else if (live) {
             // (groups of 8 registers: the empty asm statements keep the
             // compiler from holding RPL staged pivot entries live at once)
+            // Groups of 8 rows wholly above the pivot row are skipped.
             T d = 0, xk = 0;
+            const T *pl = pc + lane * PL;
 #pragma unroll
             for (int rg = 0; rg < RPL; rg += 8) {
+                if (rg + 7 >= r0) {
+                    const flt4 v0 = *reinterpret_cast<const flt4 *>(pl + rg);
+                    const flt4 v1 = *reinterpret_cast<const flt4 *>(pl + rg + 4);
 #pragma unroll
-                for (int r = rg; r < rg + 8; ++r) {
-                    if (r > r0) {
-                        d += pc[lane + 64 * r] * x[r];
-                    } else if (r == r0) {
-                        xk = x[r];
-                        if (lane > kl) d += pc[lane + 64 * r] * x[r];
+                    for (int e = 0; e < 8; ++e) {
+                        const int r = rg + e;
+                        const T pv = e < 4 ? v0[e & 3] : v1[e & 3];
+                        if (r > r0) {
+                            d += pv * x[r];
+                        } else if (r == r0) {
+                            xk = x[r];
+                            if (lane > kl) d += pv * x[r];
+                        }
                     }
                 }
                 __asm__ volatile("" ::: "memory");
@@ -459,11 +474,17 @@ __global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__res
             T ns = 0;
 #pragma unroll
             for (int rg = 0; rg < RPL; rg += 8) {
+                if (rg + 7 >= r0) {
+                    const flt4 v0 = *reinterpret_cast<const flt4 *>(pl + rg);
+                    const flt4 v1 = *reinterpret_cast<const flt4 *>(pl + rg + 4);
 #pragma unroll
-                for (int r = rg; r < rg + 8; ++r) {
-                    if (r > r0 || (r == r0 && lane > kl)) {
-                        x[r] -= f * pc[lane + 64 * r];
-                        ns += x[r] * x[r];
+                    for (int e = 0; e < 8; ++e) {
+                        const int r = rg + e;
+                        const T pv = e < 4 ? v0[e & 3] : v1[e & 3];
+                        if (r > r0 || (r == r0 && lane > kl)) {
+                            x[r] -= f * pv;
+                            ns += x[r] * x[r];
+                        }
                     }
                 }
                 __asm__ volatile("" ::: "memory");
