@@ -44,6 +44,8 @@ def _lib():
                                         ctypes.c_int, _dp, ctypes.c_int]
         lib.oracle_sign_normalize.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp, ctypes.c_int]
         lib.oracle_rr_pair.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _ip]
+        lib.oracle_syevj.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip]
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_max_threads.restype = ctypes.c_int
         _LIB = lib
@@ -86,6 +88,23 @@ def svd(A, precondition: bool = True, order: str = "cyclic", eps: float = 0.0,
     if st < 0:
         raise ValueError(f"oracle_svd: bad argument ({st})")
     return U, S, V, {"status": st, "sweeps": sweeps.value, "jpvt": jpvt[:n].copy()}
+
+
+def eigh(A, eps: float = 0.0, maxiter: int = 60, sign_normalize: bool = True):
+    """Symmetric eigendecomposition A = X diag(w) X^T by FP64 cyclic two-sided
+    Jacobi; w ascending.  Returns (w, X, info) with info = {status, sweeps}."""
+    A = _f64(A)
+    n = A.shape[0]
+    if A.shape != (n, n):
+        raise ValueError("A must be square")
+    w = np.zeros(max(n, 1))
+    X = np.zeros((n, n), order="F")
+    sweeps = ctypes.c_int(0)
+    st = _lib().oracle_syevj(n, _d(A), max(n, 1), _d(w), _d(X), max(n, 1), float(eps), int(maxiter),
+                             int(sign_normalize), ctypes.byref(sweeps))
+    if st < 0:
+        raise ValueError(f"oracle_syevj: bad argument ({st})")
+    return w[:n].copy(), X, {"status": st, "sweeps": sweeps.value}
 
 
 def geqr2(A):

@@ -430,3 +430,99 @@ int oracle_svd(int m, int n, const double *A, int lda, double *S,
     free(tau2); free(X); free(VX);
     return status;
 }
+
+/*
+ * Symmetric eigendecomposition A = X diag(w) X^T (n x n, A symmetric; only
+ * what is stored is used, both triangles are read as given) by the cyclic
+ * two-sided Jacobi method: the textbook computation of the spectral
+ * decomposition that the mixed-precision eigensolver of Section 8
+ * (Algorithm 6) also delivers.
+ *
+ * Each sweep visits the pairs (p, q), p < q, in row-cyclic order.  A pair is
+ * rotated when |a_pq| > eps sqrt(|a_pp| |a_qq|) (and a_pq != 0); the rotation
+ * is the 2 x 2 symmetric Schur rotation (the formula of oracle_rotation with
+ * alpha = a_pp, beta = a_qq, gamma = a_pq), applied as
+ * A <- J^T A J on rows and columns p, q, with a_pp <- a_pp - t a_pq,
+ * a_qq <- a_qq + t a_pq and a_pq <- 0; X <- X J accumulates the rotations.
+ * The method stops after a sweep without rotations, or after maxiter sweeps.
+ * w is then sorted ascending (stable) with X's columns, and, when sign_norm
+ * is set, each column of X is negated if its largest-magnitude entry (first
+ * on ties) is negative.
+ *
+ * eps <= 0 selects sqrt(n) 2^-53.  Returns ORC_OK, ORC_NOCONV or ORC_BADARG.
+ */
+int oracle_syevj(int n, const double *A, int lda, double *w, double *X, int ldx,
+                 double eps, int maxiter, int sign_norm, int *sweeps)
+{
+    if (n < 0 || lda < (n > 1 ? n : 1) || ldx < (n > 1 ? n : 1)) return ORC_BADARG;
+    if (sweeps) *sweeps = 0;
+    if (n == 0) return ORC_OK;
+    double *M = (double *)malloc((size_t)n * n * sizeof(double));
+    for (int j = 0; j < n; ++j) memcpy(M + IX(0, j, n), A + IX(0, j, lda), (size_t)n * sizeof(double));
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) X[IX(i, j, ldx)] = (i == j) ? 1.0 : 0.0;
+    const double e = eps > 0 ? eps : sqrt((double)n) * ldexp(1.0, -53);
+    int status = ORC_NOCONV, sw = 0;
+    for (; sw < maxiter; ++sw) {
+        int rotated = 0;
+        for (int p = 0; p < n - 1; ++p) {
+            for (int q = p + 1; q < n; ++q) {
+                const double app = M[IX(p, p, n)], aqq = M[IX(q, q, n)], apq = M[IX(p, q, n)];
+                if (apq == 0.0 || !(fabs(apq) > e * sqrt(fabs(app) * fabs(aqq)))) continue;
+                /* the root t of t^2 + 2 zeta t - 1 = 0 with |t| <= 1 */
+                const double zeta = (aqq - app) / (2.0 * apq);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+                rotated = 1;
+                for (int r = 0; r < n; ++r) {
+                    if (r == p || r == q) continue;
+                    const double arp = M[IX(r, p, n)], arq = M[IX(r, q, n)];
+                    const double np_ = c * arp - s * arq, nq_ = s * arp + c * arq;
+                    M[IX(r, p, n)] = np_; M[IX(p, r, n)] = np_;
+                    M[IX(r, q, n)] = nq_; M[IX(q, r, n)] = nq_;
+                }
+                M[IX(p, p, n)] = app - t * apq;
+                M[IX(q, q, n)] = aqq + t * apq;
+                M[IX(p, q, n)] = 0.0;
+                M[IX(q, p, n)] = 0.0;
+                for (int r = 0; r < n; ++r) {
+                    const double xp = X[IX(r, p, ldx)], xq = X[IX(r, q, ldx)];
+                    X[IX(r, p, ldx)] = c * xp - s * xq;
+                    X[IX(r, q, ldx)] = s * xp + c * xq;
+                }
+            }
+        }
+        if (!rotated) { status = ORC_OK; ++sw; break; }
+    }
+    if (sweeps) *sweeps = sw;
+    for (int i = 0; i < n; ++i) w[i] = M[IX(i, i, n)];
+    free(M);
+    /* stable ascending sort of w with the columns of X (insertion sort) */
+    double *col = (double *)malloc((size_t)n * sizeof(double));
+    for (int i = 1; i < n; ++i) {
+        const double wi = w[i];
+        for (int r = 0; r < n; ++r) col[r] = X[IX(r, i, ldx)];
+        int j = i - 1;
+        while (j >= 0 && w[j] > wi) {
+            w[j + 1] = w[j];
+            for (int r = 0; r < n; ++r) X[IX(r, j + 1, ldx)] = X[IX(r, j, ldx)];
+            --j;
+        }
+        w[j + 1] = wi;
+        for (int r = 0; r < n; ++r) X[IX(r, j + 1, ldx)] = col[r];
+    }
+    free(col);
+    if (sign_norm) {
+        for (int i = 0; i < n; ++i) {
+            int k = 0;
+            double best = -1.0;
+            for (int r = 0; r < n; ++r) {
+                const double a = fabs(X[IX(r, i, ldx)]);
+                if (a > best) { best = a; k = r; }
+            }
+            if (X[IX(k, i, ldx)] < 0.0)
+                for (int r = 0; r < n; ++r) X[IX(r, i, ldx)] = -X[IX(r, i, ldx)];
+        }
+    }
+    return status;
+}

@@ -403,3 +403,99 @@ def test_adjoint_central_differences_on_c5_shape():
             fd = (lp - lm) / (2 * h)
             an = np.sum(gA * E)
             assert abs(fd - an) <= 1e-5 * max(1.0, abs(an)), (fd, an)
+
+
+# ---------------------------------------------------------------------------
+# Symmetric eigendecomposition (cyclic two-sided Jacobi, the oracle of the
+# eigensolver of Section 8)
+# ---------------------------------------------------------------------------
+
+def exact_eig(A, dps=60):
+    """Eigenvalues of the stored symmetric FP64 matrix A in 60-digit arithmetic,
+    ascending."""
+    with mpmath.workdps(dps):
+        E = mpmath.eigsy(mpmath.matrix(A.tolist()), eigvals_only=True)
+        return np.array(sorted(float(x) for x in E))
+
+
+@pytest.mark.parametrize("a,b,c", [(2.0, 1.0, -1.0), (1.0, 1e-9, 1.0), (0.0, 3.0, 0.0),
+                                   (-5.0, 2.0, 7.0), (1e-8, 1e-12, 2e-8)])
+def test_eig_2x2_closed_form(a, b, c):
+    """[[a, b], [b, c]]: eigenvalues (a + c)/2 -+ sqrt(((a - c)/2)^2 + b^2),
+    evaluated at 50 digits; X diagonalises A."""
+    A = np.array([[a, b], [b, c]])
+    w, X, info = oracle.eigh(A)
+    assert info["status"] == 0
+    with mpmath.workdps(50):
+        m = (mpmath.mpf(a) + c) / 2
+        r = mpmath.sqrt(((mpmath.mpf(a) - c) / 2) ** 2 + mpmath.mpf(b) ** 2)
+        ref = np.array([float(m - r), float(m + r)])
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(w - ref)) <= 4 * U53 * scale
+    D = X.T @ A @ X
+    assert abs(D[0, 1]) <= 4 * U53 * scale
+    assert np.linalg.norm(X.T @ X - np.eye(2)) <= 4 * U53
+
+
+def test_eig_diagonal_is_exact_permutation():
+    """A diagonal matrix needs no rotation: w is its sorted diagonal exactly and
+    X the matching permutation."""
+    rng = np.random.default_rng(3)
+    d = rng.standard_normal(17)
+    w, X, info = oracle.eigh(np.diag(d))
+    assert info["sweeps"] == 1 and np.array_equal(w, np.sort(d))
+    assert np.array_equal(X, np.eye(17)[:, np.argsort(d, kind="stable")])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_eig_known_spectrum_with_plus_minus_pairs(seed):
+    """A = Q diag(lam) Q^T with Haar Q, lam indefinite with +-pairs of equal
+    magnitude and a double eigenvalue: eigenvalues to normwise backward
+    accuracy, residual, orthogonality."""
+    rng = np.random.default_rng(seed)
+    n = 40
+    mag = 10.0 ** -rng.uniform(0, 6, n)
+    lam = mag * np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    lam[1] = -lam[0]
+    lam[5] = -lam[4]
+    lam[9] = lam[8]
+    Q = testmats.haar(rng, n, n)
+    A = (Q * lam) @ Q.T
+    A = (A + A.T) / 2
+    w, X, info = oracle.eigh(A)
+    assert info["status"] == 0
+    nA = np.linalg.norm(A, 2)
+    assert np.max(np.abs(w - np.sort(lam))) <= 50 * n * U53 * nA
+    assert np.linalg.norm(A @ X - X * w) <= 50 * n * U53 * np.linalg.norm(A)
+    assert np.linalg.norm(X.T @ X - np.eye(n)) <= 50 * n * U53
+
+
+def test_eig_matches_lapack_and_invariants():
+    """Against LAPACK (numpy eigh) normwise; trace and Frobenius norm kept."""
+    rng = np.random.default_rng(11)
+    n = 33
+    B = rng.standard_normal((n, n))
+    A = (B + B.T) / 2
+    w, X, info = oracle.eigh(A)
+    nA = np.linalg.norm(A, 2)
+    assert np.max(np.abs(w - np.linalg.eigvalsh(A))) <= 20 * n * U53 * nA
+    assert abs(w.sum() - np.trace(A)) <= 10 * n * U53 * nA
+    assert abs((w ** 2).sum() - np.linalg.norm(A) ** 2) <= 20 * n * U53 * np.linalg.norm(A) ** 2
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_eig_relative_accuracy_on_graded_definite(seed):
+    """A = D H D, H well-conditioned positive definite, D graded over 10 orders:
+    Jacobi with the relative test keeps every eigenvalue to high relative
+    accuracy (60-digit reference of the stored matrix), where normwise methods
+    lose the small ones."""
+    rng = np.random.default_rng(seed)
+    n = 12
+    G = rng.standard_normal((n, n))
+    H = G @ G.T / n + np.eye(n)
+    d = 10.0 ** -rng.uniform(0, 10, n)
+    A = (H * d).T * d
+    A = (A + A.T) / 2
+    w, X, info = oracle.eigh(A)
+    ref = exact_eig(A)
+    assert np.max(np.abs(w - ref) / np.abs(ref)) <= 1e-13
