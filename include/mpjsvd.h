@@ -49,6 +49,8 @@ extern "C" {
                                     preconditions, Section 4) */
 #define SVD_ERR_NONFINITE 2      /* A holds NaN or Inf; outputs undefined   */
 #define SVD_WARN_RANK_DEFICIENT 3 /* some sigma_i == 0; U(:, i) set to zero */
+#define EIG_ERR_CLUSTER 4        /* eig_mixed: a block of equal |eigenvalue|
+                                    larger than 64; outputs undefined       */
 
 /* svd_opts.branch / svd_info.branch_taken (Algorithm 4's special cases) */
 #define SVD_BRANCH_AUTO 0
@@ -123,6 +125,9 @@ typedef struct {
                               between the two blocks (each pair of columns is
                               rotated about once per sweep, as in Algorithm 1);
                               1: all pairs in every round */
+    double tol_cluster;    /* eig_mixed only: consecutive singular values of
+                              A Q with relative gap <= tol_cluster form one
+                              block of U^T A U; 0 -> 1e-8 */
 } svd_opts;
 
 /* Kernel classes reported by svd_info.kern_* (kernel_timing 1: SVD_K_QRCP
@@ -274,6 +279,50 @@ int svd_backward(int batch, int m, int n,
                  void *work, size_t work_bytes, void *stream);
 
 /* Human-readable name of a status or return code. */
+/*
+ * Mixed-precision symmetric eigensolver (Section 8, Algorithm 6):
+ *   A = X diag(W) X^T for a symmetric n x n A (both triangles are read as
+ *   given; symmetry is not checked).
+ *   1-3. the low-precision decomposition, its orthogonalisation and the FP64
+ *      one-sided Jacobi refinement without V: the mixed-precision SVD of A
+ *      (svd_mixed with want_v = 0), A = U Sigma V^T;
+ *   4. blocks of U^T A U over runs of sigma with relative gap <= tol_cluster
+ *      (sigma and -sigma may both be eigenvalues);
+ *   5. blocks of two or more diagonalised by FP64 two-sided Jacobi (at most
+ *      64 columns each), a block of one takes the sign of u_i^T A u_i;
+ *   6. W ascending, X's columns with it; sign rule of svd_opts.sign_normalize.
+ * Options: those of svd_mixed (want_u, want_v and kernel_timing are set
+ * internally), sign_normalize for X, and tol_cluster.  NULL =
+ * svd_default_opts(.., 1).
+ * Arguments:
+ *   1 n (0 <= n <= 8192), 2 A, 3 lda >= max(1, n)   device, not modified
+ *   4 W        device output, n eigenvalues ascending
+ *   5 X, 6 ldx device output n x n, ldx >= max(1, n), eigenvectors in columns
+ *   7 work, 8 work_bytes   device scratch, >= eig_workspace_size(n, o)
+ *   9 o        options (host)
+ *   10 info    HOST pointer, filled before return (may be NULL)
+ *   11 stream  hipStream_t
+ * Returns 0, or -k for an invalid argument k (-9: an option out of range).
+ * The numerical outcome is info->status: SVD_OK, SVD_WARN_NOCONV,
+ * SVD_ERR_NONFINITE, SVD_WARN_RANK_DEFICIENT (a zero singular value: the
+ * matching columns of X are zero) or EIG_ERR_CLUSTER.  The call reads
+ * results back and synchronises the stream before it returns.
+ */
+typedef struct {
+    int status;
+    int sweeps_low;        /* FP32 sweeps of the SVD                     */
+    int sweeps_work;       /* FP64 sweeps of the SVD                     */
+    int n_clusters;        /* blocks of two or more diagonalised         */
+    int max_cluster;       /* largest block                              */
+    float stage_ms[4];     /* SVD of A, A U and signs, blocks, sort and
+                              output                                     */
+} eig_info;
+
+size_t eig_workspace_size(int n, const svd_opts *o);
+int eig_mixed(int n, const double *A, int lda, double *W, double *X, int ldx,
+              void *work, size_t work_bytes, const svd_opts *o, eig_info *info,
+              void *stream);
+
 const char *svd_status_string(int code);
 
 /* Description of the HIP failure behind the last SVD_ERR_HIP return of a

@@ -24,10 +24,11 @@ EXPORTS = [
     "svd_default_opts", "svd_workspace_size", "svd_plain", "svd_mixed",
     "svd_batched_plan_create", "svd_batched", "svd_batched_plan_destroy",
     "svd_backward_workspace_size", "svd_backward", "svd_status_string", "svd_last_error",
-    "svd_set_tuning", "svd_tuning_lookup",
+    "svd_set_tuning", "svd_tuning_lookup", "eig_workspace_size", "eig_mixed",
 ]
 
 SVD_OK, SVD_WARN_NOCONV, SVD_ERR_NONFINITE, SVD_WARN_RANK_DEFICIENT = 0, 1, 2, 3
+EIG_ERR_CLUSTER = 4
 KERNEL_CLASSES = ["jac_gram<f32>", "jac_inner<f32>", "jac_update<f32>", "jac_gram<f64>",
                   "jac_inner<f64>", "jac_update<f64>", "qrcp", "qr_panel", "gemm", "-", "-", "-"]
 NCLASS = 12
@@ -47,7 +48,7 @@ class SvdOpts(ctypes.Structure):
         ("kernel_timing", ctypes.c_int), ("low_stop_off", ctypes.c_double),
         ("block_cols_low", ctypes.c_int), ("block_cols_work", ctypes.c_int),
         ("v_method", ctypes.c_int), ("diagnostics", ctypes.c_int), ("tol_vsolve", ctypes.c_double),
-        ("inner_pairs", ctypes.c_int),
+        ("inner_pairs", ctypes.c_int), ("tol_cluster", ctypes.c_double),
     ]
 
 
@@ -76,6 +77,18 @@ class SvdInfo(ctypes.Structure):
             "v_method_taken": self.v_method_taken, "sweeps_vfix": self.sweeps_vfix,
             "orth_vx": self.orth_vx, "orth_y": self.orth_y,
         }
+
+
+class EigInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int), ("sweeps_low", ctypes.c_int), ("sweeps_work", ctypes.c_int),
+        ("n_clusters", ctypes.c_int), ("max_cluster", ctypes.c_int), ("stage_ms", ctypes.c_float * 4),
+    ]
+
+    def as_dict(self) -> dict:
+        return {"status": self.status, "sweeps_low": self.sweeps_low, "sweeps_work": self.sweeps_work,
+                "n_clusters": self.n_clusters, "max_cluster": self.max_cluster,
+                "stage_ms": list(self.stage_ms)}
 
 
 class SvdBatchInfo(ctypes.Structure):
@@ -122,6 +135,11 @@ def load():
                                  _ll, _vp, _vp, _vp, _vp, _ll, ctypes.c_double, _vp,
                                  ctypes.c_size_t, _vp]
     lib.svd_backward.restype = ctypes.c_int
+    lib.eig_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(SvdOpts)]
+    lib.eig_workspace_size.restype = ctypes.c_size_t
+    lib.eig_mixed.argtypes = [ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp,
+                              ctypes.c_size_t, ctypes.POINTER(SvdOpts), ctypes.POINTER(EigInfo), _vp]
+    lib.eig_mixed.restype = ctypes.c_int
     lib.svd_status_string.argtypes = [ctypes.c_int]
     lib.svd_status_string.restype = ctypes.c_char_p
     lib.svd_last_error.argtypes = []
@@ -233,6 +251,33 @@ def svd(A, mode: str = "mixed", workspace: Workspace | None = None, opts: SvdOpt
         raise RuntimeError(f"svd_{mode} returned {rc}: {lib.svd_status_string(rc).decode()} "
                            f"[{lib.svd_last_error().decode()}]")
     return Ut.t(), S, Vt.t(), info.as_dict()
+
+
+def eigh(A, workspace: Workspace | None = None, opts: SvdOpts | None = None, **kw):
+    """A = X diag(W) X^T for a symmetric n x n float64 CUDA tensor by the
+    mixed-precision eigensolver (Algorithm 6).  Keyword arguments set svd_opts
+    fields.  Returns (W ascending, X, info dict)."""
+    import torch
+    lib = load()
+    _check_device(A, "A")
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be square")
+    n = A.shape[0]
+    o = opts if opts is not None else default_opts(True, **kw)
+    dev = A.device
+    Acm = A.t().contiguous()
+    W = torch.empty((n,), dtype=torch.float64, device=dev)
+    Xt = torch.empty((n, n), dtype=torch.float64, device=dev)
+    nbytes = int(lib.eig_workspace_size(n, ctypes.byref(o)))
+    ws = (workspace or _ws_default).get(nbytes, dev)
+    info = EigInfo()
+    with torch.cuda.device(dev):
+        rc = lib.eig_mixed(n, Acm.data_ptr(), max(n, 1), W.data_ptr(), Xt.data_ptr(), max(n, 1),
+                           ws.data_ptr(), ws.numel(), ctypes.byref(o), ctypes.byref(info), _stream_ptr(dev))
+    if rc != 0:
+        raise RuntimeError(f"eig_mixed returned {rc}: {lib.svd_status_string(rc).decode()} "
+                           f"[{lib.svd_last_error().decode()}]")
+    return W, Xt.t(), info.as_dict()
 
 
 def call_raw(mode: str, m: int, n: int, A_ptr: int, lda: int, S_ptr: int, U_ptr: int, ldu: int,

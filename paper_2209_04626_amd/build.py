@@ -24,7 +24,7 @@ FLAGS = [
 ]
 
 SOURCES = ["gemm.hip", "qr.hip", "qrcp.hip", "jacobi.hip", "misc.hip", "backward.hip",
-           "batched.hip", "api.hip", "tune.hip", "vsolve.hip"]
+           "batched.hip", "api.hip", "tune.hip", "vsolve.hip", "eig.hip"]
 
 
 def _compile(src: str) -> str:

@@ -46,6 +46,7 @@ extern "C" void svd_default_opts(svd_opts *o, int mixed) {
     o->diagnostics = 0;
     o->tol_vsolve = 0.0;
     o->inner_pairs = 0;
+    o->tol_cluster = 0.0;
 }
 
 namespace {
@@ -497,6 +498,7 @@ extern "C" const char *svd_status_string(int code) {
     case SVD_WARN_NOCONV: return "warning: a Jacobi phase reached its sweep cap";
     case SVD_ERR_NONFINITE: return "error: input holds NaN or Inf";
     case SVD_WARN_RANK_DEFICIENT: return "warning: zero singular value(s)";
+    case EIG_ERR_CLUSTER: return "error: a block of equal |eigenvalue| larger than 64";
     case SVD_ERR_HIP: return "error: HIP runtime failure";
     default: return code < 0 ? "error: invalid argument" : "unknown status";
     }

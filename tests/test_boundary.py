@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     src = open(os.path.join(ROOT, "include", "mpjsvd.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_]\w*\s*\**\s*(svd_\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_]\w*\s*\**\s*((?:svd|eig)_\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 
