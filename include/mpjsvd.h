@@ -128,6 +128,13 @@ typedef struct {
     double tol_cluster;    /* eig_mixed only: consecutive singular values of
                               A Q with relative gap <= tol_cluster form one
                               block of U^T A U; 0 -> 1e-8 */
+    int y2_safeguard;      /* 1 (default): after the switch, the columns j
+                              of Y whose normalised Gram row has an
+                              off-diagonal max|c_ij| > tol_y2 form Y2; if there
+                              are two or more, FP64 sweeps run on Y2 alone
+                              before the sweeps over all of Y (Section 3.4);
+                              costs one FP64 Gram product; 0: off */
+    double tol_y2;         /* 0 -> 64 sqrt(n) 2^-24 */
 } svd_opts;
 
 /* Kernel classes reported by svd_info.kern_* (kernel_timing 1: SVD_K_QRCP
@@ -168,6 +175,8 @@ typedef struct {
     double orth_y;         /* diagnostics: max|D^-1 Y^T Y D^-1 - I| of Y
                               after the switch (D = column norms), -1 if not
                               measured */
+    int n_y2;              /* columns in Y2 (0: the safeguard did not act) */
+    int sweeps_y2;         /* FP64 sweeps run on Y2 alone */
 } svd_info;
 
 /* Load the tuning table measured by the autotuner (not part of the paper's

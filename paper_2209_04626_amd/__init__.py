@@ -49,6 +49,7 @@ class SvdOpts(ctypes.Structure):
         ("block_cols_low", ctypes.c_int), ("block_cols_work", ctypes.c_int),
         ("v_method", ctypes.c_int), ("diagnostics", ctypes.c_int), ("tol_vsolve", ctypes.c_double),
         ("inner_pairs", ctypes.c_int), ("tol_cluster", ctypes.c_double),
+        ("y2_safeguard", ctypes.c_int), ("tol_y2", ctypes.c_double),
     ]
 
 
@@ -62,6 +63,7 @@ class SvdInfo(ctypes.Structure):
         ("kern_bytes", ctypes.c_double * NCLASS), ("kern_flops", ctypes.c_double * NCLASS),
         ("v_method_taken", ctypes.c_int), ("sweeps_vfix", ctypes.c_int),
         ("orth_vx", ctypes.c_double), ("orth_y", ctypes.c_double),
+        ("n_y2", ctypes.c_int), ("sweeps_y2", ctypes.c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -76,6 +78,7 @@ class SvdInfo(ctypes.Structure):
             "kern_bytes": list(self.kern_bytes), "kern_flops": list(self.kern_flops),
             "v_method_taken": self.v_method_taken, "sweeps_vfix": self.sweeps_vfix,
             "orth_vx": self.orth_vx, "orth_y": self.orth_y,
+            "n_y2": self.n_y2, "sweeps_y2": self.sweeps_y2,
         }
 
 

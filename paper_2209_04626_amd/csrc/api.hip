@@ -4,6 +4,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <vector>
+
 #include "../../include/mpjsvd.h"
 #include "common.hpp"
 #include "internal.hpp"
@@ -47,6 +49,8 @@ extern "C" void svd_default_opts(svd_opts *o, int mixed) {
     o->tol_vsolve = 0.0;
     o->inner_pairs = 0;
     o->tol_cluster = 0.0;
+    o->y2_safeguard = 1;
+    o->tol_y2 = 0.0;
 }
 
 namespace {
@@ -58,7 +62,7 @@ struct Layout {
     size_t off_atall, off_tau0, off_t0, off_a1, off_wp, off_nrm2, off_piv, off_a1p, off_tau1,
         off_t1, off_rt, off_tau2, off_t2, off_x, off_y, off_vacc, off_y32, off_xt, off_ulow, off_bm,
         off_tau3, off_t3, off_ux, off_vx, off_sig, off_rank, off_nrmx, off_small, off_qr, off_jac,
-        off_v32, total;
+        off_v32, off_v2, off_idx, total;
 };
 
 // Jacobi block width per stage: the FP32 stage is bound by the latency of
@@ -116,6 +120,8 @@ Layout layout(int m, int n, const svd_opts &o) {
     L.off_rank = take((size_t)n * sizeof(int));
     L.off_nrmx = take((size_t)n * d);
     L.off_small = take(4096);
+    L.off_v2 = take(o.y2_safeguard ? NN * d : 0);           // V columns of Y2
+    L.off_idx = take((size_t)n * sizeof(int) + (size_t)n * sizeof(float));
     L.off_qr = take(qr_scratch_doubles(m > n ? m : n, n, nullptr) * d);
     {
         const size_t j32 = jacobi_scratch_bytes(L.N, L.b32, (int)f);
@@ -196,6 +202,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     if (o.v_method != 0 && o.v_method != 1) return -12;
     if (o.switch_method < 1 || o.switch_method > 3) return -12;
     if (o.inner_pairs != 0 && o.inner_pairs != 1) return -12;
+    if (o.y2_safeguard != 0 && o.y2_safeguard != 1) return -12;
     if (info) {
         memset(info, 0, sizeof(*info));
         info->orth = -1.0;
@@ -364,21 +371,68 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         tm.mark(6);
     }
     MPJ_CHECK(hipGetLastError());
+    // Algorithm 3's Y = A1 Q has no triangular factor to solve with: V is
+    // accumulated there
+    const bool alg3 = branch == SVD_BRANCH_LOW && o.switch_method == 3;
+    const bool vsolve = o.want_v && o.v_method == 1 && !alg3;
     double orth_y = -1.0;
-    if (o.diagnostics) {
+    int n_y2 = 0, sweeps_y2 = 0;
+    const bool y2check = o.y2_safeguard && branch == SVD_BRANCH_LOW && n >= 2;
+    if (o.diagnostics && !y2check) {
         // how far the columns of Y are from orthogonal when the FP64 sweeps start
         normalize_cols64(s, n, n, Y, N, Ulow, N);
         gemm_orth_maxdev64(s, n, Ulow, N, &sm->orthy);
         if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
         orth_y = hs.orthy;
     }
+    if (y2check) {
+        // Section 3.4's safeguard: C = D^-1 Y^T Y D^-1; the columns whose
+        // off-diagonal max|c_ij| is well above the FP32 level form Y2, and
+        // FP64 sweeps run on Y2 alone before the sweeps over all of Y
+        int *idx = (int *)(w + L.off_idx);
+        float *dev = (float *)(idx + n);
+        normalize_cols64(s, n, n, Y, N, Ulow, N);
+        gemm<double>(s, true, false, n, n, n, 1.0, Ulow, N, Ulow, N, 0.0, VX, n, q.split,
+                     q.split_elems, jw.kc);
+        colmax_offdiag(s, n, VX, n, dev);
+        std::vector<float> hdev(n);
+        if (read_back(s, hdev.data(), dev, (size_t)n * sizeof(float))) return SVD_ERR_HIP;
+        float dmax = 0.f;
+        for (int j = 0; j < n; ++j) dmax = fmaxf(dmax, hdev[j]);
+        if (o.diagnostics) orth_y = dmax;
+        const double tol2 = o.tol_y2 > 0 ? o.tol_y2 : 64.0 * sqrt((double)n) * ldexp(1.0, -24);
+        std::vector<int> y2;
+        for (int j = 0; j < n; ++j)
+            if ((double)hdev[j] > tol2) y2.push_back(j);
+        const int k = (int)y2.size();
+        if (k >= 2) {
+            const int K = cdiv(k, 2 * L.b64) * 2 * L.b64;   // Y2's columns, zero padded
+            double *Y2 = Ulow, *V2 = (o.want_v && !vsolve) ? D(L.off_v2) : nullptr;
+            MPJ_CHECK(hipMemcpyAsync(idx, y2.data(), (size_t)k * sizeof(int), hipMemcpyHostToDevice, s));
+            zero_pad_fill(s, N, K, Y2, N);
+            gather_cols(s, N, k, Y, N, idx, Y2, N);
+            if (V2) {
+                zero_pad_fill(s, N, K, V2, N);
+                gather_cols(s, N, k, Vacc, N, idx, V2, N);
+            }
+            jacobi_carve(jw, w + L.off_jac, N, L.b64, (int)sizeof(double));
+            jw.off_hist = nullptr;
+            jw.n_real = k;
+            int conv_y2 = 0;
+            sweeps_y2 = jacobi_sweeps_cols<double>(s, N, K, L.b64, Y2, V2, eps_work, o.maxsweep_work,
+                                                   inner, jw, &conv_y2);
+            jw.n_real = n;
+            if (sweeps_y2 < 0) return SVD_ERR_HIP;
+            scatter_cols(s, N, k, Y2, N, idx, Y, N);
+            if (V2) scatter_cols(s, N, k, V2, N, idx, Vacc, N);
+            MPJ_CHECK(hipGetLastError());
+            n_y2 = k;
+        }
+    }
 
     // a8: FP64 one-sided Jacobi (Algorithm 1); V_X accumulated from Q
     // (v_method 0) or formed afterwards (v_method 1, Section 3.4)
-    // Algorithm 3's Y = A1 Q has no triangular factor to solve with: V is
-    // accumulated there
-    const bool alg3 = branch == SVD_BRANCH_LOW && o.switch_method == 3;
-    const bool vsolve = o.want_v && o.v_method == 1 && !alg3;
+
     int conv_work = 0;
     jacobi_carve(jw, w + L.off_jac, N, L.b64, (int)sizeof(double));
     jw.off_hist = off_work;
@@ -462,6 +516,8 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         info->sweeps_vfix = sweeps_vfix;
         info->orth_vx = orth_vx;
         info->orth_y = orth_y;
+        info->n_y2 = n_y2;
+        info->sweeps_y2 = sweeps_y2;
         int st = SVD_OK;
         if (!conv_work) st = SVD_WARN_NOCONV;
         if (hs.nzero) st = SVD_WARN_RANK_DEFICIENT;

@@ -153,6 +153,13 @@ void jacobi_carve(JacobiWork &j, char *base, int N, int b, int elem);
 template <typename T>
 int jacobi_sweeps(hipStream_t s, int N, int b, T *Y, T *V, double eps,
                   int maxsweep, int max_inner, JacobiWork &jw, int *conv);
+// The same on the first ncols columns of Y and V only (ncols a multiple of 2b).
+template <typename T>
+int jacobi_sweeps_cols(hipStream_t s, int N, int ncols, int b, T *Y, T *V, double eps,
+                       int maxsweep, int max_inner, JacobiWork &jw, int *conv);
+void scatter_cols(hipStream_t s, int rows, int n, const double *D, int ldd, const int *idx, double *A,
+                  int lda);
+void colmax_offdiag(hipStream_t s, int n, const double *C, int ldc, float *dev);
 
 // ---------------------------------------------------------------- misc
 void copy_scan(hipStream_t s, int m, int n, const double *A, int lda,

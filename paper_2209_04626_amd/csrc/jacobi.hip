@@ -531,11 +531,13 @@ void jacobi_carve(JacobiWork &jw, char *base, int N, int b, int elem) {
     jw.flag = (int *)p;
 }
 
+// Sweeps over the ncols columns of Y (N rows, ld N; ncols a multiple of 2b,
+// at most N) and of V (N rows).
 template <typename T, int B2, int INNER_NT>
-static int sweeps_impl(hipStream_t s, int N, T *Y, T *V, double eps, int maxsweep, int max_inner,
-                       JacobiWork &jw, int *conv) {
+static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, int maxsweep,
+                       int max_inner, JacobiWork &jw, int *conv) {
     constexpr int b = B2 / 2;
-    const int nblk = N / b;
+    const int nblk = ncols / b;
     const int npairs = nblk / 2;
     const int nch = cdiv(N, JR_RG);
     const int nchG = cdiv(N, JR_RGG);
@@ -553,9 +555,9 @@ static int sweeps_impl(hipStream_t s, int N, T *Y, T *V, double eps, int maxswee
         // and writes Y (and V) once and costs 2 N (2b)^2 flops per pair and
         // matrix; the inner solve is (2b - 1) rounds of b rotations applied
         // two-sided to the 2b x 2b block and one-sided to W (12 (2b)^2 b flops)
-        const double gram_bytes = (double)N * N * E;
+        const double gram_bytes = (double)N * ncols * E;
         const double gram_flops = (double)npairs * N * B2 * B2;
-        const double upd_bytes = 2.0 * (double)N * N * E * (V ? 2 : 1);
+        const double upd_bytes = 2.0 * (double)N * ncols * E * (V ? 2 : 1);
         const double upd_flops = 2.0 * (double)npairs * N * B2 * B2 * (V ? 2 : 1);
         const double inner_flops = 12.0 * (double)npairs * B2 * B2 * b;
         for (int r = 0; r < nblk - 1; ++r) {
@@ -594,15 +596,27 @@ static int sweeps_impl(hipStream_t s, int N, T *Y, T *V, double eps, int maxswee
 }
 
 template <typename T>
+int jacobi_sweeps_cols(hipStream_t s, int N, int ncols, int b, T *Y, T *V, double eps, int maxsweep,
+                       int max_inner, JacobiWork &jw, int *conv) {
+    if (ncols <= 0 || ncols > N || ncols % (2 * b) != 0) {
+        note_hip_error(hipErrorInvalidValue, "jacobi_sweeps_cols: column count");
+        return -1;
+    }
+    if (b == 16) return sweeps_impl<T, 32, 256>(s, N, ncols, Y, V, eps, maxsweep, max_inner, jw, conv);
+    return sweeps_impl<T, 64, 256>(s, N, ncols, Y, V, eps, maxsweep, max_inner, jw, conv);
+}
+
+template <typename T>
 int jacobi_sweeps(hipStream_t s, int N, int b, T *Y, T *V, double eps, int maxsweep, int max_inner,
                   JacobiWork &jw, int *conv) {
-    if (b == 16) return sweeps_impl<T, 32, 256>(s, N, Y, V, eps, maxsweep, max_inner, jw, conv);
-    return sweeps_impl<T, 64, 256>(s, N, Y, V, eps, maxsweep, max_inner, jw, conv);
+    return jacobi_sweeps_cols<T>(s, N, N, b, Y, V, eps, maxsweep, max_inner, jw, conv);
 }
 
 template int jacobi_sweeps<float>(hipStream_t, int, int, float *, float *, double, int, int,
                                   JacobiWork &, int *);
 template int jacobi_sweeps<double>(hipStream_t, int, int, double *, double *, double, int, int,
                                    JacobiWork &, int *);
+template int jacobi_sweeps_cols<double>(hipStream_t, int, int, int, double *, double *, double, int,
+                                        int, JacobiWork &, int *);
 
 } // namespace mpj

@@ -310,3 +310,38 @@ void sign_normalize(hipStream_t s, int m, int n, double *U, int ldu, bool have_u
 }
 
 } // namespace mpj
+
+namespace mpj {
+
+// A(:, idx[k]) = D(:, k) for k < n   (the inverse of gather_cols)
+__global__ void k_scatter_cols(int rows, int n, const double *D, int ldd, const int *idx, double *A,
+                               int lda) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)rows * n) return;
+    const int i = (int)(e % rows), k = (int)(e / rows);
+    A[(size_t)idx[k] * lda + i] = D[(size_t)k * ldd + i];
+}
+void scatter_cols(hipStream_t s, int rows, int n, const double *D, int ldd, const int *idx, double *A,
+                  int lda) {
+    if ((size_t)rows * n == 0) return;
+    hipLaunchKernelGGL(k_scatter_cols, grid1((size_t)rows * n), dim3(256), 0, s, rows, n, D, ldd, idx,
+                       A, lda);
+}
+
+// dev[j] = max_{i != j} |C(i, j)|   (one wavefront per column)
+__global__ __launch_bounds__(256) void k_colmax_offdiag(int n, const double *C, int ldc, float *dev) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= n) return;
+    float m = 0.f;
+    for (int i = lane; i < n; i += 64)
+        if (i != j) m = fmaxf(m, (float)fabs(C[(size_t)j * ldc + i]));
+    m = wave_max(m);
+    if (lane == 0) dev[j] = m;
+}
+void colmax_offdiag(hipStream_t s, int n, const double *C, int ldc, float *dev) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_colmax_offdiag, dim3(cdiv(n, 4)), dim3(256), 0, s, n, C, ldc, dev);
+}
+
+} // namespace mpj

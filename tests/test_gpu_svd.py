@@ -236,3 +236,22 @@ def test_orthogonality_of_y_after_switch(lib, method):
     assert 0.0 < info["orth_y"] < 1e-3, info
     U, S, V, info_x = run(lib, A, "plain", diagnostics=1)
     assert info_x["orth_y"] > 100 * info["orth_y"], (info_x, info)   # X itself
+
+
+@pytest.mark.parametrize("v_method", [0, 1])
+def test_y2_safeguard(lib, v_method):
+    """Section 3.4's safeguard: by default it finds no badly orthogonal columns
+    after the switch (Y2 empty); with the bound lowered it sweeps Y2 alone
+    first (a part of the columns, then all of them) and the result still
+    meets the gates."""
+    print(f"case y2 safeguard v_method={v_method}", flush=True)
+    A = known(300, 300, seed=95, e=10.0, kind="log")
+    Uo, So, Vo, _ = oracle.svd(A)
+    U, S, V, info = run(lib, A, "mixed", branch=1, diagnostics=1, v_method=v_method)
+    assert info["status"] == 0 and info["n_y2"] == 0 and info["orth_y"] > 0, info
+    for tol in (info["orth_y"] / 3, 1e-300):
+        U, S, V, info2 = run(lib, A, "mixed", branch=1, tol_y2=tol, v_method=v_method)
+        g = metrics.gates(A, U, S, V, So)
+        assert info2["status"] == 0 and g["pass"], (tol, g, info2)
+        assert info2["n_y2"] >= 2 and info2["sweeps_y2"] >= 1, info2
+    assert info2["n_y2"] == 300
