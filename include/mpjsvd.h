@@ -100,9 +100,11 @@ typedef struct {
                               QR panel and GEMM kernels with HIP events
                               (per-class totals; adds host work and a little
                               time).  Results in svd_info.kern_*. */
-    double low_stop_off;   /* end the FP32 stage once a sweep starts with
-                              every |g_pq| <= low_stop_off sqrt(g_pp g_qq);
-                              0 = only the eps_low rule.  Default 0. */
+    double low_stop_off;   /* end the FP32 stage after a sweep in which
+                              every |g_pq| met was <= low_stop_off
+                              sqrt(g_pp g_qq): the next sweep would only
+                              rotate at the FP32 rounding level.  0 (default)
+                              -> sqrt(n) eps_low; < 0: only the eps_low rule */
     int block_cols_low;    /* b of the FP32 stage (16 or 32), over block_cols;
                               0 = block_cols, else the tuning table, else 16 */
     int block_cols_work;   /* b of the FP64 stage (16 or 32), over block_cols;

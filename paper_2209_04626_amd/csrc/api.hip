@@ -336,7 +336,8 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         }
         jacobi_carve(jw, w + L.off_jac, N, L.b32, (int)sizeof(float));
         jw.off_hist = off_low;
-        jw.stop_off = o.low_stop_off;
+        jw.stop_off = o.low_stop_off > 0 ? o.low_stop_off
+                                         : (o.low_stop_off == 0 ? sqrt((double)n) * eps_low : 0.0);
         sweeps_low = jacobi_sweeps<float>(s, N, L.b32, Y32, V32, eps_low, o.maxsweep_low, inner,
                                           jw, &conv_low);
         jw.stop_off = 0.0;

@@ -603,6 +603,10 @@ int jacobi_sweeps_cols(hipStream_t s, int N, int ncols, int b, T *Y, T *V, doubl
         return -1;
     }
     if (b == 16) return sweeps_impl<T, 32, 256>(s, N, ncols, Y, V, eps, maxsweep, max_inner, jw, conv);
+    // 64-wide FP64 blocks: 512 threads shorten each round's per-thread work
+    // (2 groups of G and 4 rows of W per thread instead of 4 and 8)
+    if (sizeof(T) == 8)
+        return sweeps_impl<T, 64, 512>(s, N, ncols, Y, V, eps, maxsweep, max_inner, jw, conv);
     return sweeps_impl<T, 64, 256>(s, N, ncols, Y, V, eps, maxsweep, max_inner, jw, conv);
 }
 
