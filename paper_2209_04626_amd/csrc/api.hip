@@ -88,7 +88,7 @@ Layout layout(int m, int n, const svd_opts &o) {
     L.b64 = pick_b(n, o, false);
     const size_t d = sizeof(double), f = sizeof(float);
     const size_t nn = (size_t)n * n, NN = (size_t)L.N * L.N;
-    const size_t nblk = (size_t)cdiv(n, QR_NB) * QR_NB * QR_NB;
+    const size_t nblk = qr_t_doubles(n);
     size_t p = 0;
     auto take = [&](size_t bytes) { size_t o_ = p; p += al256(bytes); return o_; };
     L.off_atall = take(m > n ? (size_t)m * n * d : 0);

@@ -87,6 +87,7 @@ void normalize_cols64(hipStream_t s, int rows, int cols, const double *Y, int ld
 
 // ---------------------------------------------------------------- QR
 constexpr int QR_NB = 32;    // panel width of the blocked Householder QR
+constexpr int QR_NBO = 128;  // outer block of the QR: trailing updates and Q applications
 constexpr int QR_RC = 256;   // rows per workgroup in the panel kernels
 
 struct QRScratch {
@@ -94,8 +95,11 @@ struct QRScratch {
     double *head;   // 2 * QR_NB
     double *vtv;    // max_groups * QR_NB * QR_NB
     double *vb;     // m * QR_NB     (explicit unit-lower block of reflectors)
-    double *w1;     // QR_NB * ncols_max
-    double *w2;     // QR_NB * ncols_max
+    double *vbo;    // m * QR_NBO    (the same for an outer block)
+    double *go;     // QR_NBO * QR_NBO  (V^T V of an outer block)
+    double *tp;     // QR_NB * QR_NB    (T of the current panel)
+    double *w1;     // QR_NBO * ncols_max
+    double *w2;     // QR_NBO * ncols_max
     double *split;  // split-K scratch
     size_t split_elems;
     int *flags;     // max_groups step flags of the one-launch panel
@@ -104,9 +108,12 @@ struct QRScratch {
 size_t qr_scratch_doubles(int m, int ncols_max, size_t *split_elems);
 void qr_scratch_carve(QRScratch &q, double *base, int m, int ncols_max);
 
+// Doubles of the block factors T of an n-column QR: ceil(n / QR_NBO) blocks
+// of QR_NBO x QR_NBO.
+size_t qr_t_doubles(int n);
 // Householder QR of the m x n matrix A (m >= n): R in the upper triangle,
-// reflectors below, tau[n], block factors T (ceil(n/QR_NB) blocks of
-// QR_NB x QR_NB, ld QR_NB) in Tall.
+// reflectors below, tau[n], block factors T of each outer block of QR_NBO
+// columns (QR_NBO x QR_NBO, ld QR_NBO, upper triangular) in Tall.
 void qr_factor(hipStream_t s, int m, int n, double *A, int lda, double *tau,
                double *Tall, QRScratch &q);
 // C (m x ncol) <- Q C (trans = false) or Q^T C (trans = true), Q from

@@ -291,11 +291,11 @@ __global__ void qr_flags_zero(int n, int *flags) {
     if (e < n) flags[e] = 0;
 }
 
-// T (nb x nb upper, ld QR_NB) from G = V^T V (ld QR_NB) and tau:
+// T (nb x nb upper, zeros below, ld ldt) from G = V^T V (ld QR_NB) and tau:
 // T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j).  One wavefront;
 // lane t keeps row t of T in registers.
 __global__ __launch_bounds__(64) void qr_build_t(int nb, const double *vtv, const double *tau,
-                                                 double *T) {
+                                                 double *T, int ldt) {
     __shared__ double G[QR_NB * QR_NB];
     __shared__ double ts[QR_NB];
     __shared__ double z[QR_NB];
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(64) void qr_build_t(int nb, const double *vtv, cons
     }
     if (t < QR_NB) {
 #pragma unroll
-        for (int l = 0; l < QR_NB; ++l) T[l * QR_NB + t] = tr[l];
+        for (int l = 0; l < QR_NB; ++l) T[(size_t)l * ldt + t] = tr[l];
     }
 }
 
@@ -337,12 +337,15 @@ __global__ __launch_bounds__(256) void qr_extract_v(int mp, int nb, const double
     Vb[(size_t)k * ldv + i] = v;
 }
 
+size_t qr_t_doubles(int n) { return (size_t)cdiv(n, QR_NBO) * QR_NBO * QR_NBO; }
+
 size_t qr_scratch_doubles(int m, int ncols_max, size_t *split_elems) {
     const int G = cdiv(m, QR_RC);
-    const size_t se = (size_t)8 * QR_NB * (size_t)ncols_max;
+    const size_t se = (size_t)8 * QR_NBO * (size_t)ncols_max;
     if (split_elems) *split_elems = se;
     return (size_t)2 * G * QR_NB + 2 * QR_NB + (size_t)G * QR_NB * QR_NB + (size_t)m * QR_NB +
-           2 * (size_t)QR_NB * ncols_max + se + (size_t)(G + 63) / 2 + 128;
+           (size_t)m * QR_NBO + (size_t)QR_NBO * QR_NBO + (size_t)QR_NB * QR_NB +
+           2 * (size_t)QR_NBO * ncols_max + se + (size_t)(G + 63) / 2 + 128;
 }
 
 void qr_scratch_carve(QRScratch &q, double *base, int m, int ncols_max) {
@@ -354,23 +357,26 @@ void qr_scratch_carve(QRScratch &q, double *base, int m, int ncols_max) {
     q.head = p; p += 2 * QR_NB;
     q.vtv = p; p += (size_t)G * QR_NB * QR_NB;
     q.vb = p; p += (size_t)m * QR_NB;
-    q.w1 = p; p += (size_t)QR_NB * ncols_max;
-    q.w2 = p; p += (size_t)QR_NB * ncols_max;
+    q.vbo = p; p += (size_t)m * QR_NBO;
+    q.go = p; p += (size_t)QR_NBO * QR_NBO;
+    q.tp = p; p += (size_t)QR_NB * QR_NB;
+    q.w1 = p; p += (size_t)QR_NBO * ncols_max;
+    q.w2 = p; p += (size_t)QR_NBO * ncols_max;
     q.split = p; p += se;
     q.split_elems = se;
     q.flags = (int *)(p + 32);
 }
 
-static void extract_v(hipStream_t s, int mp, int nb, const double *P, int ld, QRScratch &q) {
+static void extract_v(hipStream_t s, int mp, int nb, const double *P, int ld, double *vb) {
     const size_t tot = (size_t)mp * nb;
     hipLaunchKernelGGL(qr_extract_v, dim3((unsigned)cdivl((long long)tot, 256)), dim3(256), 0, s,
-                       mp, nb, P, ld, q.vb, mp);
+                       mp, nb, P, ld, vb, mp);
 }
 
 // Factor one panel (mp x nb at P), leave its explicit V in Vb and build its T
 // from V^T V (FP64 matrix-core product).
 static void panel_factor(hipStream_t s, int mp, int nb, double *P, int ld, double *tau,
-                         double *T, QRScratch &q, int panel) {
+                         double *T, int ldt, QRScratch &q, int panel) {
     const int G = cdiv(mp, QR_RC);
     if (G <= QR_COOP_MAXG) {
         // algorithmic work: the panel read and written once, 2 mp nb^2 flops
@@ -384,49 +390,81 @@ static void panel_factor(hipStream_t s, int mp, int nb, double *P, int ld, doubl
             hipLaunchKernelGGL(qr_panel_step, dim3(G), dim3(QR_RC), 0, s, j, mp, nb, G, P, ld,
                                q.part, q.head, tau);
     }
-    extract_v(s, mp, nb, P, ld, q);
+    extract_v(s, mp, nb, P, ld, q.vb);
     gemm<double>(s, true, false, nb, nb, mp, 1.0, q.vb, mp, q.vb, mp, 0.0, q.vtv, QR_NB, q.split,
                  q.split_elems, q.kc);
-    hipLaunchKernelGGL(qr_build_t, dim3(1), dim3(64), 0, s, nb, q.vtv, tau, T);
+    hipLaunchKernelGGL(qr_build_t, dim3(1), dim3(64), 0, s, nb, q.vtv, tau, T, ldt);
 }
 
-// C (mp x ncol) <- (I - V T' V^T) C with T' = T (trans = false) or T^T.
-static void apply_block(hipStream_t s, bool transT, int mp, int nb, const double *T, int ncol,
-                        double *C, int ldc, QRScratch &q) {
-    gemm<double>(s, true, false, nb, ncol, mp, 1.0, q.vb, mp, C, ldc, 0.0, q.w1, nb, q.split,
+// C (mp x ncol) <- (I - V T' V^T) C with T' = T (trans = false) or T^T; V
+// explicit in vb (ld mp), T with ld ldt.
+static void apply_block(hipStream_t s, bool transT, int mp, int nb, const double *T, int ldt,
+                        int ncol, double *C, int ldc, const double *vb, QRScratch &q) {
+    gemm<double>(s, true, false, nb, ncol, mp, 1.0, vb, mp, C, ldc, 0.0, q.w1, nb, q.split,
                  q.split_elems, q.kc);
-    gemm<double>(s, transT, false, nb, ncol, nb, 1.0, T, QR_NB, q.w1, nb, 0.0, q.w2, nb, nullptr, 0,
+    gemm<double>(s, transT, false, nb, ncol, nb, 1.0, T, ldt, q.w1, nb, 0.0, q.w2, nb, nullptr, 0,
                  q.kc);
-    gemm<double>(s, false, false, mp, ncol, nb, -1.0, q.vb, mp, q.w2, nb, 1.0, C, ldc, nullptr, 0,
+    gemm<double>(s, false, false, mp, ncol, nb, -1.0, vb, mp, q.w2, nb, 1.0, C, ldc, nullptr, 0,
                  q.kc);
 }
 
+// Two-level blocked Householder QR: 32-wide panels (one launch each) update
+// the rest of their 128-column outer block with the panel's compact-WY form;
+// the outer block's T is assembled from the panel T's on its diagonal and
+// the blocks above them, T(0:r, c) = -T(0:r, 0:r) (V(:, 0:r)^T V_c) T_c (the
+// column recurrence of the compact-WY form taken a panel at a time), and the
+// trailing columns take one compact-WY product of depth 128.
 void qr_factor(hipStream_t s, int m, int n, double *A, int lda, double *tau, double *Tall,
                QRScratch &q) {
     const int gmax = cdiv(m, QR_RC);
     if (gmax <= QR_COOP_MAXG)
         hipLaunchKernelGGL(qr_flags_zero, dim3(cdiv(gmax, 256)), dim3(256), 0, s, gmax, q.flags);
-    for (int c0 = 0, blk = 0; c0 < n; c0 += QR_NB, ++blk) {
-        const int nb = min(QR_NB, n - c0);
-        const int mp = m - c0;
-        double *P = A + (size_t)c0 * lda + c0;
-        double *T = Tall + (size_t)blk * QR_NB * QR_NB;
-        panel_factor(s, mp, nb, P, lda, tau + c0, T, q, blk);
-        const int nt = n - c0 - nb;
-        if (nt > 0) apply_block(s, true, mp, nb, T, nt, P + (size_t)nb * lda, lda, q);
+    int panel = 0;
+    for (int c0o = 0, ob = 0; c0o < n; c0o += QR_NBO, ++ob) {
+        const int nbo = min(QR_NBO, n - c0o);
+        const int mpo = m - c0o;
+        double *To = Tall + (size_t)ob * QR_NBO * QR_NBO;
+        zero_pad_fill(s, QR_NBO, QR_NBO, To, QR_NBO);
+        for (int c0 = c0o; c0 < c0o + nbo; c0 += QR_NB, ++panel) {
+            const int nb = min(QR_NB, c0o + nbo - c0);
+            const int mp = m - c0;
+            double *P = A + (size_t)c0 * lda + c0;
+            double *Tp = To + (size_t)(c0 - c0o) * QR_NBO + (c0 - c0o);
+            panel_factor(s, mp, nb, P, lda, tau + c0, Tp, QR_NBO, q, panel);
+            const int nin = c0o + nbo - c0 - nb;   // the rest of the outer block
+            if (nin > 0)
+                apply_block(s, true, mp, nb, Tp, QR_NBO, nin, P + (size_t)nb * lda, lda, q.vb, q);
+        }
+        double *Po = A + (size_t)c0o * lda + c0o;
+        extract_v(s, mpo, nbo, Po, lda, q.vbo);
+        if (nbo > QR_NB) {
+            gemm<double>(s, true, false, nbo, nbo, mpo, 1.0, q.vbo, mpo, q.vbo, mpo, 0.0, q.go, QR_NBO,
+                         q.split, q.split_elems, q.kc);
+            for (int r = QR_NB; r < nbo; r += QR_NB) {
+                const int cb = min(QR_NB, nbo - r);
+                gemm<double>(s, false, false, r, cb, r, 1.0, To, QR_NBO, q.go + (size_t)r * QR_NBO,
+                             QR_NBO, 0.0, q.w1, r, nullptr, 0, q.kc);
+                gemm<double>(s, false, false, r, cb, cb, -1.0, q.w1, r, To + (size_t)r * QR_NBO + r,
+                             QR_NBO, 0.0, To + (size_t)r * QR_NBO, QR_NBO, nullptr, 0, q.kc);
+            }
+        }
+        const int nt = n - c0o - nbo;
+        if (nt > 0)
+            apply_block(s, true, mpo, nbo, To, QR_NBO, nt, Po + (size_t)nbo * lda, lda, q.vbo, q);
     }
 }
 
 void qr_apply_left(hipStream_t s, bool trans, int m, int k, const double *Qf, int ldq,
                    const double *Tall, int ncol, double *C, int ldc, QRScratch &q) {
-    const int nblk = cdiv(k, QR_NB);
-    for (int t = 0; t < nblk; ++t) {
-        const int blk = trans ? t : nblk - 1 - t;
-        const int c0 = blk * QR_NB;
-        const int nb = min(QR_NB, k - c0);
+    const int nob = cdiv(k, QR_NBO);
+    for (int t = 0; t < nob; ++t) {
+        const int ob = trans ? t : nob - 1 - t;
+        const int c0 = ob * QR_NBO;
+        const int nb = min(QR_NBO, k - c0);
         const int mp = m - c0;
-        extract_v(s, mp, nb, Qf + (size_t)c0 * ldq + c0, ldq, q);
-        apply_block(s, trans, mp, nb, Tall + (size_t)blk * QR_NB * QR_NB, ncol, C + c0, ldc, q);
+        extract_v(s, mp, nb, Qf + (size_t)c0 * ldq + c0, ldq, q.vbo);
+        apply_block(s, trans, mp, nb, Tall + (size_t)ob * QR_NBO * QR_NBO, QR_NBO, ncol, C + c0, ldc,
+                    q.vbo, q);
     }
 }
 
