@@ -17,8 +17,13 @@ Prints one JSON line.  Options: --gpus (only 1), --steps K, --warmup W,
 --n (size), --mode (both | mixed | plain: "both" is the metric, the others are
 for profiling runs), --no-cpu-baseline, --cpu-sample-n.
 
+Kernel classes: before the timed region, one SVD of each kind per kernel
+class is run with HIP events on the launches of that class only (recorded by
+the dispatch itself for the Jacobi kernels); the largest class of the mixed
+step (GEMMs aside) is the dominant kernel, and the timed mixed SVDs clock it
+(the pivot pass as one interval per pass).
 roofline.traffic is the HBM traffic per launch of the dominant kernel from
-the counter runs recorded in profiles/qrcp_persist_f32_n4096_traffic.md; it
+the counter runs recorded in profiles/ (a <kernel>_n4096_traffic.md file); it
 is reported only while the kernel's sources hash to the value recorded there.
 """
 from __future__ import annotations
@@ -35,6 +40,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+CLOCK_EVERY = 8                # sampled clocking of the dominant Jacobi class
 FP64_PEAK_TF = 78.6            # dense FP64 (vector and MFMA)
 FP32_PEAK_TF = 157.3           # dense FP32 (vector and MFMA)
 
@@ -60,23 +66,32 @@ def algorithmic_flops(n: int, info: dict, mixed: bool) -> float:
     return f
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "qrcp_persist_f32_n4096_traffic.md")
-TRAFFIC_SOURCES = ["paper_2209_04626_amd/csrc/qrcp.hip", "paper_2209_04626_amd/csrc/common.hpp"]
+# counter records (profiles/) of the kernels bench.py may report as dominant,
+# with the sources whose hash the record carries
+TRAFFIC = {
+    "qrcp": ("qrcp_persist_f32_n4096_traffic.md",
+             ["paper_2209_04626_amd/csrc/qrcp.hip", "paper_2209_04626_amd/csrc/common.hpp"]),
+    "jac_update<f32>": ("jac_update_f32_n4096_traffic.md",
+                        ["paper_2209_04626_amd/csrc/jacobi.hip", "paper_2209_04626_amd/csrc/common.hpp"]),
+}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(kernel: str = "qrcp") -> str:
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in TRAFFIC[kernel][1]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def recorded_traffic(n: int):
-    """HBM bytes per launch of the pivot step kernel measured with the
-    FETCH_SIZE / WRITE_SIZE counters (copy-calibrated), or None when there is
-    no record for this size or the kernel has changed since."""
-    if n != 4096 or not os.path.exists(TRAFFIC_FILE):
+def recorded_traffic(n: int, kernel: str = "qrcp"):
+    """HBM bytes per launch of `kernel` measured with the FETCH_SIZE /
+    WRITE_SIZE counters (copy-calibrated), or None when there is no record for
+    this size or the kernel's sources have changed since."""
+    if n != 4096 or kernel not in TRAFFIC:
+        return None
+    TRAFFIC_FILE = os.path.join(ROOT, "profiles", TRAFFIC[kernel][0])
+    if not os.path.exists(TRAFFIC_FILE):
         return None
     rec = {}
     with open(TRAFFIC_FILE) as fh:
@@ -84,7 +99,7 @@ def recorded_traffic(n: int):
             m = re.match(r"^- (\w+): `?([^`\s]+)`?", line.strip())
             if m:
                 rec[m.group(1)] = m.group(2)
-    if rec.get("source_sha256") != kernel_source_hash():
+    if rec.get("source_sha256") != kernel_source_hash(kernel):
         return None
     try:
         return float(rec["traffic_bytes_per_launch"])
@@ -102,27 +117,36 @@ CLASS_ROOF = {
 }
 
 
-def kernel_table(info: dict, mp, overhead_s: float = 0.0) -> list:
-    """Per kernel class of one clocked SVD: launches, time, algorithmic bytes
-    and flops per launch, achieved rates and the fraction of the roof that
-    bounds the class (hbm: bytes against 8 TB/s; mfma: flops against the FP64
-    matrix peak; latency: flops against the FP64 peak, for scale only).
-    overhead_s, the time the event brackets add to one launch, is taken off
-    each launch (ms_raw keeps the bracketed total)."""
+def class_survey(mp, A, ws, mode: str, classes) -> dict:
+    """One clocked SVD per kernel class, with HIP events around the launches of
+    that class only (kernel_timing = 100 + class), so the other launches run
+    as in an unclocked SVD.  Returns {class: (ms, launches, bytes, flops)}."""
+    import torch
+    out = {}
+    for c in classes:
+        o = mp.default_opts(mode == "mixed")
+        o.kernel_timing = 100 + c
+        info = mp.svd(A, mode, workspace=ws, opts=o)[3]
+        torch.cuda.synchronize()
+        if info["kern_calls"][c] > 0:
+            out[c] = (info["kern_ms"][c], info["kern_calls"][c], info["kern_bytes"][c], info["kern_flops"][c])
+    return out
+
+
+def kernel_table(survey: dict, mp) -> list:
+    """Per kernel class: launches, time, algorithmic bytes and flops per
+    launch, achieved rates and the fraction of the roof that bounds the class
+    (hbm: bytes against 8 TB/s; mfma: flops against the FP64 matrix peak;
+    latency: flops against the FP64 peak, for scale only)."""
     rows = []
-    for c, name in enumerate(mp.KERNEL_CLASSES):
-        calls = info["kern_calls"][c]
-        if name == "-" or calls <= 0:
-            continue
-        ms_raw = info["kern_ms"][c]
-        ms = max(ms_raw - calls * overhead_s * 1e3, 0.5 * ms_raw)
-        byts, flops = info["kern_bytes"][c], info["kern_flops"][c]
+    for c, (ms, calls, byts, flops) in survey.items():
+        name = mp.KERNEL_CLASSES[c]
         sec = ms / 1e3
         gbs = byts / sec / 1e9 if sec > 0 else 0.0
         tfs = flops / sec / 1e12 if sec > 0 else 0.0
         bound, fpk = CLASS_ROOF.get(name, ("hbm", None))
         frac = gbs / HBM_PEAK_GBS if bound == "hbm" else tfs / (fpk or FP64_PEAK_TF)
-        rows.append({"kernel": name, "launches": calls, "ms": round(ms, 3), "ms_raw": round(ms_raw, 3),
+        rows.append({"kernel": name, "class": c, "launches": calls, "ms": round(ms, 3),
                      "avg_us": round(ms * 1e3 / calls, 2), "bytes_per_launch": round(byts / calls),
                      "flops_per_launch": round(flops / calls), "GB_s": round(gbs, 1),
                      "TFLOP_s": round(tfs, 3), "bound": bound, "frac": round(frac, 4)})
@@ -182,6 +206,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--mode", choices=("both", "mixed", "plain"), default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-survey", action="store_true",
+                    help="skip the per-class clocked SVDs (no kernels table, no roofline)")
     ap.add_argument("--cpu-sample-n", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -215,11 +241,31 @@ def main() -> int:
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
-    # timed: K mixed SVDs (the step); the dominant kernel (the QRCP pivot
-    # step) is clocked with HIP events on the library's stream, one interval
-    # per pass of n back-to-back launches
-    opts_mixed.kernel_timing = 1
-    opts_plain.kernel_timing = 1
+    # per-class kernel times of one SVD of each kind (untimed): each class
+    # clocked in an SVD of its own, HIP events around that class's launches
+    # only; the GEMM class (many shapes) is listed but never picked
+    survey = {}
+    if do_mixed and not args.no_survey:
+        survey["mixed"] = class_survey(mp, A, ws, "mixed", range(0, 8))
+    if do_plain and not args.no_survey:
+        survey["plain"] = class_survey(mp, A, ws, "plain", range(0, 9))
+    kernels = {k: kernel_table(v, mp) for k, v in survey.items()}
+    # the dominant kernel: the class with the largest total time in the mixed
+    # step (the Jacobi kernels are clocked by events that their dispatch
+    # records, so clocking them in the timed region costs no extra packets)
+    dom_class = None
+    if do_mixed and "mixed" in survey:
+        dom_class = max(survey["mixed"].items(), key=lambda kv: kv[1][0])[0]
+    print(f"[bench] class survey done; dominant class {dom_class}", file=sys.stderr, flush=True)
+
+    # timed: K mixed SVDs (the step) with the dominant kernel clocked by HIP
+    # events on the library's stream (the pivot pass as one interval per
+    # pass); K plain SVDs without events
+    opts_mixed.kernel_timing = 1 if dom_class == 6 else (100 + dom_class if dom_class is not None else 0)
+    # a Jacobi class is clocked on every CLOCK_EVERY-th launch (a uniform
+    # sample over rounds and sweeps) so that its events barely touch the step
+    opts_mixed.kernel_timing_every = CLOCK_EVERY
+    opts_plain.kernel_timing = 0
     infos, infos_p = [], []
     t_mixed = t_plain = None
     if do_mixed:
@@ -273,58 +319,28 @@ def main() -> int:
     if t_plain_vs is not None:
         g_plain_vs = gates_gpu(A, Upv, Spv, Vpv, s_ref, kappa or 1.0)
 
-    # per-class kernel clocks from one extra SVD of each kind (untimed, every
-    # launch bracketed by HIP events on the library's stream)
-    # The brackets add a little to each launch; the added time per launch is
-    # estimated from the clocked SVD's wall time against the timed one and
-    # taken off each class before the dominant kernel is chosen.
-    kernels, clock_overhead_us = {}, {}
-    for mode, t_ref, on in (("mixed", t_mixed, do_mixed), ("plain", t_plain, do_plain)):
-        if not on:
-            continue
-        oc = mp.default_opts(mode == "mixed")
-        oc.kernel_timing = 2
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        info_c = mp.svd(A, mode, workspace=ws, opts=oc)[3]
-        torch.cuda.synchronize()
-        t_c = time.perf_counter() - t0
-        ncalls = sum(info_c["kern_calls"])
-        ovh = max(0.0, (t_c - t_ref) / max(ncalls, 1))
-        clock_overhead_us[mode] = round(ovh * 1e6, 3)
-        kernels[mode] = kernel_table(info_c, mp, ovh)
-    torch.cuda.synchronize()
-
-    # roofline of the dominant kernel of the step (largest class of the mixed
-    # SVD): the pivot pass is clocked inside the timed region (one interval
-    # per pass); another class would come from the clocked SVD
+    # roofline of the dominant kernel class of the mixed step, from the
+    # clocked launches of the timed region
     roofline = None
-    if do_mixed:
-        # the GEMM class gathers kernels of many shapes; the dominant kernel is
-        # the largest of the single-kernel classes
-        dom = [k for k in kernels["mixed"] if k["kernel"] != "gemm"][0]
-        if dom["kernel"] == "qrcp":
-            c = mp.KERNEL_CLASSES.index("qrcp")
-            ms = float(np.sum([i["kern_ms"][c] for i in infos]))
-            calls = int(np.sum([i["kern_calls"][c] for i in infos]))
-            byts = float(np.sum([i["kern_bytes"][c] for i in infos]))
-            avg_s = ms / 1e3 / max(calls, 1)
-            bytes_per_launch = byts / max(calls, 1)
-            src = "timed region"
-        else:
-            avg_s = dom["avg_us"] / 1e6
-            bytes_per_launch = dom["bytes_per_launch"]
-            calls = dom["launches"]
-            src = "clocked SVD after the timed region"
-        traffic = recorded_traffic(n) if dom["kernel"] == "qrcp" else None
-        if dom["bound"] == "mfma":
-            ach = dom["TFLOP_s"]
+    if do_mixed and dom_class is not None:
+        c = dom_class
+        ms = float(np.sum([i["kern_ms"][c] for i in infos]))
+        calls = int(np.sum([i["kern_calls"][c] for i in infos]))
+        byts = float(np.sum([i["kern_bytes"][c] for i in infos]))
+        flops = float(np.sum([i["kern_flops"][c] for i in infos]))
+        name = mp.KERNEL_CLASSES[c]
+        avg_s = ms / 1e3 / max(calls, 1)
+        bytes_per_launch = byts / max(calls, 1)
+        bound, _ = CLASS_ROOF.get(name, ("hbm", None))
+        traffic = recorded_traffic(n, name)
+        if bound == "mfma":
+            ach = flops / (ms / 1e3) / 1e12
             roofline = {"bound": "mfma", "achieved": round(ach, 2), "peak": FP64_PEAK_TF,
                         "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TF, 4)}
-        elif dom["bound"] == "latency":
+        elif bound == "latency":
             # a chain of dependent LDS rounds: priced against the FP64 vector
             # ALU peak (256 CUs x 128 FP64 flop/clk x 2.4 GHz)
-            ach = dom["TFLOP_s"]
+            ach = flops / (ms / 1e3) / 1e12
             roofline = {"bound": "alu", "achieved": round(ach, 3), "peak": FP64_PEAK_TF,
                         "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TF, 4)}
         else:
@@ -333,8 +349,9 @@ def main() -> int:
                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4)}
         roofline.update({
             "traffic": None if traffic is None else round(traffic),
-            "kernel": dom["kernel"], "avg_us": round(avg_s * 1e6, 2), "launches": calls,
-            "bytes_per_launch": round(bytes_per_launch), "measured": src,
+            "kernel": name, "avg_us": round(avg_s * 1e6, 2), "launches": calls,
+            "bytes_per_launch": round(bytes_per_launch),
+            "measured": "timed region" + (f", every {CLOCK_EVERY}th launch" if c < 6 else ""),
         })
 
     line = {
@@ -379,7 +396,6 @@ def main() -> int:
         }
     line["roofline"] = roofline
     line["kernels"] = kernels
-    line["kernel_clock_overhead_us"] = clock_overhead_us
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_sample_n)

@@ -99,7 +99,9 @@ typedef struct {
                               2: bracket every launch of the Jacobi, pivot,
                               QR panel and GEMM kernels with HIP events
                               (per-class totals; adds host work and a little
-                              time).  Results in svd_info.kern_*. */
+                              time); 100 + c: bracket only the launches of
+                              class c (SVD_K_*), the others run without
+                              events.  Results in svd_info.kern_*. */
     double low_stop_off;   /* end the FP32 stage after a sweep in which
                               every |g_pq| met was <= low_stop_off
                               sqrt(g_pp g_qq): the next sweep would only
@@ -137,6 +139,10 @@ typedef struct {
                               before the sweeps over all of Y (Section 3.4);
                               costs one FP64 Gram product; 0: off */
     double tol_y2;         /* 0 -> 64 sqrt(n) 2^-24 */
+    int kernel_timing_every; /* with kernel_timing >= 2: clock only every
+                              k-th launch of a Jacobi kernel class (a sample
+                              that keeps the events' cost out of the rest of
+                              the launches); 0 or 1 = every launch */
 } svd_opts;
 
 /* Kernel classes reported by svd_info.kern_* (kernel_timing 1: SVD_K_QRCP

@@ -50,6 +50,7 @@ class SvdOpts(ctypes.Structure):
         ("v_method", ctypes.c_int), ("diagnostics", ctypes.c_int), ("tol_vsolve", ctypes.c_double),
         ("inner_pairs", ctypes.c_int), ("tol_cluster", ctypes.c_double),
         ("y2_safeguard", ctypes.c_int), ("tol_y2", ctypes.c_double),
+        ("kernel_timing_every", ctypes.c_int),
     ]
 
 

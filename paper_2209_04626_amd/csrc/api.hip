@@ -51,6 +51,7 @@ extern "C" void svd_default_opts(svd_opts *o, int mixed) {
     o->tol_cluster = 0.0;
     o->y2_safeguard = 1;
     o->tol_y2 = 0.0;
+    o->kernel_timing_every = 1;
 }
 
 namespace {
@@ -203,6 +204,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     if (o.switch_method < 1 || o.switch_method > 3) return -12;
     if (o.inner_pairs != 0 && o.inner_pairs != 1) return -12;
     if (o.y2_safeguard != 0 && o.y2_safeguard != 1) return -12;
+    if (o.kernel_timing_every < 0) return -12;
     if (info) {
         memset(info, 0, sizeof(*info));
         info->orth = -1.0;
@@ -241,6 +243,8 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     jw.cross_pairs = o.inner_pairs == 0 ? 1 : 0;
     KernelClock kclock;
     kclock.on = o.kernel_timing != 0;
+    if (o.kernel_timing >= 100) kclock.only = o.kernel_timing - 100;
+    if (o.kernel_timing_every > 1) kclock.every = o.kernel_timing_every;
     jw.kc = o.kernel_timing >= 2 ? &kclock : nullptr;
     q.kc = jw.kc;
     float off_low[32] = {0}, off_work[32] = {0};

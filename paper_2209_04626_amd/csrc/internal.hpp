@@ -17,6 +17,10 @@ struct KernelClock {
     std::vector<double> bytes, flops;
     size_t used = 0;
     bool on = false;
+    int only = -1;          // >= 0: bracket only the launches of this class
+    int every = 1;          // clock every `every`-th launch of a class (slot())
+    int seen[NC] = {0};
+    bool skipping = false;
     float ms[NC] = {0};
     int calls[NC] = {0};
     int pass_calls = 0;
@@ -24,6 +28,8 @@ struct KernelClock {
     double tot_flops[NC] = {0};
     void begin(hipStream_t s, int c, double b, double f = 0.0) {
         if (!on) return;
+        skipping = only >= 0 && c != only;
+        if (skipping) return;
         if (used + 2 > ev.size()) {
             hipEvent_t e0, e1;
             hipEventCreate(&e0);
@@ -39,8 +45,33 @@ struct KernelClock {
         flops[used / 2] = f;
         hipEventRecord(ev[used], s);
     }
+    // The events of one launch of class c that the dispatch itself records
+    // (hipExtLaunchKernelGGL): no marker packets around the kernel, so short
+    // launches are timed as the trace sees them.  False when c is not
+    // clocked.
+    bool slot(int c, double b, double f, hipEvent_t *e0, hipEvent_t *e1) {
+        if (!on || (only >= 0 && c != only)) return false;
+        if (seen[c]++ % every != 0) return false;
+        if (used + 2 > ev.size()) {
+            hipEvent_t a, z;
+            hipEventCreate(&a);
+            hipEventCreate(&z);
+            ev.push_back(a);
+            ev.push_back(z);
+            cls.push_back(c);
+            bytes.push_back(b);
+            flops.push_back(f);
+        }
+        cls[used / 2] = c;
+        bytes[used / 2] = b;
+        flops[used / 2] = f;
+        *e0 = ev[used];
+        *e1 = ev[used + 1];
+        used += 2;
+        return true;
+    }
     void end(hipStream_t s) {
-        if (!on) return;
+        if (!on || skipping) return;
         hipEventRecord(ev[used + 1], s);
         used += 2;
     }
@@ -151,6 +182,7 @@ struct JacobiWork {
     double stop_off = 0.0;      // also stop once a sweep starts with off <= this
     int cross_pairs = 0;        // 1: after a sweep's first round, rotate only the
                                 // pairs between the two blocks of each block pair
+    int *rcount = nullptr;      // device: block pairs rotated in each round
 };
 size_t jacobi_scratch_bytes(int N, int b, int elem);
 void jacobi_carve(JacobiWork &j, char *base, int N, int b, int elem);

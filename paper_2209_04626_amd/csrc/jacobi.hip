@@ -19,6 +19,11 @@
 // in which no block pair needed a rotation on a freshly computed Gram block.
 #include <string.h>
 
+#include <hip/hip_ext.h>
+
+#include <utility>
+#include <vector>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -190,7 +195,7 @@ __device__ __forceinline__ bool jac_rot_test(double al, double be, double ga, do
 template <typename T, int B2, int NT>
 __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict__ Gp,
                                                 T *__restrict__ Wm, int *skip, int *flag,
-                                                double eps, int max_inner, int cross) {
+                                                double eps, int max_inner, int cross, int *rcnt) {
     constexpr int LD = B2 + 1;
     constexpr int H = B2 / 2;
     constexpr int M = B2 - 1;
@@ -306,7 +311,11 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
         if (tid == 0) skip[pair] = 1;
         return;
     }
-    if (tid == 0) { skip[pair] = 0; *flag = 1; }
+    if (tid == 0) {
+        skip[pair] = 0;
+        *flag = 1;
+        atomicAdd(rcnt, 1);   // pairs rotated in this round
+    }
 
     // 3. cyclic rounds of disjoint rotations on G, accumulating W = prod J
     const int a = tid % H, cg = tid / H;
@@ -517,6 +526,7 @@ size_t jacobi_scratch_bytes(int N, int b, int elem) {
     bytes += (size_t)npairs * B2 * B2 * elem;                // W blocks
     bytes += (size_t)npairs * sizeof(int) + 256;             // skip flags
     bytes += 256;                                             // flag
+    bytes += (size_t)(N / b) * sizeof(int) + 256;            // pairs rotated per round
     return bytes + 1024;
 }
 
@@ -528,7 +538,8 @@ void jacobi_carve(JacobiWork &jw, char *base, int N, int b, int elem) {
     jw.gram = p; p += (size_t)npairs * nch * B2 * B2 * elem;
     jw.wmat = p; p += (size_t)npairs * B2 * B2 * elem;
     jw.skip = (int *)p; p += (size_t)npairs * sizeof(int) + 256;
-    jw.flag = (int *)p;
+    jw.flag = (int *)p; p += 256;
+    jw.rcount = (int *)p;
 }
 
 // Sweeps over the ncols columns of Y (N rows, ld N; ncols a multiple of 2b,
@@ -544,8 +555,16 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
     const int nchV = V ? nch : 0;
     *conv = 0;
     int sw = 0;
+    std::vector<std::pair<size_t, int>> upd_slots;   // clocked update launches (slot, round)
+    std::vector<int> hcount(nblk);
+    // one rotated pair in the update: its 2b columns of Y (and V) read and
+    // written once, 2 N (2b)^2 flops per matrix
+    const double pair_upd_bytes = 2.0 * N * B2 * sizeof(T) * (V ? 2 : 1);
+    const double pair_upd_flops = 2.0 * N * B2 * B2 * (V ? 2 : 1);
     for (; sw < maxsweep; ++sw) {
         hipError_t e = hipMemsetAsync(jw.flag, 0, 3 * sizeof(int), s);
+        if (e == hipSuccess) e = hipMemsetAsync(jw.rcount, 0, (size_t)nblk * sizeof(int), s);
+        upd_slots.clear();
         if (e != hipSuccess) { note_hip_error(e, "jacobi flag reset"); return -1; }
         // kernel-class ids for the optional per-launch clock
         const int kbase = sizeof(T) == 4 ? 0 : 3;
@@ -561,22 +580,45 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
         const double upd_flops = 2.0 * (double)npairs * N * B2 * B2 * (V ? 2 : 1);
         const double inner_flops = 12.0 * (double)npairs * B2 * B2 * b;
         for (int r = 0; r < nblk - 1; ++r) {
-            if (jw.kc) jw.kc->begin(s, kbase + 0, gram_bytes, gram_flops);
-            hipLaunchKernelGGL((jac_gram<T, B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, N, nblk, r, Y,
-                               N, (T *)jw.gram, nchG);
-            if (jw.kc) { jw.kc->end(s); jw.kc->begin(s, kbase + 1, 0.0, inner_flops); }
-            hipLaunchKernelGGL((jac_inner<T, B2, INNER_NT>), dim3(npairs), dim3(INNER_NT), 0, s, nchG,
-                               (const T *)jw.gram, (T *)jw.wmat, jw.skip, jw.flag, eps, max_inner,
-                               (jw.cross_pairs && r > 0) ? 1 : 0);
-            if (jw.kc) { jw.kc->end(s); jw.kc->begin(s, kbase + 2, upd_bytes, upd_flops); }
-            hipLaunchKernelGGL((jac_update<T, B2>), dim3(npairs, nch + nchV), dim3(JR_NT), 0, s, N,
-                               nblk, r, Y, N, V, N, nch, (const T *)jw.wmat, jw.skip);
-            if (jw.kc) jw.kc->end(s);
+            // optional per-launch clock: events recorded by the dispatch itself
+            hipEvent_t e0, e1;
+            const int cross = (jw.cross_pairs && r > 0) ? 1 : 0;
+            if (jw.kc && jw.kc->slot(kbase + 0, gram_bytes, gram_flops, &e0, &e1))
+                hipExtLaunchKernelGGL((jac_gram<T, B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, e0, e1,
+                                      0, N, nblk, r, (const T *)Y, N, (T *)jw.gram, nchG);
+            else
+                hipLaunchKernelGGL((jac_gram<T, B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, N, nblk, r,
+                                   Y, N, (T *)jw.gram, nchG);
+            if (jw.kc && jw.kc->slot(kbase + 1, 0.0, inner_flops, &e0, &e1))
+                hipExtLaunchKernelGGL((jac_inner<T, B2, INNER_NT>), dim3(npairs), dim3(INNER_NT), 0, s,
+                                      e0, e1, 0, nchG, (const T *)jw.gram, (T *)jw.wmat, jw.skip,
+                                      jw.flag, eps, max_inner, cross, jw.rcount + r);
+            else
+                hipLaunchKernelGGL((jac_inner<T, B2, INNER_NT>), dim3(npairs), dim3(INNER_NT), 0, s,
+                                   nchG, (const T *)jw.gram, (T *)jw.wmat, jw.skip, jw.flag, eps,
+                                   max_inner, cross, jw.rcount + r);
+            if (jw.kc && jw.kc->slot(kbase + 2, upd_bytes, upd_flops, &e0, &e1)) {
+                upd_slots.push_back({jw.kc->used / 2 - 1, r});
+                hipExtLaunchKernelGGL((jac_update<T, B2>), dim3(npairs, nch + nchV), dim3(JR_NT), 0, s,
+                                      e0, e1, 0, N, nblk, r, Y, N, V, N, nch, (const T *)jw.wmat,
+                                      (const int *)jw.skip);
+            } else
+                hipLaunchKernelGGL((jac_update<T, B2>), dim3(npairs, nch + nchV), dim3(JR_NT), 0, s, N,
+                                   nblk, r, Y, N, V, N, nch, (const T *)jw.wmat, jw.skip);
         }
         e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(jw.hflag, jw.flag, 3 * sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && !upd_slots.empty())
+            e = hipMemcpyAsync(hcount.data(), jw.rcount, (size_t)nblk * sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { note_hip_error(e, "jacobi sweep"); return -1; }
+        // a clocked update launch moves the columns of the pairs its round
+        // rotated (the others are skipped): its algorithmic bytes and flops
+        for (auto &us : upd_slots) {
+            const double k = (double)hcount[us.second];
+            jw.kc->bytes[us.first] = k * pair_upd_bytes;
+            jw.kc->flops[us.first] = k * pair_upd_flops;
+        }
         if (jw.kc) jw.kc->collect();
         float off, smx;
         memcpy(&off, jw.hflag + 1, sizeof(float));
