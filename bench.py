@@ -73,6 +73,8 @@ TRAFFIC = {
              ["paper_2209_04626_amd/csrc/qrcp.hip", "paper_2209_04626_amd/csrc/common.hpp"]),
     "jac_update<f32>": ("jac_update_f32_n4096_traffic.md",
                         ["paper_2209_04626_amd/csrc/jacobi.hip", "paper_2209_04626_amd/csrc/common.hpp"]),
+    "qr_panel": ("qr_panel_coop_n4096_traffic.md",
+                 ["paper_2209_04626_amd/csrc/qr.hip", "paper_2209_04626_amd/csrc/common.hpp"]),
 }
 
 

@@ -30,9 +30,21 @@
 namespace mpj {
 
 constexpr int JR_NT = 256;   // threads per workgroup
-constexpr int JR_RG = 256;   // rows per workgroup in update
-constexpr int JR_RGG = 256;  // rows per workgroup in gram
-constexpr int JR_SLAB = 32;  // rows staged in LDS at a time
+
+// Row tiling per precision: rows per workgroup of the Gram kernel (each
+// workgroup writes one partial Gram block, so fewer rows mean more partials
+// to reduce), rows staged in LDS per step of the Gram kernel, and rows per
+// workgroup of the update (no partials: smaller chunks only add workgroups).
+template <typename T> struct JTile;
+template <> struct JTile<float> {
+    static constexpr int GRAM_RG = 512, GRAM_SLAB = 32, UPD_RG = 256;
+};
+template <> struct JTile<double> {
+    static constexpr int GRAM_RG = 256, GRAM_SLAB = 32, UPD_RG = 256;
+};
+inline int gram_chunks(int N, int elem) {
+    return cdiv(N, elem == 4 ? JTile<float>::GRAM_RG : JTile<double>::GRAM_RG);
+}
 
 __device__ __forceinline__ int blk_col(int c, int b, int I, int J) {
     return c < b ? I * b + c : J * b + (c - b);
@@ -46,6 +58,7 @@ template <typename T, int B2>
 __global__ __launch_bounds__(JR_NT) void jac_gram(int N, int nblk, int r, const T *__restrict__ Y,
                                                   int ldy, T *__restrict__ Gp, int nchunk) {
     constexpr int b = B2 / 2;
+    constexpr int JR_SLAB = JTile<T>::GRAM_SLAB, JR_RGG = JTile<T>::GRAM_RG;
     constexpr int NTT = B2 / 16;                       // tiles per dimension
     constexpr int NUT = NTT * (NTT + 1) / 2;           // upper-triangle tiles
     constexpr int TPW = (NUT + 3) / 4;
@@ -110,6 +123,70 @@ __global__ __launch_bounds__(JR_NT) void jac_gram(int N, int nblk, int r, const 
                 out[i + j * B2] = acc[q][e];
             }
         }
+    }
+}
+
+// FP32 partial Gram block without staging the columns in LDS.  Each
+// wavefront owns 64-row stripes of the chunk.  Lane (g, i) of the wavefront
+// (g = lane / 16, i = lane % 16) reads, for every 16-column tile h of the pair
+// and u = 0..3, rows 16 u + 4 g .. + 3 of column 16 h + i as one 16-byte
+// vector; element t of it is row k = (u, t) of the MFMA step for both
+// operands, so the A and B operands of every tile come straight from these
+// registers (the MFMA sums over k in any order).  All four wavefronts form
+// every tile on or above the block diagonal over their own rows; the four
+// partial tiles are then summed in a fixed order through LDS.
+template <int B2>
+__global__ __launch_bounds__(JR_NT) void jac_gram_f32(int N, int nblk, int r, const float *__restrict__ Y,
+                                                      int ldy, float *__restrict__ Gp, int nchunk) {
+    constexpr int b = B2 / 2;
+    constexpr int NTT = B2 / 16;                       // tiles per dimension
+    constexpr int NUT = NTT * (NTT + 1) / 2;           // upper-triangle tiles
+    constexpr int RG = JTile<float>::GRAM_RG;
+    __shared__ float red[4][NUT][256];
+    const int pair = blockIdx.x, chunk = blockIdx.y;
+    int I, J;
+    rr_slot(nblk, r, pair, &I, &J);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int g = lane >> 4, li = lane & 15;
+    const float *col[NTT];
+#pragma unroll
+    for (int h = 0; h < NTT; ++h) col[h] = Y + (size_t)blk_col(16 * h + li, b, I, J) * ldy + 4 * g;
+    flt4 acc[NUT];
+#pragma unroll
+    for (int q = 0; q < NUT; ++q) acc[q] = flt4{0, 0, 0, 0};
+    const int rbeg = chunk * RG, rend = min(N, rbeg + RG);
+    for (int r0 = rbeg + 64 * w; r0 + 64 <= rend; r0 += 64 * (JR_NT / 64)) {
+        flt4 v[NTT][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int h = 0; h < NTT; ++h) v[h][u] = *(const flt4 *)(col[h] + r0 + 16 * u);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                int q = 0;
+#pragma unroll
+                for (int ta = 0; ta < NTT; ++ta)
+#pragma unroll
+                    for (int tc = ta; tc < NTT; ++tc, ++q) acc[q] = mfma16(v[ta][u][t], v[tc][u][t], acc[q]);
+            }
+    }
+    // lane l, element e of tile q holds G entry (4 (l / 16) + e, l % 16) of q
+#pragma unroll
+    for (int q = 0; q < NUT; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) red[w][q][lane * 4 + e] = acc[q][e];
+    __syncthreads();
+    float *out = Gp + ((size_t)pair * nchunk + chunk) * B2 * B2;
+    for (int idx = tid; idx < NUT * 256; idx += JR_NT) {
+        const int q = idx >> 8, jl = (idx >> 4) & 15, il = idx & 15;
+        int ta = 0, qq = q;
+        while (qq >= NTT - ta) { qq -= NTT - ta; ++ta; }
+        const int tc = ta + qq;
+        const int src = ((il >> 2) * 16 + jl) * 4 + (il & 3);
+        const float s = ((red[0][q][src] + red[1][q][src]) + red[2][q][src]) + red[3][q][src];
+        out[(16 * ta + il) + (16 * tc + jl) * B2] = s;
     }
 }
 
@@ -428,8 +505,6 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
 // slab is loaded into registers while the current one is multiplied.
 template <typename T>
 struct UpdSlab { static constexpr int SL = 32; };
-template <>
-struct UpdSlab<float> { static constexpr int SL = 64; };
 
 template <typename T, int B2>
 __global__ __launch_bounds__(JR_NT) void jac_update(int N, int nblk, int r, T *__restrict__ Y,
@@ -457,7 +532,7 @@ __global__ __launch_bounds__(JR_NT) void jac_update(int N, int nblk, int r, T *_
     int ld, chunk;
     if ((int)blockIdx.y < nchY) { M = Y; ld = ldy; chunk = blockIdx.y; }
     else { M = V; ld = ldv; chunk = blockIdx.y - nchY; }
-    const int rbeg = chunk * JR_RG, rend = min(N, rbeg + JR_RG);
+    const int rbeg = chunk * JTile<T>::UPD_RG, rend = min(N, rbeg + JTile<T>::UPD_RG);
     // this thread's slab elements: column e / SL, row e % SL
     size_t coff[PER];
     int crow[PER];
@@ -518,10 +593,82 @@ __global__ __launch_bounds__(JR_NT) void jac_update(int N, int nblk, int r, T *_
     }
 }
 
+// FP32 update without LDS.  Each wavefront owns a 64-row stripe of the
+// chunk and forms its transpose, [Y_I Y_J]^T <- W^T [Y_I Y_J]^T, on the matrix
+// cores: W^T is the A operand (held in registers for the whole launch) and the
+// stripe, read as 16-byte vectors, the B operand.  The MFMA sums over k in
+// any order, and its column index is free as well: lane j of a 16-lane group
+// reads rows 4j..4j+3 of one column, and element t of that vector feeds the
+// product of column tile t (stripe rows 4j + t).  With the FP32 accumulator
+// layout (lane l holds rows 4 (l / 16) + e of column l % 16) lane l ends up
+// with rows 4 (l % 16) .. + 3 of output columns 4 (l / 16) + e, so both the
+// reads and the writes cover 256 contiguous bytes of a column per 16 lanes.
+// The k index of step s on lane group g is column (B2/4) g + s, which keeps
+// each lane's W entries contiguous (two 16-byte reads per 16-column tile).
+// Requires N a multiple of 64 (whole stripes) and 16-byte aligned columns.
+template <int B2>
+__global__ __launch_bounds__(JR_NT) void jac_update_f32(int N, int nblk, int r, float *__restrict__ Y,
+                                                        int ldy, float *__restrict__ V, int ldv,
+                                                        int nchY, const float *__restrict__ Wm,
+                                                        const int *__restrict__ skip) {
+    constexpr int b = B2 / 2, KS = B2 / 4, NTI = B2 / 16;
+    static_assert(KS % 4 == 0 && b % KS == 0, "k mapping");
+    const int pair = blockIdx.x;
+    if (skip[pair]) return;
+    int I, J;
+    rr_slot(nblk, r, pair, &I, &J);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, li = lane & 15;
+    float *M;
+    int ld, chunk;
+    if ((int)blockIdx.y < nchY) { M = Y; ld = ldy; chunk = blockIdx.y; }
+    else { M = V; ld = ldv; chunk = blockIdx.y - nchY; }
+    const int rbeg = chunk * JTile<float>::UPD_RG, rend = min(N, rbeg + JTile<float>::UPD_RG);
+    // A operand: wr[ti][s] = W[KS g + s][16 ti + li] (W column-major, B2 x B2)
+    const float *wsrc = Wm + (size_t)pair * B2 * B2;
+    float wr[NTI][KS];
+#pragma unroll
+    for (int ti = 0; ti < NTI; ++ti)
+#pragma unroll
+        for (int s4 = 0; s4 < KS / 4; ++s4) {
+            const flt4 v = *(const flt4 *)(wsrc + (size_t)(16 * ti + li) * B2 + KS * g + 4 * s4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) wr[ti][4 * s4 + q] = v[q];
+        }
+    // lane group g reads columns KS g .. KS g + KS - 1 of the pair, all in
+    // one of the two blocks
+    const int c0 = KS * g;
+    const float *ag = M + (size_t)(c0 < b ? I * b + c0 : J * b + c0 - b) * ld;
+    for (int r0 = rbeg + 64 * w; r0 + 64 <= rend; r0 += 64 * (JR_NT / 64)) {
+        flt4 a[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) a[s] = *(const flt4 *)(ag + (size_t)s * ld + r0 + 4 * li);
+        flt4 acc[4][NTI];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int ti = 0; ti < NTI; ++ti) acc[t][ti] = flt4{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int ti = 0; ti < NTI; ++ti) acc[t][ti] = mfma16(wr[ti][s], a[s][t], acc[t][ti]);
+#pragma unroll
+        for (int ti = 0; ti < NTI; ++ti)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int c = 16 * ti + 4 * g + e;
+                *(flt4 *)(M + (size_t)blk_col(c, b, I, J) * ld + r0 + 4 * li) =
+                    flt4{acc[0][ti][e], acc[1][ti][e], acc[2][ti][e], acc[3][ti][e]};
+            }
+    }
+}
+
 size_t jacobi_scratch_bytes(int N, int b, int elem) {
     const int B2 = 2 * b;
     const int npairs = N / B2;
-    const int nch = cdiv(N, JR_RGG);
+    const int nch = gram_chunks(N, elem);
     size_t bytes = (size_t)npairs * nch * B2 * B2 * elem;   // gram partials
     bytes += (size_t)npairs * B2 * B2 * elem;                // W blocks
     bytes += (size_t)npairs * sizeof(int) + 256;             // skip flags
@@ -533,7 +680,7 @@ size_t jacobi_scratch_bytes(int N, int b, int elem) {
 void jacobi_carve(JacobiWork &jw, char *base, int N, int b, int elem) {
     const int B2 = 2 * b;
     const int npairs = N / B2;
-    const int nch = cdiv(N, JR_RGG);
+    const int nch = gram_chunks(N, elem);
     char *p = base;
     jw.gram = p; p += (size_t)npairs * nch * B2 * B2 * elem;
     jw.wmat = p; p += (size_t)npairs * B2 * B2 * elem;
@@ -550,8 +697,8 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
     constexpr int b = B2 / 2;
     const int nblk = ncols / b;
     const int npairs = nblk / 2;
-    const int nch = cdiv(N, JR_RG);
-    const int nchG = cdiv(N, JR_RGG);
+    const int nch = cdiv(N, JTile<T>::UPD_RG);
+    const int nchG = gram_chunks(N, (int)sizeof(T));
     const int nchV = V ? nch : 0;
     *conv = 0;
     int sw = 0;
@@ -583,12 +730,22 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
             // optional per-launch clock: events recorded by the dispatch itself
             hipEvent_t e0, e1;
             const int cross = (jw.cross_pairs && r > 0) ? 1 : 0;
-            if (jw.kc && jw.kc->slot(kbase + 0, gram_bytes, gram_flops, &e0, &e1))
-                hipExtLaunchKernelGGL((jac_gram<T, B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, e0, e1,
-                                      0, N, nblk, r, (const T *)Y, N, (T *)jw.gram, nchG);
-            else
-                hipLaunchKernelGGL((jac_gram<T, B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, N, nblk, r,
-                                   Y, N, (T *)jw.gram, nchG);
+            const bool gclk = jw.kc && jw.kc->slot(kbase + 0, gram_bytes, gram_flops, &e0, &e1);
+            if constexpr (sizeof(T) == 4) {
+                if (gclk)
+                    hipExtLaunchKernelGGL((jac_gram_f32<B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, e0,
+                                          e1, 0, N, nblk, r, (const T *)Y, N, (T *)jw.gram, nchG);
+                else
+                    hipLaunchKernelGGL((jac_gram_f32<B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, N, nblk,
+                                       r, (const T *)Y, N, (T *)jw.gram, nchG);
+            } else {
+                if (gclk)
+                    hipExtLaunchKernelGGL((jac_gram<T, B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, e0, e1,
+                                          0, N, nblk, r, (const T *)Y, N, (T *)jw.gram, nchG);
+                else
+                    hipLaunchKernelGGL((jac_gram<T, B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, N, nblk,
+                                       r, (const T *)Y, N, (T *)jw.gram, nchG);
+            }
             if (jw.kc && jw.kc->slot(kbase + 1, 0.0, inner_flops, &e0, &e1))
                 hipExtLaunchKernelGGL((jac_inner<T, B2, INNER_NT>), dim3(npairs), dim3(INNER_NT), 0, s,
                                       e0, e1, 0, nchG, (const T *)jw.gram, (T *)jw.wmat, jw.skip,
@@ -597,14 +754,27 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
                 hipLaunchKernelGGL((jac_inner<T, B2, INNER_NT>), dim3(npairs), dim3(INNER_NT), 0, s,
                                    nchG, (const T *)jw.gram, (T *)jw.wmat, jw.skip, jw.flag, eps,
                                    max_inner, cross, jw.rcount + r);
-            if (jw.kc && jw.kc->slot(kbase + 2, upd_bytes, upd_flops, &e0, &e1)) {
-                upd_slots.push_back({jw.kc->used / 2 - 1, r});
-                hipExtLaunchKernelGGL((jac_update<T, B2>), dim3(npairs, nch + nchV), dim3(JR_NT), 0, s,
-                                      e0, e1, 0, N, nblk, r, Y, N, V, N, nch, (const T *)jw.wmat,
-                                      (const int *)jw.skip);
-            } else
-                hipLaunchKernelGGL((jac_update<T, B2>), dim3(npairs, nch + nchV), dim3(JR_NT), 0, s, N,
-                                   nblk, r, Y, N, V, N, nch, (const T *)jw.wmat, jw.skip);
+            const bool clk = jw.kc && jw.kc->slot(kbase + 2, upd_bytes, upd_flops, &e0, &e1);
+            if (clk) upd_slots.push_back({jw.kc->used / 2 - 1, r});
+            if constexpr (sizeof(T) == 4) {
+                const dim3 ugrid(npairs, nch + nchV);
+                if (clk)
+                    hipExtLaunchKernelGGL((jac_update_f32<B2>), ugrid, dim3(JR_NT), 0, s, e0, e1, 0, N,
+                                          nblk, r, Y, N, V, N, nch, (const T *)jw.wmat,
+                                          (const int *)jw.skip);
+                else
+                    hipLaunchKernelGGL((jac_update_f32<B2>), ugrid, dim3(JR_NT), 0, s, N, nblk, r, Y, N,
+                                       V, N, nch, (const T *)jw.wmat, (const int *)jw.skip);
+            } else {
+                const dim3 ugrid(npairs, nch + nchV);
+                if (clk)
+                    hipExtLaunchKernelGGL((jac_update<T, B2>), ugrid, dim3(JR_NT), 0, s, e0, e1, 0, N,
+                                          nblk, r, Y, N, V, N, nch, (const T *)jw.wmat,
+                                          (const int *)jw.skip);
+                else
+                    hipLaunchKernelGGL((jac_update<T, B2>), ugrid, dim3(JR_NT), 0, s, N, nblk, r, Y, N,
+                                       V, N, nch, (const T *)jw.wmat, (const int *)jw.skip);
+            }
         }
         e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(jw.hflag, jw.flag, 3 * sizeof(int), hipMemcpyDeviceToHost, s);
@@ -642,6 +812,11 @@ int jacobi_sweeps_cols(hipStream_t s, int N, int ncols, int b, T *Y, T *V, doubl
                        int max_inner, JacobiWork &jw, int *conv) {
     if (ncols <= 0 || ncols > N || ncols % (2 * b) != 0) {
         note_hip_error(hipErrorInvalidValue, "jacobi_sweeps_cols: column count");
+        return -1;
+    }
+    // the update works on whole 64-row stripes with 16-byte column accesses
+    if (N % 64 != 0) {
+        note_hip_error(hipErrorInvalidValue, "jacobi_sweeps_cols: row count not a multiple of 64");
         return -1;
     }
     if (b == 16) return sweeps_impl<T, 32, 256>(s, N, ncols, Y, V, eps, maxsweep, max_inner, jw, conv);
