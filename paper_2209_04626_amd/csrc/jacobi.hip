@@ -31,101 +31,27 @@ namespace mpj {
 
 constexpr int JR_NT = 256;   // threads per workgroup
 
-// Row tiling per precision: rows per workgroup of the Gram kernel (each
-// workgroup writes one partial Gram block, so fewer rows mean more partials
-// to reduce), rows staged in LDS per step of the Gram kernel, and rows per
-// workgroup of the update (no partials: smaller chunks only add workgroups).
-template <typename T> struct JTile;
-template <> struct JTile<float> {
-    static constexpr int GRAM_RG = 512, GRAM_SLAB = 32, UPD_RG = 256;
-};
-template <> struct JTile<double> {
-    static constexpr int GRAM_RG = 256, GRAM_SLAB = 32, UPD_RG = 256;
-};
-inline int gram_chunks(int N, int elem) {
-    return cdiv(N, elem == 4 ? JTile<float>::GRAM_RG : JTile<double>::GRAM_RG);
+constexpr int JU_RG = 256;   // rows per workgroup of the update
+
+// Rows per workgroup of the Gram kernels: a quarter of N in whole 64-row
+// stripes, between 256 and 1024.  Each workgroup writes one partial Gram
+// block that the inner solve reduces, so long chunks save the reduction and
+// the per-workgroup set-up (at n = 4096: 4 partials per pair instead of 16);
+// the lower bound keeps enough workgroups in flight for small N.
+inline int gram_rows(int N) {
+    const int rg = (N / 4) / 64 * 64;
+    return rg < 256 ? 256 : (rg > 1024 ? 1024 : rg);
 }
+inline int gram_chunks(int N) { return cdiv(N, gram_rows(N)); }
 
 __device__ __forceinline__ int blk_col(int c, int b, int I, int J) {
     return c < b ? I * b + c : J * b + (c - b);
 }
 
-// Partial Gram block of one row chunk.  Only the 16 x 16 tiles on or above
-// the block diagonal are formed (G is symmetric; the inner solve reads the
-// upper triangle).  The next 32-row slab is loaded into registers while the
-// matrix cores work on the current one.
-template <typename T, int B2>
-__global__ __launch_bounds__(JR_NT) void jac_gram(int N, int nblk, int r, const T *__restrict__ Y,
-                                                  int ldy, T *__restrict__ Gp, int nchunk) {
-    constexpr int b = B2 / 2;
-    constexpr int JR_SLAB = JTile<T>::GRAM_SLAB, JR_RGG = JTile<T>::GRAM_RG;
-    constexpr int NTT = B2 / 16;                       // tiles per dimension
-    constexpr int NUT = NTT * (NTT + 1) / 2;           // upper-triangle tiles
-    constexpr int TPW = (NUT + 3) / 4;
-    constexpr int PER = B2 * JR_SLAB / JR_NT;          // slab elements per thread
-    __shared__ T Ps[B2][JR_SLAB + 1];
-    const int pair = blockIdx.x, chunk = blockIdx.y;
-    int I, J;
-    rr_slot(nblk, r, pair, &I, &J);
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    // this wavefront's tiles (ti <= tj), enumerated row by row
-    int tI[TPW], tJ[TPW];
-#pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-        int u = w + 4 * q, ti = 0;
-        while (u >= NTT - ti && ti < NTT) { u -= NTT - ti; ++ti; }
-        tI[q] = ti; tJ[q] = ti + u;
-    }
-    typedef typename acc4<T>::type V4;
-    V4 acc[TPW];
-#pragma unroll
-    for (int q = 0; q < TPW; ++q) acc[q] = V4{0, 0, 0, 0};
-    const int rbeg = chunk * JR_RGG, rend = min(N, rbeg + JR_RGG);
-    T pf[PER];
-    auto fetch = [&](int r0) {
-#pragma unroll
-        for (int e0 = 0; e0 < PER; ++e0) {
-            const int e = tid + e0 * JR_NT;
-            const int c = e / JR_SLAB, rr = e % JR_SLAB;
-            const int gi = r0 + rr;
-            pf[e0] = gi < rend ? Y[(size_t)blk_col(c, b, I, J) * ldy + gi] : T(0);
-        }
-    };
-    fetch(rbeg);
-    for (int r0 = rbeg; r0 < rend; r0 += JR_SLAB) {
-        __syncthreads();
-#pragma unroll
-        for (int e0 = 0; e0 < PER; ++e0) {
-            const int e = tid + e0 * JR_NT;
-            Ps[e / JR_SLAB][e % JR_SLAB] = pf[e0];
-        }
-        __syncthreads();
-        if (r0 + JR_SLAB < rend) fetch(r0 + JR_SLAB);
-#pragma unroll
-        for (int kk = 0; kk < JR_SLAB; kk += 4) {
-#pragma unroll
-            for (int q = 0; q < TPW; ++q) {
-                if (w + 4 * q < NUT) {
-                    const T a = Ps[16 * tI[q] + lane % 16][kk + lane / 16];
-                    const T bb = Ps[16 * tJ[q] + lane % 16][kk + lane / 16];
-                    acc[q] = mfma16(a, bb, acc[q]);
-                }
-            }
-        }
-    }
-    T *out = Gp + ((size_t)pair * nchunk + chunk) * B2 * B2;
-#pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-        if (w + 4 * q < NUT) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int i = 16 * tI[q] + mfma_row<T>(lane, e), j = 16 * tJ[q] + lane % 16;
-                out[i + j * B2] = acc[q][e];
-            }
-        }
-    }
-}
-
+// Partial Gram blocks.  Only the 16 x 16 tiles on or above the block
+// diagonal are formed (G is symmetric; the inner solve reads the upper
+// triangle), one partial block per row chunk.
+//
 // FP32 partial Gram block without staging the columns in LDS.  Each
 // wavefront owns 64-row stripes of the chunk.  Lane (g, i) of the wavefront
 // (g = lane / 16, i = lane % 16) reads, for every 16-column tile h of the pair
@@ -137,11 +63,10 @@ __global__ __launch_bounds__(JR_NT) void jac_gram(int N, int nblk, int r, const 
 // partial tiles are then summed in a fixed order through LDS.
 template <int B2>
 __global__ __launch_bounds__(JR_NT) void jac_gram_f32(int N, int nblk, int r, const float *__restrict__ Y,
-                                                      int ldy, float *__restrict__ Gp, int nchunk) {
+                                                      int ldy, float *__restrict__ Gp, int nchunk, int RG) {
     constexpr int b = B2 / 2;
     constexpr int NTT = B2 / 16;                       // tiles per dimension
     constexpr int NUT = NTT * (NTT + 1) / 2;           // upper-triangle tiles
-    constexpr int RG = JTile<float>::GRAM_RG;
     __shared__ float red[4][NUT][256];
     const int pair = blockIdx.x, chunk = blockIdx.y;
     int I, J;
@@ -187,6 +112,72 @@ __global__ __launch_bounds__(JR_NT) void jac_gram_f32(int N, int nblk, int r, co
         const int src = ((il >> 2) * 16 + jl) * 4 + (il & 3);
         const float s = ((red[0][q][src] + red[1][q][src]) + red[2][q][src]) + red[3][q][src];
         out[(16 * ta + il) + (16 * tc + jl) * B2] = s;
+    }
+}
+
+// FP64 partial Gram block in the same register-direct form: a stripe is 32
+// rows, lane (g, i) reads rows 8 u + 2 g, + 1 of column 16 h + i as one
+// 16-byte vector (u = 0..3), and element t is row k = (u, t) of the MFMA step
+// for both operands.  Every wavefront forms all upper tiles over its own
+// rows (an even split of the MFMA work); the four partial tiles are added in
+// wavefront order through one LDS buffer.
+template <int B2>
+__global__ __launch_bounds__(JR_NT) void jac_gram_f64(int N, int nblk, int r, const double *__restrict__ Y,
+                                                      int ldy, double *__restrict__ Gp, int nchunk, int RG) {
+    constexpr int b = B2 / 2;
+    constexpr int NTT = B2 / 16;                       // tiles per dimension
+    constexpr int NUT = NTT * (NTT + 1) / 2;           // upper-triangle tiles
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    __shared__ double red[NUT][256];
+    const int pair = blockIdx.x, chunk = blockIdx.y;
+    int I, J;
+    rr_slot(nblk, r, pair, &I, &J);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int g = lane >> 4, li = lane & 15;
+    const double *col[NTT];
+#pragma unroll
+    for (int h = 0; h < NTT; ++h) col[h] = Y + (size_t)blk_col(16 * h + li, b, I, J) * ldy + 2 * g;
+    dbl4 acc[NUT];
+#pragma unroll
+    for (int q = 0; q < NUT; ++q) acc[q] = dbl4{0, 0, 0, 0};
+    const int rbeg = chunk * RG, rend = min(N, rbeg + RG);
+    for (int r0 = rbeg + 32 * w; r0 + 32 <= rend; r0 += 32 * (JR_NT / 64)) {
+        d2 v[NTT][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int h = 0; h < NTT; ++h) v[h][u] = *(const d2 *)(col[h] + r0 + 8 * u);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                int q = 0;
+#pragma unroll
+                for (int ta = 0; ta < NTT; ++ta)
+#pragma unroll
+                    for (int tc = ta; tc < NTT; ++tc, ++q) acc[q] = mfma16(v[ta][u][t], v[tc][u][t], acc[q]);
+            }
+    }
+    // lane l, element e of tile q holds G entry (l / 16 + 4 e, l % 16) of q;
+    // the partials are summed as ((w0 + w1) + w2) + w3
+#pragma unroll
+    for (int wv = 0; wv < 4; ++wv) {
+        if (w == wv) {
+#pragma unroll
+            for (int q = 0; q < NUT; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    red[q][lane * 4 + e] = wv == 0 ? acc[q][e] : red[q][lane * 4 + e] + acc[q][e];
+        }
+        __syncthreads();
+    }
+    double *out = Gp + ((size_t)pair * nchunk + chunk) * B2 * B2;
+    for (int idx = tid; idx < NUT * 256; idx += JR_NT) {
+        const int q = idx >> 8, jl = (idx >> 4) & 15, il = idx & 15;
+        int ta = 0, qq = q;
+        while (qq >= NTT - ta) { qq -= NTT - ta; ++ta; }
+        const int tc = ta + qq;
+        out[(16 * ta + il) + (16 * tc + jl) * B2] = red[q][((il & 3) * 16 + jl) * 4 + (il >> 2)];
     }
 }
 
@@ -499,100 +490,6 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
     }
 }
 
-// [Y_I Y_J] <- [Y_I Y_J] W (and V) on one row chunk: slabs of SL rows are
-// loaded coalesced (one column segment per group of lanes), multiplied by W on
-// the matrix cores, staged back through LDS and stored coalesced.  The next
-// slab is loaded into registers while the current one is multiplied.
-template <typename T>
-struct UpdSlab { static constexpr int SL = 32; };
-
-template <typename T, int B2>
-__global__ __launch_bounds__(JR_NT) void jac_update(int N, int nblk, int r, T *__restrict__ Y,
-                                                    int ldy, T *__restrict__ V, int ldv,
-                                                    int nchY, const T *__restrict__ Wm,
-                                                    const int *__restrict__ skip) {
-    constexpr int SL = UpdSlab<T>::SL;
-    constexpr int b = B2 / 2;
-    constexpr int NTI = SL / 16, NTJ = B2 / 16;  // row and column tiles of a slab
-    constexpr int NTL = NTI * NTJ;
-    constexpr int TPW = NTL / 4;
-    constexpr int PER = B2 * SL / JR_NT;
-    static_assert(TPW * 4 == NTL && PER * JR_NT == B2 * SL, "tiling");
-    __shared__ T Ws[B2][B2 + 1];
-    __shared__ T Ps[B2][SL + 1];
-    __shared__ T Os[B2][SL + 1];
-    const int pair = blockIdx.x;
-    if (skip[pair]) return;
-    int I, J;
-    rr_slot(nblk, r, pair, &I, &J);
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const T *wsrc = Wm + (size_t)pair * B2 * B2;
-    for (int e = tid; e < B2 * B2; e += JR_NT) Ws[e % B2][e / B2] = wsrc[e];
-    T *M;
-    int ld, chunk;
-    if ((int)blockIdx.y < nchY) { M = Y; ld = ldy; chunk = blockIdx.y; }
-    else { M = V; ld = ldv; chunk = blockIdx.y - nchY; }
-    const int rbeg = chunk * JTile<T>::UPD_RG, rend = min(N, rbeg + JTile<T>::UPD_RG);
-    // this thread's slab elements: column e / SL, row e % SL
-    size_t coff[PER];
-    int crow[PER];
-#pragma unroll
-    for (int e0 = 0; e0 < PER; ++e0) {
-        const int e = tid + e0 * JR_NT;
-        coff[e0] = (size_t)blk_col(e / SL, b, I, J) * ld;
-        crow[e0] = e % SL;
-    }
-    typedef typename acc4<T>::type V4;
-    T pf[PER];
-    auto fetch = [&](int r0) {
-#pragma unroll
-        for (int e0 = 0; e0 < PER; ++e0) {
-            const int gi = r0 + crow[e0];
-            pf[e0] = gi < rend ? M[coff[e0] + gi] : T(0);
-        }
-    };
-    fetch(rbeg);
-    for (int r0 = rbeg; r0 < rend; r0 += SL) {
-        __syncthreads();
-#pragma unroll
-        for (int e0 = 0; e0 < PER; ++e0) {
-            const int e = tid + e0 * JR_NT;
-            Ps[e / SL][e % SL] = pf[e0];
-        }
-        __syncthreads();
-        if (r0 + SL < rend) fetch(r0 + SL);
-        V4 acc[TPW];
-#pragma unroll
-        for (int q = 0; q < TPW; ++q) acc[q] = V4{0, 0, 0, 0};
-#pragma unroll
-        for (int kk = 0; kk < B2; kk += 4) {
-#pragma unroll
-            for (int q = 0; q < TPW; ++q) {
-                const int tile = w + 4 * q;
-                const int ti = tile % NTI, tj = tile / NTI;
-                const T a = Ps[kk + lane / 16][16 * ti + lane % 16];
-                const T bb = Ws[kk + lane / 16][16 * tj + lane % 16];
-                acc[q] = mfma16(a, bb, acc[q]);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-            const int tile = w + 4 * q;
-            const int ti = tile % NTI, tj = tile / NTI;
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                Os[16 * tj + lane % 16][16 * ti + mfma_row<T>(lane, e)] = acc[q][e];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int e0 = 0; e0 < PER; ++e0) {
-            const int e = tid + e0 * JR_NT;
-            const int gi = r0 + crow[e0];
-            if (gi < rend) M[coff[e0] + gi] = Os[e / SL][e % SL];
-        }
-    }
-}
-
 // FP32 update without LDS.  Each wavefront owns a 64-row stripe of the
 // chunk and forms its transpose, [Y_I Y_J]^T <- W^T [Y_I Y_J]^T, on the matrix
 // cores: W^T is the A operand (held in registers for the whole launch) and the
@@ -623,7 +520,7 @@ __global__ __launch_bounds__(JR_NT) void jac_update_f32(int N, int nblk, int r, 
     int ld, chunk;
     if ((int)blockIdx.y < nchY) { M = Y; ld = ldy; chunk = blockIdx.y; }
     else { M = V; ld = ldv; chunk = blockIdx.y - nchY; }
-    const int rbeg = chunk * JTile<float>::UPD_RG, rend = min(N, rbeg + JTile<float>::UPD_RG);
+    const int rbeg = chunk * JU_RG, rend = min(N, rbeg + JU_RG);
     // A operand: wr[ti][s] = W[KS g + s][16 ti + li] (W column-major, B2 x B2)
     const float *wsrc = Wm + (size_t)pair * B2 * B2;
     float wr[NTI][KS];
@@ -665,10 +562,79 @@ __global__ __launch_bounds__(JR_NT) void jac_update_f32(int N, int nblk, int r, 
     }
 }
 
+// FP64 update in the same transposed form: W^T (the A operand) is read from
+// LDS, the stripe (the B operand) straight from 16-byte loads.  A stripe is
+// 32 rows: lane j of a 16-lane group reads rows 2j, 2j + 1 of one column, and
+// element t feeds column tile t of the product.  With the FP64 accumulator
+// layout (lane l holds rows l / 16 + 4 e of column l % 16), lane l ends up
+// with rows 2 (l % 16), + 1 of output columns l / 16 + 4 e: 256 contiguous
+// bytes per column per 16 lanes, read and written.
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+template <int B2>
+__global__ __launch_bounds__(JR_NT, 2) void jac_update_f64(int N, int nblk, int r, double *__restrict__ Y,
+                                                        int ldy, double *__restrict__ V, int ldv,
+                                                        int nchY, const double *__restrict__ Wm,
+                                                        const int *__restrict__ skip) {
+    constexpr int b = B2 / 2, KS = B2 / 4, NTI = B2 / 16, LDW = B2 + 1;
+    constexpr int RG = JU_RG;
+    constexpr int TP = NTI > 2 ? 2 : NTI;
+    static_assert(b % KS == 0, "k mapping");
+    __shared__ double Ws[B2 * LDW];   // Ws[j LDW + k] = W[k][j]
+    const int pair = blockIdx.x;
+    if (skip[pair]) return;
+    int I, J;
+    rr_slot(nblk, r, pair, &I, &J);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int g = lane >> 4, li = lane & 15;
+    const double *wsrc = Wm + (size_t)pair * B2 * B2;   // column-major B2 x B2
+    for (int e = tid; e < B2 * B2; e += JR_NT) Ws[(e / B2) * LDW + e % B2] = wsrc[e];
+    __syncthreads();
+    double *M;
+    int ld, chunk;
+    if ((int)blockIdx.y < nchY) { M = Y; ld = ldy; chunk = blockIdx.y; }
+    else { M = V; ld = ldv; chunk = blockIdx.y - nchY; }
+    const int rbeg = chunk * RG, rend = min(N, rbeg + RG);
+    // lane group g reads columns KS g .. KS g + KS - 1 of the pair, all in
+    // one of the two blocks
+    const int c0 = KS * g;
+    const double *ag = M + (size_t)(c0 < b ? I * b + c0 : J * b + c0 - b) * ld;
+    const double *wl = Ws + li * LDW + c0;
+    for (int r0 = rbeg + 32 * w; r0 + 32 <= rend; r0 += 32 * (JR_NT / 64)) {
+        dbl2 a[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) a[s] = *(const dbl2 *)(ag + (size_t)s * ld + r0 + 2 * li);
+        // output column tiles in passes of TP (register pressure)
+#pragma unroll
+        for (int t0 = 0; t0 < NTI; t0 += TP) {
+            dbl4 acc[2][TP];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int ti = 0; ti < TP; ++ti) acc[t][ti] = dbl4{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int ti = 0; ti < TP; ++ti) {
+                    const double wv = wl[16 * (t0 + ti) * LDW + s];
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) acc[t][ti] = mfma16(wv, a[s][t], acc[t][ti]);
+                }
+#pragma unroll
+            for (int ti = 0; ti < TP; ++ti)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int c = 16 * (t0 + ti) + g + 4 * e;
+                    *(dbl2 *)(M + (size_t)blk_col(c, b, I, J) * ld + r0 + 2 * li) =
+                        dbl2{acc[0][ti][e], acc[1][ti][e]};
+                }
+        }
+    }
+}
+
 size_t jacobi_scratch_bytes(int N, int b, int elem) {
     const int B2 = 2 * b;
     const int npairs = N / B2;
-    const int nch = gram_chunks(N, elem);
+    const int nch = gram_chunks(N);
     size_t bytes = (size_t)npairs * nch * B2 * B2 * elem;   // gram partials
     bytes += (size_t)npairs * B2 * B2 * elem;                // W blocks
     bytes += (size_t)npairs * sizeof(int) + 256;             // skip flags
@@ -680,7 +646,7 @@ size_t jacobi_scratch_bytes(int N, int b, int elem) {
 void jacobi_carve(JacobiWork &jw, char *base, int N, int b, int elem) {
     const int B2 = 2 * b;
     const int npairs = N / B2;
-    const int nch = gram_chunks(N, elem);
+    const int nch = gram_chunks(N);
     char *p = base;
     jw.gram = p; p += (size_t)npairs * nch * B2 * B2 * elem;
     jw.wmat = p; p += (size_t)npairs * B2 * B2 * elem;
@@ -697,8 +663,8 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
     constexpr int b = B2 / 2;
     const int nblk = ncols / b;
     const int npairs = nblk / 2;
-    const int nch = cdiv(N, JTile<T>::UPD_RG);
-    const int nchG = gram_chunks(N, (int)sizeof(T));
+    const int nch = cdiv(N, JU_RG);
+    const int rgG = gram_rows(N), nchG = gram_chunks(N);
     const int nchV = V ? nch : 0;
     *conv = 0;
     int sw = 0;
@@ -734,17 +700,17 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
             if constexpr (sizeof(T) == 4) {
                 if (gclk)
                     hipExtLaunchKernelGGL((jac_gram_f32<B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, e0,
-                                          e1, 0, N, nblk, r, (const T *)Y, N, (T *)jw.gram, nchG);
+                                          e1, 0, N, nblk, r, (const T *)Y, N, (T *)jw.gram, nchG, rgG);
                 else
                     hipLaunchKernelGGL((jac_gram_f32<B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, N, nblk,
-                                       r, (const T *)Y, N, (T *)jw.gram, nchG);
+                                       r, (const T *)Y, N, (T *)jw.gram, nchG, rgG);
             } else {
                 if (gclk)
-                    hipExtLaunchKernelGGL((jac_gram<T, B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, e0, e1,
-                                          0, N, nblk, r, (const T *)Y, N, (T *)jw.gram, nchG);
+                    hipExtLaunchKernelGGL((jac_gram_f64<B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, e0,
+                                          e1, 0, N, nblk, r, (const T *)Y, N, (T *)jw.gram, nchG, rgG);
                 else
-                    hipLaunchKernelGGL((jac_gram<T, B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, N, nblk,
-                                       r, (const T *)Y, N, (T *)jw.gram, nchG);
+                    hipLaunchKernelGGL((jac_gram_f64<B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, N, nblk,
+                                       r, (const T *)Y, N, (T *)jw.gram, nchG, rgG);
             }
             if (jw.kc && jw.kc->slot(kbase + 1, 0.0, inner_flops, &e0, &e1))
                 hipExtLaunchKernelGGL((jac_inner<T, B2, INNER_NT>), dim3(npairs), dim3(INNER_NT), 0, s,
@@ -768,11 +734,11 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
             } else {
                 const dim3 ugrid(npairs, nch + nchV);
                 if (clk)
-                    hipExtLaunchKernelGGL((jac_update<T, B2>), ugrid, dim3(JR_NT), 0, s, e0, e1, 0, N,
+                    hipExtLaunchKernelGGL((jac_update_f64<B2>), ugrid, dim3(JR_NT), 0, s, e0, e1, 0, N,
                                           nblk, r, Y, N, V, N, nch, (const T *)jw.wmat,
                                           (const int *)jw.skip);
                 else
-                    hipLaunchKernelGGL((jac_update<T, B2>), ugrid, dim3(JR_NT), 0, s, N, nblk, r, Y, N,
+                    hipLaunchKernelGGL((jac_update_f64<B2>), ugrid, dim3(JR_NT), 0, s, N, nblk, r, Y, N,
                                        V, N, nch, (const T *)jw.wmat, (const int *)jw.skip);
             }
         }
