@@ -271,7 +271,7 @@ __device__ __forceinline__ void coop_columns(std::integer_sequence<int, J...>, d
 
 __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P, int ld,
                                                       double *part, double *head, double *tau,
-                                                      int *flags, int base) {
+                                                      int *flags, int base, double *Vb) {
     __shared__ CoopShared sh;
     const int i = blockIdx.x * QR_RC + threadIdx.x;
     const bool live = i < mp;
@@ -284,6 +284,10 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
 #pragma unroll
     for (int k = 0; k < QR_NB; ++k)
         if (live && k < nb) P[(size_t)k * ld + i] = a[k];
+    // the explicit unit lower trapezoidal V of the panel (ld mp)
+#pragma unroll
+    for (int k = 0; k < QR_NB; ++k)
+        if (live && k < nb) Vb[(size_t)k * mp + i] = i > k ? a[k] : (i == k ? 1.0 : 0.0);
 }
 
 __global__ void qr_flags_zero(int n, int *flags) {
@@ -291,39 +295,46 @@ __global__ void qr_flags_zero(int n, int *flags) {
     if (e < n) flags[e] = 0;
 }
 
-// T (nb x nb upper, zeros below, ld ldt) from G = V^T V (ld QR_NB) and tau:
-// T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j).  One wavefront;
-// lane t keeps row t of T in registers.
+// T (nb x nb upper, zeros below, ld ldt) of the compact-WY form
+// H_0 ... H_{nb-1} = I - V T V^T, from G = V^T V (ld QR_NB) and tau.  T is the
+// inverse of diag(1/tau) + striu(G); the columns of that triangular system
+// are independent, so lane j solves for column j by back substitution,
+// T_jj = tau_j, T_ij = -tau_i sum_{i<k<=j} G_ik T_kj for i = j-1 .. 0, with
+// no exchange between lanes.  A zero tau (an identity reflector) gives a zero
+// row and column, with no division.  The sums run in registers, over the
+// whole column with masked terms, so every lane follows the same unrolled
+// sequence and reads the same entry of G at a time.
 __global__ __launch_bounds__(64) void qr_build_t(int nb, const double *vtv, const double *tau,
                                                  double *T, int ldt) {
     __shared__ double G[QR_NB * QR_NB];
     __shared__ double ts[QR_NB];
-    __shared__ double z[QR_NB];
     const int t = threadIdx.x;
+    // entries of G outside nb x nb are never written by the product: zero them
 #pragma unroll
-    for (int k = 0; k < QR_NB * QR_NB / 64; ++k) G[t + 64 * k] = vtv[t + 64 * k];
+    for (int k = 0; k < QR_NB * QR_NB / 64; ++k) {
+        const int e = t + 64 * k;
+        G[e] = (e % QR_NB < nb && e / QR_NB < nb) ? vtv[e] : 0.0;
+    }
     if (t < QR_NB) ts[t] = t < nb ? tau[t] : 0.0;
     __syncthreads();
-    double tr[QR_NB];
+    const int j = t;
+    double c[QR_NB];
 #pragma unroll
-    for (int l = 0; l < QR_NB; ++l) tr[l] = 0.0;
+    for (int i = 0; i < QR_NB; ++i) c[i] = (i == j && j < nb) ? ts[i] : 0.0;
 #pragma unroll
-    for (int j = 0; j < QR_NB; ++j) {
-        if (j < nb) {
-            const double tj = ts[j];
-            if (t < j) z[t] = -tj * G[j * QR_NB + t];
-            __syncthreads();
-            double acc = 0.0;
+    for (int i = QR_NB - 2; i >= 0; --i) {
+        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-            for (int l = 0; l < j; ++l)
-                if (l >= t) acc += tr[l] * z[l];
-            tr[j] = t < j ? acc : (t == j ? tj : 0.0);
-            __syncthreads();
+        for (int k = i + 1; k < QR_NB; ++k) {
+            // c[k] is zero for k > j, so the masked terms add nothing
+            if ((k - i) & 1) s0 = fma(G[k * QR_NB + i], c[k], s0);
+            else s1 = fma(G[k * QR_NB + i], c[k], s1);
         }
+        if (i < j) c[i] = -ts[i] * (s0 + s1);
     }
-    if (t < QR_NB) {
+    if (j < QR_NB) {
 #pragma unroll
-        for (int l = 0; l < QR_NB; ++l) T[(size_t)l * ldt + t] = tr[l];
+        for (int i = 0; i < QR_NB; ++i) T[(size_t)j * ldt + i] = j < nb ? c[i] : 0.0;
     }
 }
 
@@ -382,15 +393,15 @@ static void panel_factor(hipStream_t s, int mp, int nb, double *P, int ld, doubl
         // algorithmic work: the panel read and written once, 2 mp nb^2 flops
         if (q.kc) q.kc->begin(s, 7, 2.0 * mp * nb * sizeof(double), 2.0 * mp * nb * nb);
         hipLaunchKernelGGL(qr_panel_coop, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.part, q.head,
-                           tau, q.flags, panel * 64);
+                           tau, q.flags, panel * 64, q.vb);
         if (q.kc) q.kc->end(s);
     } else {
         hipLaunchKernelGGL(qr_panel_init, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.part, q.head);
         for (int j = 0; j < nb; ++j)
             hipLaunchKernelGGL(qr_panel_step, dim3(G), dim3(QR_RC), 0, s, j, mp, nb, G, P, ld,
                                q.part, q.head, tau);
+        extract_v(s, mp, nb, P, ld, q.vb);
     }
-    extract_v(s, mp, nb, P, ld, q.vb);
     gemm<double>(s, true, false, nb, nb, mp, 1.0, q.vb, mp, q.vb, mp, 0.0, q.vtv, QR_NB, q.split,
                  q.split_elems, q.kc);
     hipLaunchKernelGGL(qr_build_t, dim3(1), dim3(64), 0, s, nb, q.vtv, tau, T, ldt);

@@ -163,6 +163,31 @@ def test_large_n_pivot_step_fallback(lib):
         assert rel < 1e-11, (mode, rel)
 
 
+def test_gram_chunks_not_multiple_of_256(lib):
+    """n = 1344: the Gram kernels take row chunks of N/4 = 320 rows (five
+    64-row stripes over four wavefronts, ten 32-row FP64 stripes) and a last
+    chunk of 64 rows.  sigma geometric in [1e-3, 1] stands in for the
+    oracle's, as in the n = 4160 case."""
+    import torch
+    n = 1344
+    print(f"case square n={n}", flush=True)
+    rng = np.random.default_rng(1344)
+    s = testmats.sigma_geometric(n, 3.0)
+    A = testmats.compose(testmats.haar(rng, n, n), s, testmats.haar(rng, n, n))
+    At = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    eye = torch.eye(n, dtype=torch.float64, device="cuda")
+    for mode in ("mixed", "plain"):
+        U, S, V, info = lib.svd(At, mode, branch=1 if mode == "mixed" else 0)
+        torch.cuda.synchronize()
+        assert info["status"] == 0, info
+        orth_u = torch.linalg.norm(U.t() @ U - eye).item()
+        orth_v = torch.linalg.norm(V.t() @ V - eye).item()
+        res = (torch.linalg.norm(At - (U * S) @ V.t()) / torch.linalg.norm(At)).item()
+        rel = np.max(np.abs(S.cpu().numpy() - s) / s)
+        assert orth_u <= 1e-13 * n and orth_v <= 1e-13 * n and res <= 1e-14 * n, (mode, orth_u, orth_v, res)
+        assert rel < 1e-11, (mode, rel)
+
+
 def graded(m, n, seed, e=8.0, d=4.0):
     """A = B diag(10^w), w ~ U(-d, 0): badly scaled columns over a B with
     log-uniform sigma (the A = B D family)."""
