@@ -172,17 +172,18 @@ struct JacobiWork {
     void *gram;      // partial Gram blocks
     void *wmat;      // per-pair rotation blocks
     int *skip;       // per-pair "nothing to rotate" flags
-    int *flag;       // device: [0] any rotation this sweep, [1] max relative
-                     // off-diagonal |g_pq| / sqrt(g_pp g_qq) seen, [2] max
-                     // |sin| of the rotations applied (float bits)
+    int *flag;       // device: [0] any rotation this sweep
     int *hflag;      // host copy of flag[0..2]
+    float *offp;     // device, per pair slot: max relative off-diagonal
+                     // |g_pq| / sqrt(g_pp g_qq) seen this sweep
+    float *smxp;     // device, per pair slot: max |sin| applied this sweep
     int n_real = 0;  // columns of the problem (before padding)
     KernelClock *kc = nullptr;
     float *off_hist = nullptr;  // per-sweep max relative off-diagonal (host, 32)
     double stop_off = 0.0;      // also stop once a sweep starts with off <= this
     int cross_pairs = 0;        // 1: after a sweep's first round, rotate only the
                                 // pairs between the two blocks of each block pair
-    int *rcount = nullptr;      // device: block pairs rotated in each round
+    int *rotmap = nullptr;      // device: per round and pair slot, 1 if rotated
 };
 size_t jacobi_scratch_bytes(int N, int b, int elem);
 void jacobi_carve(JacobiWork &j, char *base, int N, int b, int elem);

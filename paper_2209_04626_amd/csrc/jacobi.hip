@@ -17,8 +17,6 @@
 // Applying any orthogonal W keeps the computation rowwise backward stable
 // (the argument of Section 4), and convergence is declared only after a sweep
 // in which no block pair needed a rotation on a freshly computed Gram block.
-#include <string.h>
-
 #include <hip/hip_ext.h>
 
 #include <utility>
@@ -263,7 +261,8 @@ __device__ __forceinline__ bool jac_rot_test(double al, double be, double ga, do
 template <typename T, int B2, int NT>
 __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict__ Gp,
                                                 T *__restrict__ Wm, int *skip, int *flag,
-                                                double eps, int max_inner, int cross, int *rcnt) {
+                                                float *offp, float *smxp, int *rot, double eps,
+                                                int max_inner, int cross) {
     constexpr int LD = B2 + 1;
     constexpr int H = B2 / 2;
     constexpr int M = B2 - 1;
@@ -372,18 +371,24 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
             if (pq > 0.0) offmax = fmaxf(offmax, (float)(fabs(g) / sqrt(pq)));
         }
     }
+    // The per-sweep maxima and the rotated-pair map are kept per pair slot
+    // (this workgroup is the slot's only writer in a launch, and rounds are
+    // ordered launches), so no two workgroups touch the same word: atomics
+    // on one shared word cost several microseconds per launch here.
+    __shared__ float wmx[NT / 64], wsm[NT / 64];
     offmax = wave_max(offmax);
-    if ((tid & 63) == 0 && offmax > 0.f) atomicMax((unsigned int *)(flag + 1), __float_as_uint(offmax));
+    if ((tid & 63) == 0) wmx[tid >> 6] = offmax;
     need = block_or<NT>(need, ired);
-    if (!need) {
-        if (tid == 0) skip[pair] = 1;
-        return;
-    }
     if (tid == 0) {
-        skip[pair] = 0;
-        *flag = 1;
-        atomicAdd(rcnt, 1);   // pairs rotated in this round
+        float m = 0.f;
+#pragma unroll
+        for (int q = 0; q < NT / 64; ++q) m = fmaxf(m, wmx[q]);
+        if (m > offp[pair]) offp[pair] = m;
+        skip[pair] = need ? 0 : 1;
+        rot[pair] = need ? 1 : 0;
+        if (need) *flag = 1;
     }
+    if (!need) return;
 
     // 3. cyclic rounds of disjoint rotations on G, accumulating W = prod J
     const int a = tid % H, cg = tid / H;
@@ -479,7 +484,14 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
     }
 
     smax = wave_max(smax);
-    if ((tid & 63) == 0 && smax > 0.f) atomicMax((unsigned int *)(flag + 2), __float_as_uint(smax));
+    if ((tid & 63) == 0) wsm[tid >> 6] = smax;
+    __syncthreads();
+    if (tid == 0) {
+        float m = 0.f;
+#pragma unroll
+        for (int q = 0; q < NT / 64; ++q) m = fmaxf(m, wsm[q]);
+        if (m > smxp[pair]) smxp[pair] = m;
+    }
 
     // 4. write W (column-major)
     T *wo = Wm + (size_t)pair * B2 * B2;
@@ -639,7 +651,8 @@ size_t jacobi_scratch_bytes(int N, int b, int elem) {
     bytes += (size_t)npairs * B2 * B2 * elem;                // W blocks
     bytes += (size_t)npairs * sizeof(int) + 256;             // skip flags
     bytes += 256;                                             // flag
-    bytes += (size_t)(N / b) * sizeof(int) + 256;            // pairs rotated per round
+    bytes += 2 * ((size_t)npairs * sizeof(float) + 256);     // per-slot maxima
+    bytes += (size_t)(N / b) * npairs * sizeof(int) + 256;   // rotated map per round
     return bytes + 1024;
 }
 
@@ -652,7 +665,9 @@ void jacobi_carve(JacobiWork &jw, char *base, int N, int b, int elem) {
     jw.wmat = p; p += (size_t)npairs * B2 * B2 * elem;
     jw.skip = (int *)p; p += (size_t)npairs * sizeof(int) + 256;
     jw.flag = (int *)p; p += 256;
-    jw.rcount = (int *)p;
+    jw.offp = (float *)p; p += (size_t)npairs * sizeof(float) + 256;
+    jw.smxp = (float *)p; p += (size_t)npairs * sizeof(float) + 256;
+    jw.rotmap = (int *)p;
 }
 
 // Sweeps over the ncols columns of Y (N rows, ld N; ncols a multiple of 2b,
@@ -669,14 +684,16 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
     *conv = 0;
     int sw = 0;
     std::vector<std::pair<size_t, int>> upd_slots;   // clocked update launches (slot, round)
-    std::vector<int> hcount(nblk);
+    std::vector<int> hrot((size_t)nblk * npairs);
+    std::vector<float> hoff(npairs), hsmx(npairs);
     // one rotated pair in the update: its 2b columns of Y (and V) read and
     // written once, 2 N (2b)^2 flops per matrix
     const double pair_upd_bytes = 2.0 * N * B2 * sizeof(T) * (V ? 2 : 1);
     const double pair_upd_flops = 2.0 * N * B2 * B2 * (V ? 2 : 1);
     for (; sw < maxsweep; ++sw) {
         hipError_t e = hipMemsetAsync(jw.flag, 0, 3 * sizeof(int), s);
-        if (e == hipSuccess) e = hipMemsetAsync(jw.rcount, 0, (size_t)nblk * sizeof(int), s);
+        if (e == hipSuccess) e = hipMemsetAsync(jw.offp, 0, (size_t)npairs * sizeof(float), s);
+        if (e == hipSuccess) e = hipMemsetAsync(jw.smxp, 0, (size_t)npairs * sizeof(float), s);
         upd_slots.clear();
         if (e != hipSuccess) { note_hip_error(e, "jacobi flag reset"); return -1; }
         // kernel-class ids for the optional per-launch clock
@@ -715,11 +732,12 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
             if (jw.kc && jw.kc->slot(kbase + 1, 0.0, inner_flops, &e0, &e1))
                 hipExtLaunchKernelGGL((jac_inner<T, B2, INNER_NT>), dim3(npairs), dim3(INNER_NT), 0, s,
                                       e0, e1, 0, nchG, (const T *)jw.gram, (T *)jw.wmat, jw.skip,
-                                      jw.flag, eps, max_inner, cross, jw.rcount + r);
+                                      jw.flag, jw.offp, jw.smxp, jw.rotmap + (size_t)r * npairs, eps,
+                                      max_inner, cross);
             else
                 hipLaunchKernelGGL((jac_inner<T, B2, INNER_NT>), dim3(npairs), dim3(INNER_NT), 0, s,
-                                   nchG, (const T *)jw.gram, (T *)jw.wmat, jw.skip, jw.flag, eps,
-                                   max_inner, cross, jw.rcount + r);
+                                   nchG, (const T *)jw.gram, (T *)jw.wmat, jw.skip, jw.flag, jw.offp,
+                                   jw.smxp, jw.rotmap + (size_t)r * npairs, eps, max_inner, cross);
             const bool clk = jw.kc && jw.kc->slot(kbase + 2, upd_bytes, upd_flops, &e0, &e1);
             if (clk) upd_slots.push_back({jw.kc->used / 2 - 1, r});
             if constexpr (sizeof(T) == 4) {
@@ -744,21 +762,29 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
         }
         e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(jw.hflag, jw.flag, 3 * sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hoff.data(), jw.offp, (size_t)npairs * sizeof(float), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hsmx.data(), jw.smxp, (size_t)npairs * sizeof(float), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess && !upd_slots.empty())
-            e = hipMemcpyAsync(hcount.data(), jw.rcount, (size_t)nblk * sizeof(int), hipMemcpyDeviceToHost, s);
+            e = hipMemcpyAsync(hrot.data(), jw.rotmap, (size_t)(nblk - 1) * npairs * sizeof(int),
+                               hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { note_hip_error(e, "jacobi sweep"); return -1; }
         // a clocked update launch moves the columns of the pairs its round
         // rotated (the others are skipped): its algorithmic bytes and flops
         for (auto &us : upd_slots) {
-            const double k = (double)hcount[us.second];
+            double k = 0.0;
+            for (int q = 0; q < npairs; ++q) k += hrot[(size_t)us.second * npairs + q];
             jw.kc->bytes[us.first] = k * pair_upd_bytes;
             jw.kc->flops[us.first] = k * pair_upd_flops;
         }
         if (jw.kc) jw.kc->collect();
-        float off, smx;
-        memcpy(&off, jw.hflag + 1, sizeof(float));
-        memcpy(&smx, jw.hflag + 2, sizeof(float));
+        float off = 0.f, smx = 0.f;
+        for (int q = 0; q < npairs; ++q) {
+            off = fmaxf(off, hoff[q]);
+            smx = fmaxf(smx, hsmx[q]);
+        }
         if (jw.off_hist && sw < 32) jw.off_hist[sw] = off;
         // Algorithm 1's rule: a sweep without rotations
         if (*jw.hflag == 0) { *conv = 1; ++sw; break; }
