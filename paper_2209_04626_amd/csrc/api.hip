@@ -363,12 +363,22 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
                          q.split_elems, jw.kc);
         }
         qr_factor(s, n, n, Bm, n, tau3, T3, q);
-        set_identity(s, N, Vacc, N);
-        qr_apply_left(s, false, n, n, Bm, n, T3, n, Vacc, N, q);
-        zero_pad_fill(s, N, N, Y, N);
-        gemm<double>(s, false, false, n, n, n, 1.0, o.switch_method == 3 ? A1 : X,
-                     o.switch_method == 3 ? n : N, Vacc, N, 0.0, Y, N, q.split, q.split_elems,
-                     jw.kc);
+        if ((!o.want_v || o.v_method == 1) && o.switch_method != 3) {
+            // V is formed after the sweeps (Section 3.4) or not at all, so Q
+            // itself is not needed: Y = X Q = (Q^T X^T)^T, the reflectors
+            // applied to X^T (U_low's buffer is free once B is formed)
+            transpose64(s, n, n, X, N, Ulow, N);
+            qr_apply_left(s, true, n, n, Bm, n, T3, n, Ulow, N, q);
+            zero_pad_fill(s, N, N, Y, N);
+            transpose64(s, n, n, Ulow, N, Y, N);
+        } else {
+            set_identity(s, N, Vacc, N);
+            qr_apply_left(s, false, n, n, Bm, n, T3, n, Vacc, N, q);
+            zero_pad_fill(s, N, N, Y, N);
+            gemm<double>(s, false, false, n, n, n, 1.0, o.switch_method == 3 ? A1 : X,
+                         o.switch_method == 3 ? n : N, Vacc, N, 0.0, Y, N, q.split, q.split_elems,
+                         jw.kc);
+        }
         tm.mark(6);
     } else {
         MPJ_CHECK(hipMemcpyAsync(Y, X, (size_t)N * N * sizeof(double), hipMemcpyDeviceToDevice, s));

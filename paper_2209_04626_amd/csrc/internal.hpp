@@ -211,6 +211,8 @@ void transpose_upper_to_lower(hipStream_t s, int n, const double *R, int ldr,
                               double *L, int ldl, int Npad);
 void set_identity(hipStream_t s, int N, double *V, int ldv);
 void zero_pad_fill(hipStream_t s, int rows, int cols, double *D, int ldd);
+// B (cols x rows) = A^T (A rows x cols).
+void transpose64(hipStream_t s, int rows, int cols, const double *A, int lda, double *B, int ldb);
 void diag_cond(hipStream_t s, int n, const double *R, int ldr, double *out);
 void col_norms(hipStream_t s, int rows, int n, const double *X, int ldx, double *nrm);
 void count_small(hipStream_t s, int n, const double *nrm, double rel, int *out);

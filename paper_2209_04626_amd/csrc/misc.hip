@@ -83,6 +83,31 @@ void zero_pad_fill(hipStream_t s, int rows, int cols, double *D, int ldd) {
     hipLaunchKernelGGL(k_zero, grid1((size_t)rows * cols), dim3(256), 0, s, rows, cols, D, ldd);
 }
 
+// B (cols x rows, ldb) = A^T (A rows x cols, lda), through 32 x 32 LDS tiles
+// so that both sides are read and written along their columns.
+__global__ __launch_bounds__(256) void k_transpose(int rows, int cols, const double *A, int lda,
+                                                   double *B, int ldb) {
+    __shared__ double tile[32][33];
+    const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+#pragma unroll
+    for (int k = 0; k < 32; k += 8) {
+        const int i = i0 + tx, j = j0 + ty + k;
+        if (i < rows && j < cols) tile[ty + k][tx] = A[(size_t)j * lda + i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 32; k += 8) {
+        const int j = j0 + tx, i = i0 + ty + k;   // B(j, i) = A(i, j)
+        if (i < rows && j < cols) B[(size_t)i * ldb + j] = tile[tx][ty + k];
+    }
+}
+void transpose64(hipStream_t s, int rows, int cols, const double *A, int lda, double *B, int ldb) {
+    if ((size_t)rows * cols == 0) return;
+    hipLaunchKernelGGL(k_transpose, dim3(cdiv(rows, 32), cdiv(cols, 32)), dim3(256), 0, s, rows, cols,
+                       A, lda, B, ldb);
+}
+
 // out[0] = max|r_ii| / min|r_ii|  (cond_R of Algorithm 4, Section 3.5)
 __global__ __launch_bounds__(256) void k_diag_cond(int n, const double *R, int ldr, double *out) {
     __shared__ double mx[4], mn[4];
