@@ -172,7 +172,7 @@ constexpr int QR_COOP_SPIN = 1 << 22;
 struct CoopShared {
     double red[QR_RC * (QR_NB + 1)];
     double s8[(QR_RC / QR_NB) * QR_NB];
-    double S[QR_NB], H[QR_NB];
+    double S[QR_NB], H[QR_NB], tv[QR_NB];
     int bad;
 };
 
@@ -253,6 +253,7 @@ __device__ __forceinline__ void coop_column(double (&a)[QR_NB], CoopShared &sh, 
         scale = 1.0 / (x0 - beta);
     }
     if (g == 0 && t == 0) tau[J] = sh.bad ? __builtin_nan("") : tv;
+    if (t == 0) sh.tv[J] = tv;
     // 5. apply it to this thread's row
     if (live && i >= J) {
         const double v = i == J ? 1.0 : a[J] * scale;
@@ -269,9 +270,17 @@ __device__ __forceinline__ void coop_columns(std::integer_sequence<int, J...>, d
     (coop_column<J>(a, sh, mp, nb, part, head, tau, flags, base), ...);
 }
 
+// After the last column: G = V^T V of the panel, each workgroup's rows on
+// the matrix cores (wavefront w forms 16 x 16 tile (w % 2, w / 2) over the
+// 256 rows held in LDS), published through the same coherent stores and a
+// flag raised to base + QR_NB + 1; workgroup 0 alone waits, adds the partial
+// tiles in workgroup order and forms T from G as qr_build_t does (lane j
+// solves column j of the inverse of diag(1/tau) + striu(G)).  No workgroup
+// waits for workgroup 0, so this adds one wait, not a round trip.
 __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P, int ld,
                                                       double *part, double *head, double *tau,
-                                                      int *flags, int base, double *Vb) {
+                                                      int *flags, int base, double *Vb,
+                                                      double *Gpart, double *T, int ldt) {
     __shared__ CoopShared sh;
     const int i = blockIdx.x * QR_RC + threadIdx.x;
     const bool live = i < mp;
@@ -284,10 +293,70 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
 #pragma unroll
     for (int k = 0; k < QR_NB; ++k)
         if (live && k < nb) P[(size_t)k * ld + i] = a[k];
-    // the explicit unit lower trapezoidal V of the panel (ld mp)
+    // the explicit unit lower trapezoidal V of the panel (ld mp), also into
+    // LDS (rows past mp and columns past nb are zero)
+    __syncthreads();
+    {
+        double *vr = sh.red + threadIdx.x * (QR_NB + 1);
 #pragma unroll
-    for (int k = 0; k < QR_NB; ++k)
-        if (live && k < nb) Vb[(size_t)k * mp + i] = i > k ? a[k] : (i == k ? 1.0 : 0.0);
+        for (int k = 0; k < QR_NB; ++k) {
+            const double v = (live && k < nb) ? (i > k ? a[k] : (i == k ? 1.0 : 0.0)) : 0.0;
+            if (live && k < nb) Vb[(size_t)k * mp + i] = v;
+            vr[k] = v;
+        }
+    }
+    __syncthreads();
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = blockIdx.x, G = gridDim.x;
+    {
+        const int ti = w & 1, tj = w >> 1;
+        dbl4 acc = dbl4{0, 0, 0, 0};
+        for (int kk = 0; kk < QR_RC; kk += 4) {
+            const double *row = sh.red + (kk + lane / 16) * (QR_NB + 1);
+            acc = mfma16(row[16 * ti + lane % 16], row[16 * tj + lane % 16], acc);
+        }
+        double *pg = Gpart + (size_t)g * QR_NB * QR_NB;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            coh_store(pg + (16 * ti + mfma_row<double>(lane, e)) + (size_t)(16 * tj + lane % 16) * QR_NB, acc[e]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    if (t == 0) coh_store(flags + g, base + QR_NB + 1);
+    if (g != 0) return;
+    if (t < G) {
+        int it = 0;
+        while (coh_load(flags + t) < base + QR_NB + 1) {
+            if (++it > QR_COOP_SPIN) { sh.bad = 1; break; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    double *Gs = sh.red;   // G (ld QR_NB), the rows of V are no longer needed
+    for (int e = t; e < QR_NB * QR_NB; e += QR_RC) {
+        double sacc = 0.0;
+        for (int q = 0; q < G; ++q) sacc += coh_load(Gpart + (size_t)q * QR_NB * QR_NB + e);
+        Gs[e] = sacc;
+    }
+    __syncthreads();
+    if (t < QR_NB) {
+        const int j = t;
+        double c[QR_NB];
+#pragma unroll
+        for (int r = 0; r < QR_NB; ++r) c[r] = (r == j && j < nb) ? sh.tv[r] : 0.0;
+#pragma unroll
+        for (int r = QR_NB - 2; r >= 0; --r) {
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int k = r + 1; k < QR_NB; ++k) {
+                if ((k - r) & 1) s0 = fma(Gs[k * QR_NB + r], c[k], s0);
+                else s1 = fma(Gs[k * QR_NB + r], c[k], s1);
+            }
+            if (r < j) c[r] = -(r < nb ? sh.tv[r] : 0.0) * (s0 + s1);
+        }
+        const double poison = sh.bad ? __builtin_nan("") : 0.0;
+#pragma unroll
+        for (int r = 0; r < QR_NB; ++r) T[(size_t)j * ldt + r] = (j < nb ? c[r] : 0.0) + poison;
+    }
 }
 
 __global__ void qr_flags_zero(int n, int *flags) {
@@ -392,8 +461,9 @@ static void panel_factor(hipStream_t s, int mp, int nb, double *P, int ld, doubl
     if (G <= QR_COOP_MAXG) {
         // algorithmic work: the panel read and written once, 2 mp nb^2 flops
         if (q.kc) q.kc->begin(s, 7, 2.0 * mp * nb * sizeof(double), 2.0 * mp * nb * nb);
+        // the panel, its explicit V and its T in one launch
         hipLaunchKernelGGL(qr_panel_coop, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.part, q.head,
-                           tau, q.flags, panel * 64, q.vb);
+                           tau, q.flags, panel * 64, q.vb, q.vtv, T, ldt);
         if (q.kc) q.kc->end(s);
     } else {
         hipLaunchKernelGGL(qr_panel_init, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.part, q.head);
@@ -401,10 +471,10 @@ static void panel_factor(hipStream_t s, int mp, int nb, double *P, int ld, doubl
             hipLaunchKernelGGL(qr_panel_step, dim3(G), dim3(QR_RC), 0, s, j, mp, nb, G, P, ld,
                                q.part, q.head, tau);
         extract_v(s, mp, nb, P, ld, q.vb);
+        gemm<double>(s, true, false, nb, nb, mp, 1.0, q.vb, mp, q.vb, mp, 0.0, q.vtv, QR_NB, q.split,
+                     q.split_elems, q.kc);
+        hipLaunchKernelGGL(qr_build_t, dim3(1), dim3(64), 0, s, nb, q.vtv, tau, T, ldt);
     }
-    gemm<double>(s, true, false, nb, nb, mp, 1.0, q.vb, mp, q.vb, mp, 0.0, q.vtv, QR_NB, q.split,
-                 q.split_elems, q.kc);
-    hipLaunchKernelGGL(qr_build_t, dim3(1), dim3(64), 0, s, nb, q.vtv, tau, T, ldt);
 }
 
 // C (mp x ncol) <- (I - V T' V^T) C with T' = T (trans = false) or T^T; V
