@@ -142,35 +142,38 @@ struct Small {
     int pad1;
 };
 
+// Per-stage HIP events; a failed event call leaves stage_ms at 0 instead of
+// failing the SVD.
 struct Timer {
-    hipEvent_t ev[9];
+    hipEvent_t ev[9] = {};
     bool ok = false;
     hipStream_t s;
     int last = 0;
     explicit Timer(hipStream_t st) : s(st) {
         ok = true;
         for (int i = 0; i < 9; ++i)
-            if (hipEventCreate(&ev[i]) != hipSuccess) ok = false;
-        if (ok) hipEventRecord(ev[0], s);
+            if (hipEventCreate(&ev[i]) != hipSuccess) { ev[i] = nullptr; ok = false; }
+        if (ok && hipEventRecord(ev[0], s) != hipSuccess) ok = false;
     }
     void mark(int stage) {  // end of stage `stage` (0..7); skipped stages get 0 ms
         if (!ok) return;
-        for (int k = last + 1; k <= stage + 1; ++k) hipEventRecord(ev[k], s);
+        for (int k = last + 1; k <= stage + 1; ++k)
+            if (hipEventRecord(ev[k], s) != hipSuccess) { ok = false; return; }
         last = stage + 1;
     }
     void fill(svd_info *info) {
         if (!ok) return;
         mark(7);
-        hipEventSynchronize(ev[8]);
+        if (!ok || hipEventSynchronize(ev[8]) != hipSuccess) return;
         for (int i = 0; i < 8; ++i) {
             float ms = 0.f;
-            hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+            if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) ms = 0.f;
             if (info) info->stage_ms[i] = ms;
         }
     }
     ~Timer() {
-        if (ok)
-            for (int i = 0; i < 9; ++i) hipEventDestroy(ev[i]);
+        for (int i = 0; i < 9; ++i)
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
     }
 };
 

@@ -573,8 +573,8 @@ extern "C" int svd_batched_plan_create(int batch, const int *h_m, const int *h_n
             hipMalloc(&P->d_order, sizeof(int) * batch) != hipSuccess ||
             hipMemcpy(P->d_meta, meta.data(), sizeof(BatchMeta) * batch, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(P->d_order, order.data(), sizeof(int) * batch, hipMemcpyHostToDevice) != hipSuccess) {
-            hipFree(P->d_meta);
-            hipFree(P->d_order);
+            (void)hipFree(P->d_meta);
+            (void)hipFree(P->d_order);
             delete P;
             return SVD_ERR_HIP;
         }
@@ -589,10 +589,10 @@ extern "C" int svd_batched_plan_create(int batch, const int *h_m, const int *h_n
 extern "C" void svd_batched_plan_destroy(void *plan) {
     BatchPlan *P = (BatchPlan *)plan;
     if (!P) return;
-    if (P->exec) hipGraphExecDestroy(P->exec);
-    if (P->cap) hipStreamDestroy(P->cap);
-    hipFree(P->d_meta);
-    hipFree(P->d_order);
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->cap) (void)hipStreamDestroy(P->cap);
+    (void)hipFree(P->d_meta);
+    (void)hipFree(P->d_order);
     delete P;
 }
 
@@ -621,7 +621,7 @@ extern "C" int svd_batched(void *plan, const double *A_base, double *S_base, dou
     if (!same) {
         // capture [reset queue; persistent kernel] once per buffer set; the
         // counter is cleared by a kernel, not a memset node
-        if (P->exec) { hipGraphExecDestroy(P->exec); P->exec = nullptr; }
+        if (P->exec) { (void)hipGraphExecDestroy(P->exec); P->exec = nullptr; }
         if (!P->cap && hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess)
             return SVD_ERR_HIP;
         hipGraph_t g = nullptr;
@@ -632,7 +632,7 @@ extern "C" int svd_batched(void *plan, const double *A_base, double *S_base, dou
                            P->maxn, A_base, S_base, U_base, V_base, wk, info, counter);
         if (hipStreamEndCapture(P->cap, &g) != hipSuccess || !g) return SVD_ERR_HIP;
         hipError_t e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (e != hipSuccess) { P->exec = nullptr; return SVD_ERR_HIP; }
         for (int i = 0; i < 7; ++i) P->key[i] = key[i];
     }

@@ -240,15 +240,18 @@ extern "C" int eig_mixed(int n, const double *A, int lda, double *W, double *X, 
     double *UX = D(L.off_ux), *T1 = D(L.off_t1), *S = D(L.off_s), *dd = D(L.off_d), *mu = D(L.off_mu);
     int *blk = (int *)(w + L.off_blk), *perm = (int *)(w + L.off_perm);
 
-    hipEvent_t ev[5];
+    hipEvent_t ev[5] = {};
     bool evok = true;
     for (int i = 0; i < 5; ++i)
-        if (hipEventCreate(&ev[i]) != hipSuccess) evok = false;
+        if (hipEventCreate(&ev[i]) != hipSuccess) { ev[i] = nullptr; evok = false; }
     struct EvGuard {
-        hipEvent_t *e; bool ok;
-        ~EvGuard() { if (ok) for (int i = 0; i < 5; ++i) hipEventDestroy(e[i]); }
-    } guard{ev, evok};
-    if (evok) hipEventRecord(ev[0], s);
+        hipEvent_t *e;
+        ~EvGuard() {
+            for (int i = 0; i < 5; ++i)
+                if (e[i]) (void)hipEventDestroy(e[i]);
+        }
+    } guard{ev};
+    if (evok && hipEventRecord(ev[0], s) != hipSuccess) evok = false;
 
     // 1-3. A = U Sigma V^T by the mixed-precision Jacobi SVD, V not formed
     const svd_opts so = eig_svd_opts(o);
@@ -260,7 +263,7 @@ extern "C" int eig_mixed(int n, const double *A, int lda, double *W, double *X, 
         if (info) info->status = SVD_ERR_NONFINITE;
         return 0;
     }
-    if (evok) hipEventRecord(ev[1], s);
+    if (evok && hipEventRecord(ev[1], s) != hipSuccess) evok = false;
 
     // 4. T1 = A U; d_i = u_i^T A u_i
     gemm<double>(s, false, false, n, n, n, 1.0, A, lda, UX, n, 0.0, T1, n, nullptr, 0);
@@ -269,7 +272,7 @@ extern "C" int eig_mixed(int n, const double *A, int lda, double *W, double *X, 
     std::vector<double> hS(n), hd(n), hmu(n);
     if (eig_read_back(s, hS.data(), S, (size_t)n * sizeof(double))) return SVD_ERR_HIP;
     if (eig_read_back(s, hd.data(), dd, (size_t)n * sizeof(double))) return SVD_ERR_HIP;
-    if (evok) hipEventRecord(ev[2], s);
+    if (evok && hipEventRecord(ev[2], s) != hipSuccess) evok = false;
     const double eps_work = o.eps_work > 0 ? o.eps_work : sqrt((double)n) * ldexp(1.0, -53);
 
     // 5. blocks of (nearly) equal sigma
@@ -303,7 +306,7 @@ extern "C" int eig_mixed(int n, const double *A, int lda, double *W, double *X, 
         MPJ_CHECK(hipGetLastError());
         if (eig_read_back(s, hmu.data(), mu, (size_t)n * sizeof(double))) return SVD_ERR_HIP;
     }
-    if (evok) hipEventRecord(ev[3], s);
+    if (evok && hipEventRecord(ev[3], s) != hipSuccess) evok = false;
 
     // 6. eigenvalues: sign(u_i^T A u_i) sigma_i for a block of one; in a
     // block, the eigenvalues mu of the diagonalised block give the signs,
@@ -332,7 +335,7 @@ extern "C" int eig_mixed(int n, const double *A, int lda, double *W, double *X, 
                        (const double *)UX, n, (const int *)perm, X, ldx);
     if (o.sign_normalize) sign_normalize(s, n, n, nullptr, 0, false, X, ldx);
     MPJ_CHECK(hipGetLastError());
-    if (evok) hipEventRecord(ev[4], s);
+    if (evok && hipEventRecord(ev[4], s) != hipSuccess) evok = false;
     MPJ_CHECK(hipStreamSynchronize(s));   // the host vectors above are the copies' sources
 
     if (info) {
@@ -344,7 +347,7 @@ extern "C" int eig_mixed(int n, const double *A, int lda, double *W, double *X, 
         if (evok)
             for (int i = 0; i < 4; ++i) {
                 float ms = 0.f;
-                hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+                if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) ms = 0.f;
                 info->stage_ms[i] = ms;
             }
     }

@@ -26,24 +26,33 @@ struct KernelClock {
     int pass_calls = 0;
     double tot_bytes[NC] = {0};
     double tot_flops[NC] = {0};
+    // The clock is optional: an event call that fails switches it off
+    // (the timings are then absent) instead of failing the computation.
+    bool grow(int c, double b, double f) {
+        if (used + 2 <= ev.size()) return true;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess) { on = false; return false; }
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            on = false;
+            return false;
+        }
+        ev.push_back(e0);
+        ev.push_back(e1);
+        cls.push_back(c);
+        bytes.push_back(b);
+        flops.push_back(f);
+        return true;
+    }
     void begin(hipStream_t s, int c, double b, double f = 0.0) {
         if (!on) return;
         skipping = only >= 0 && c != only;
         if (skipping) return;
-        if (used + 2 > ev.size()) {
-            hipEvent_t e0, e1;
-            hipEventCreate(&e0);
-            hipEventCreate(&e1);
-            ev.push_back(e0);
-            ev.push_back(e1);
-            cls.push_back(c);
-            bytes.push_back(b);
-            flops.push_back(f);
-        }
+        if (!grow(c, b, f)) return;
         cls[used / 2] = c;
         bytes[used / 2] = b;
         flops[used / 2] = f;
-        hipEventRecord(ev[used], s);
+        if (hipEventRecord(ev[used], s) != hipSuccess) on = false;
     }
     // The events of one launch of class c that the dispatch itself records
     // (hipExtLaunchKernelGGL): no marker packets around the kernel, so short
@@ -52,16 +61,7 @@ struct KernelClock {
     bool slot(int c, double b, double f, hipEvent_t *e0, hipEvent_t *e1) {
         if (!on || (only >= 0 && c != only)) return false;
         if (seen[c]++ % every != 0) return false;
-        if (used + 2 > ev.size()) {
-            hipEvent_t a, z;
-            hipEventCreate(&a);
-            hipEventCreate(&z);
-            ev.push_back(a);
-            ev.push_back(z);
-            cls.push_back(c);
-            bytes.push_back(b);
-            flops.push_back(f);
-        }
+        if (!grow(c, b, f)) return false;
         cls[used / 2] = c;
         bytes[used / 2] = b;
         flops[used / 2] = f;
@@ -72,7 +72,7 @@ struct KernelClock {
     }
     void end(hipStream_t s) {
         if (!on || skipping) return;
-        hipEventRecord(ev[used + 1], s);
+        if (hipEventRecord(ev[used + 1], s) != hipSuccess) { on = false; return; }
         used += 2;
     }
     // call after the stream has been synchronised
@@ -80,7 +80,7 @@ struct KernelClock {
         if (!on) return;
         for (size_t i = 0; i < used; i += 2) {
             float t = 0.f;
-            hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+            if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) continue;
             ms[cls[i / 2]] += t;
             calls[cls[i / 2]] += 1;
             tot_bytes[cls[i / 2]] += bytes[i / 2];
@@ -89,7 +89,7 @@ struct KernelClock {
         used = 0;
     }
     ~KernelClock() {
-        for (auto e : ev) hipEventDestroy(e);
+        for (auto e : ev) (void)hipEventDestroy(e);
     }
 };
 
