@@ -51,6 +51,15 @@ extern "C" {
 #define SVD_WARN_RANK_DEFICIENT 3 /* some sigma_i == 0; U(:, i) set to zero */
 #define EIG_ERR_CLUSTER 4        /* eig_mixed: a block of equal |eigenvalue|
                                     larger than 64; outputs undefined       */
+#define SVD_ERR_WAIT_TIMEOUT 5   /* a bounded wait between the workgroups of
+                                    a one-launch kernel (the Householder
+                                    panel) ran out, e.g. because another
+                                    stream held compute units; outputs
+                                    undefined (the one-launch pivot pass
+                                    instead falls back to per-step launches
+                                    and does not report this)              */
+#define SVD_ERR_BREAKDOWN 6      /* a singular value came out NaN or Inf
+                                    from finite input; outputs undefined    */
 
 /* svd_opts.branch / svd_info.branch_taken (Algorithm 4's special cases) */
 #define SVD_BRANCH_AUTO 0
@@ -143,6 +152,13 @@ typedef struct {
                               k-th launch of a Jacobi kernel class (a sample
                               that keeps the events' cost out of the rest of
                               the launches); 0 or 1 = every launch */
+    int wait_polls;        /* polls of each bounded cross-workgroup wait
+                              (one-launch pivot pass, Householder panel)
+                              before it gives up: 0 = default (2^22);
+                              -1 = give up at the first check (a test hook
+                              for the time-out paths: the pivot pass then
+                              falls back to per-step launches, the panel
+                              reports SVD_ERR_WAIT_TIMEOUT); < -1 invalid */
 } svd_opts;
 
 /* Kernel classes reported by svd_info.kern_* (kernel_timing 1: SVD_K_QRCP

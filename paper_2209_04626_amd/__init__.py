@@ -29,6 +29,7 @@ EXPORTS = [
 
 SVD_OK, SVD_WARN_NOCONV, SVD_ERR_NONFINITE, SVD_WARN_RANK_DEFICIENT = 0, 1, 2, 3
 EIG_ERR_CLUSTER = 4
+SVD_ERR_WAIT_TIMEOUT, SVD_ERR_BREAKDOWN = 5, 6
 KERNEL_CLASSES = ["jac_gram<f32>", "jac_inner<f32>", "jac_update<f32>", "jac_gram<f64>",
                   "jac_inner<f64>", "jac_update<f64>", "qrcp", "qr_panel", "gemm", "-", "-", "-"]
 NCLASS = 12
@@ -50,7 +51,7 @@ class SvdOpts(ctypes.Structure):
         ("v_method", ctypes.c_int), ("diagnostics", ctypes.c_int), ("tol_vsolve", ctypes.c_double),
         ("inner_pairs", ctypes.c_int), ("tol_cluster", ctypes.c_double),
         ("y2_safeguard", ctypes.c_int), ("tol_y2", ctypes.c_double),
-        ("kernel_timing_every", ctypes.c_int),
+        ("kernel_timing_every", ctypes.c_int), ("wait_polls", ctypes.c_int),
     ]
 
 
@@ -341,16 +342,23 @@ def pack_batch(mats, device):
     return torch.from_numpy(np.concatenate(flat) if flat else np.zeros(0)).to(device)
 
 
-def svd_batched(plan: BatchedPlan, A_packed, workspace: Workspace | None = None):
-    """Run the batched mixed SVD; returns packed (S, U, V) tensors and info."""
+def svd_batched(plan: BatchedPlan, A_packed, workspace: Workspace | None = None, out=None):
+    """Run the batched mixed SVD; returns packed (S, U, V) tensors and info.
+
+    out: optional (S, U, V, info) tensors from an earlier call with this plan
+    to write into; with the same input, outputs and workspace the library
+    replays its captured graph instead of capturing a new one."""
     import torch
     lib = load()
     _check_device(A_packed, "A_packed")
     dev = A_packed.device
-    S = torch.empty(max(plan.totS, 1), dtype=torch.float64, device=dev)
-    U = torch.empty(max(plan.totA, 1), dtype=torch.float64, device=dev)
-    V = torch.empty(max(plan.totV, 1), dtype=torch.float64, device=dev)
-    info = torch.zeros((max(len(plan.shapes), 1), 4), dtype=torch.int32, device=dev)
+    if out is not None:
+        S, U, V, info = out
+    else:
+        S = torch.empty(max(plan.totS, 1), dtype=torch.float64, device=dev)
+        U = torch.empty(max(plan.totA, 1), dtype=torch.float64, device=dev)
+        V = torch.empty(max(plan.totV, 1), dtype=torch.float64, device=dev)
+        info = torch.zeros((max(len(plan.shapes), 1), 4), dtype=torch.int32, device=dev)
     ws = (workspace or _ws_default).get(plan.work_bytes, dev)
     with torch.cuda.device(dev):
         rc = lib.svd_batched(plan.handle, A_packed.data_ptr(), S.data_ptr(), U.data_ptr(),

@@ -52,6 +52,7 @@ extern "C" void svd_default_opts(svd_opts *o, int mixed) {
     o->y2_safeguard = 1;
     o->tol_y2 = 0.0;
     o->kernel_timing_every = 1;
+    o->wait_polls = 0;
 }
 
 namespace {
@@ -139,7 +140,12 @@ struct Small {
     double cond;
     float orth;
     float orthv, orthy;
+    int err_wait;        // a bounded cross-workgroup wait ran out
+    int nonfinite_out;   // a singular value came out NaN or Inf
     int pad1;
+    double condl;        // max|l_ii| / min|l_ii| of X = L (before the solve for V)
+    double pivscale;     // power of two for the FP32 copy of A1 (pivots)
+    double lowscale;     // power of two for the FP32 copy of X (FP32 stage)
 };
 
 // Per-stage HIP events; a failed event call leaves stage_ms at 0 instead of
@@ -208,6 +214,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     if (o.inner_pairs != 0 && o.inner_pairs != 1) return -12;
     if (o.y2_safeguard != 0 && o.y2_safeguard != 1) return -12;
     if (o.kernel_timing_every < 0) return -12;
+    if (o.wait_polls < -1) return -12;
     if (info) {
         memset(info, 0, sizeof(*info));
         info->orth = -1.0;
@@ -239,6 +246,8 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
 
     QRScratch q;
     qr_scratch_carve(q, D(L.off_qr), m > n ? m : n, n);
+    q.err = &sm->err_wait;
+    q.spin = o.wait_polls;
     JacobiWork jw;
     int hflag[3] = {0, 0, 0};
     jw.hflag = hflag;
@@ -277,10 +286,17 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     if (o.kernel_timing == 1)
         kclock.begin(s, SVD_K_QRCP, 0.0);
     int piv_launches;
-    if (o.pivot_precision == 32)
-        piv_launches = qrcp_pivots<float>(s, n, A1, n, (float *)D(L.off_wp), w + L.off_nrm2, piv, jw.kc);
-    else
-        piv_launches = qrcp_pivots<double>(s, n, A1, n, D(L.off_wp), w + L.off_nrm2, piv, jw.kc);
+    if (o.pivot_precision == 32) {
+        // the FP32 copy of A1 is scaled by a power of two so that squared
+        // column norms of graded inputs stay inside the FP32 range
+        col_norms(s, n, n, A1, n, nrmX);
+        pow2_scale(s, n, nrmX, &sm->pivscale);
+        piv_launches = qrcp_pivots<float>(s, n, A1, n, (float *)D(L.off_wp), w + L.off_nrm2, piv,
+                                          jw.kc, &sm->pivscale, o.wait_polls);
+    } else {
+        piv_launches = qrcp_pivots<double>(s, n, A1, n, D(L.off_wp), w + L.off_nrm2, piv, jw.kc,
+                                           nullptr, o.wait_polls);
+    }
     if (o.kernel_timing == 1) {
         kclock.end(s);
         // launches and algorithmic work of the whole pass (see qrcp_pivots)
@@ -309,6 +325,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         diag_cond(s, n, A1P, n, &sm->cond);
         col_norms(s, n, n, X, N, nrmX);
         count_small(s, n, nrmX, o.small_col_rel, &sm->nsmall);
+        pow2_scale(s, n, nrmX, &sm->lowscale);
         if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
         cond = hs.cond;
         nsmall = hs.nsmall;
@@ -336,7 +353,11 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         // accumulated for switch methods 2 and 3
         const bool vlow = o.switch_method >= 2;
         float *V32 = vlow ? (float *)(w + L.off_v32) : nullptr;
-        convert_f64_f32(s, N, N, X, N, Y32, N);
+        // low(X) times a power of two (exact): squared norms and dot
+        // products of graded columns stay inside the FP32 range, and every
+        // quantity the stage hands on (angles, normalised columns) is
+        // invariant under the scale
+        convert_f64_f32(s, N, N, X, N, Y32, N, &sm->lowscale);
         if (vlow) {
             set_identity(s, N, Ulow, N);
             convert_f64_f32(s, N, N, Ulow, N, V32, N);
@@ -462,14 +483,18 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     if (vsolve) {
         // Y = X V_X = U_X Sigma, so V_X = X^{-1} Y with X = L lower triangular
         MPJ_CHECK(hipMemcpyAsync(Vacc, Y, (size_t)N * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        diag_cond(s, n, X, N, &sm->condl);
         trsm_lower(s, n, n, X, N, Vacc, N, jw.kc);
         gemm_orth_maxdev64(s, n, Vacc, N, &sm->orthv);
         if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
         orth_vx = hs.orthv;
         // default: n 2^-50 = 8 n u, the size of the rounding error that the
-        // accumulated rotations of a few sweeps leave in V_X
+        // accumulated rotations of a few sweeps leave in V_X.  A zero on the
+        // diagonal of L (rank-deficient X) makes the solve meaningless, and a
+        // NaN from it reads as an infinite deviation: both take the other
+        // route of Section 3.4.
         const double tol_v = o.tol_vsolve > 0 ? o.tol_vsolve : n * ldexp(1.0, -50);
-        if (orth_vx <= tol_v) {
+        if (orth_vx <= tol_v && hs.condl < INFINITY) {
             v_taken = 1;
         } else {
             // not accurate enough: V_X from the QR of X^T U_X (U_X = the
@@ -494,7 +519,8 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     }
 
     // a9: sigma, U_X, V_X sorted; U = Q0 Q1 U_X, V = P Q2^T V_X
-    finalize_sort(s, n, N, Y, Vacc, sig, rank, UX, VX, S, &sm->nzero, o.want_v != 0);
+    finalize_sort(s, n, N, Y, Vacc, sig, rank, UX, VX, S, &sm->nzero, &sm->nonfinite_out,
+                  o.want_v != 0);
     if (o.want_u) {
         if (!alg3) qr_apply_left(s, false, n, n, A1P, n, T1, n, UX, n, q);
         place_u(s, m, n, UX, n, U, ldu);
@@ -539,6 +565,8 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         int st = SVD_OK;
         if (!conv_work) st = SVD_WARN_NOCONV;
         if (hs.nzero) st = SVD_WARN_RANK_DEFICIENT;
+        if (hs.nonfinite_out) st = SVD_ERR_BREAKDOWN;
+        if (hs.err_wait) st = SVD_ERR_WAIT_TIMEOUT;
         info->status = st;
     }
     return 0;
@@ -573,6 +601,8 @@ extern "C" const char *svd_status_string(int code) {
     case SVD_ERR_NONFINITE: return "error: input holds NaN or Inf";
     case SVD_WARN_RANK_DEFICIENT: return "warning: zero singular value(s)";
     case EIG_ERR_CLUSTER: return "error: a block of equal |eigenvalue| larger than 64";
+    case SVD_ERR_WAIT_TIMEOUT: return "error: a bounded cross-workgroup wait ran out; outputs undefined";
+    case SVD_ERR_BREAKDOWN: return "error: a non-finite singular value from finite input; outputs undefined";
     case SVD_ERR_HIP: return "error: HIP runtime failure";
     default: return code < 0 ? "error: invalid argument" : "unknown status";
     }

@@ -121,7 +121,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(
                     const int gj = j0 + wn * 16 * TJ + tj * 16 + lane % 16;
                     if (gi < M && gj < N) {
                         const T dv = alpha * acc[ti][tj][r] - (gi == gj ? T(1) : T(0));
-                        const float d = (float)(dv < T(0) ? -dv : dv);
+                        float d = (float)(dv < T(0) ? -dv : dv);
+                        // fmaxf drops a NaN operand: a NaN entry (a NaN in X)
+                        // must read as the largest deviation instead
+                        if (d != d) d = INFINITY;
                         dmax = fmaxf(dmax, d);
                     }
                 }

@@ -134,6 +134,11 @@ struct QRScratch {
     double *split;  // split-K scratch
     size_t split_elems;
     int *flags;     // max_groups step flags of the one-launch panel
+    int *err = nullptr;          // device word set to 1 when a bounded wait of the
+                                 // one-launch panel runs out (the factors are then
+                                 // invalid); NULL: not reported
+    int spin = 0;                // polls of a bounded wait before it gives up; 0 =
+                                 // the default, < 0 = give up at once (testing)
     KernelClock *kc = nullptr;   // optional per-launch timing
 };
 size_t qr_scratch_doubles(int m, int ncols_max, size_t *split_elems);
@@ -163,9 +168,14 @@ double qrcp_step_bytes(int n, int k, int elem);
 double qrcp_step_flops(int n, int k);
 double qrcp_pass_bytes(int n, int elem);
 double qrcp_pass_flops(int n);
+// scale (device, may be NULL): a power of two applied to A1 before it is
+// rounded to T (pivots are invariant under it); spin: polls of the one-launch
+// pass's bounded waits (0 = default, < 0 = give up at once, which sends the
+// pass to the step-by-step fallback).
 template <typename T>
 int qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W,
-                 void *scratch, int *piv, KernelClock *kc = nullptr);
+                 void *scratch, int *piv, KernelClock *kc = nullptr,
+                 const double *scale = nullptr, int spin = 0);
 
 // ---------------------------------------------------------------- Jacobi
 struct JacobiWork {
@@ -217,12 +227,17 @@ void diag_cond(hipStream_t s, int n, const double *R, int ldr, double *out);
 void col_norms(hipStream_t s, int rows, int n, const double *X, int ldx, double *nrm);
 void count_small(hipStream_t s, int n, const double *nrm, double rel, int *out);
 void make_xt32(hipStream_t s, int n, const double *X, int ldx, float *Xt, int ldt);
-void convert_f64_f32(hipStream_t s, int rows, int cols, const double *X, int ldx, float *Y, int ldy);
+// Y = fp32(X * scale[0]) (scale: device pointer, NULL = 1)
+void convert_f64_f32(hipStream_t s, int rows, int cols, const double *X, int ldx, float *Y, int ldy,
+                     const double *scale = nullptr);
+// scale[0] = the power of two that brings the largest of the n norms nrm[]
+// to about 2^56 (range guard for FP32 copies; see misc.hip)
+void pow2_scale(hipStream_t s, int n, const double *nrm, double *scale);
 void convert_f32_f64(hipStream_t s, int rows, int cols, const float *X, int ldx, double *Y, int ldy);
 void normalize_f32_to_f64(hipStream_t s, int rows, int cols, const float *Y, int ldy, double *U, int ldu);
 void finalize_sort(hipStream_t s, int n, int N, const double *Y, const double *V,
                    double *sig, int *rank, double *UX, double *VX, double *S, int *nzero,
-                   bool want_v);
+                   int *nonfinite, bool want_v);
 void place_u(hipStream_t s, int m, int n, const double *W, int ldw, double *U, int ldu);
 void permute_rows_v(hipStream_t s, int n, const double *T, int ldt, const int *piv,
                     double *V, int ldv);

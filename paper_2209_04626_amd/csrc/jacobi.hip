@@ -217,11 +217,16 @@ __device__ __forceinline__ double rcp64(double x) {
 // zeta: t = sign(zeta) |g2| / (|d| + sqrt(d^2 + g2^2)), c = 1/sqrt(1 + t^2),
 // s = t c, with the square roots and the quotient from refined hardware
 // estimates.  Returns false, with the identity, when the pair passes the test
-// g^2 <= eps^2 g_pp g_qq of Algorithm 1.
+// g^2 <= eps^2 g_pp g_qq of Algorithm 1, and when g_pp g_qq is not positive:
+// in exact arithmetic a zero column has g_pq = 0, and a product that rounded
+// to zero (squares below the format's range) must not rotate for ever.
 template <int NR>
 __device__ __forceinline__ bool jac_rot_test(double al, double be, double ga, double eps2,
                                              double *c, double *s, double *t) {
-    if (!(ga * ga > eps2 * al * be)) { *c = 1.0; *s = 0.0; *t = 0.0; return false; }
+    if (!(ga * ga > eps2 * al * be) || !(al * be > 0.0)) {
+        *c = 1.0; *s = 0.0; *t = 0.0;
+        return false;
+    }
     const double d = be - al, g2 = 2.0 * ga;
     double tt;
     if (d == 0.0) {
@@ -367,7 +372,7 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
         if (uok[k] && p < q) {
             const double g = (double)G[0][p * LD + q];
             const double pq = (double)G[0][p * LD + p] * (double)G[0][q * LD + q];
-            if (g * g > eps2 * pq && (!cross || (p < H && q >= H))) need = 1;
+            if (g * g > eps2 * pq && pq > 0.0 && (!cross || (p < H && q >= H))) need = 1;
             if (pq > 0.0) offmax = fmaxf(offmax, (float)(fabs(g) / sqrt(pq)));
         }
     }

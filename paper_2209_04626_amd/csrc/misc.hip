@@ -177,35 +177,73 @@ void count_small(hipStream_t s, int n, const double *nrm, double rel, int *out) 
     hipLaunchKernelGGL(k_count_small, dim3(1), dim3(256), 0, s, n, nrm, rel, out);
 }
 
-// X_t = low(X) D^-1, D_jj = FP32 2-norm of low(X)(:, j)  (Algorithm 4, Section 3.5)
+// X_t = low(X) D^-1 with D_jj the 2-norm of column j (Algorithm 4, Section
+// 3.5).  The norm is summed in FP64 and the column divided by it before the
+// rounding to FP32: squared FP32 norms would underflow for columns below
+// about 1e-19 (graded inputs reach 1e-20), and the rounded X_t is the same
+// up to one FP32 rounding for every column that an FP32 norm could handle.
 __global__ __launch_bounds__(256) void k_make_xt32(int n, const double *X, int ldx, float *Xt,
                                                    int ldt) {
     const int lane = threadIdx.x & 63;
     const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (j >= n) return;
-    float s = 0.f;
+    double s = 0.0;
     for (int i = lane; i < n; i += 64) {
-        const float v = (float)X[(size_t)j * ldx + i];
-        s += v * v;
+        const double v = X[(size_t)j * ldx + i];
+        s = fma(v, v, s);
     }
     s = wave_sum(s);
-    const float d = sqrtf(s);
-    const float inv = d > 0.f ? 1.f / d : 0.f;
-    for (int i = lane; i < n; i += 64) Xt[(size_t)j * ldt + i] = (float)X[(size_t)j * ldx + i] * inv;
+    const double d = sqrt(s);
+    const double inv = d > 0.0 ? 1.0 / d : 0.0;
+    for (int i = lane; i < n; i += 64) Xt[(size_t)j * ldt + i] = (float)(X[(size_t)j * ldx + i] * inv);
 }
 void make_xt32(hipStream_t s, int n, const double *X, int ldx, float *Xt, int ldt) {
     hipLaunchKernelGGL(k_make_xt32, dim3(cdiv(n, 4)), dim3(256), 0, s, n, X, ldx, Xt, ldt);
 }
 
-__global__ void k_f64_f32(int rows, int cols, const double *X, int ldx, float *Y, int ldy) {
+__global__ void k_f64_f32(int rows, int cols, const double *X, int ldx, float *Y, int ldy,
+                          const double *scale) {
     const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (size_t)rows * cols) return;
     const int i = (int)(e % rows), j = (int)(e / rows);
-    Y[(size_t)j * ldy + i] = (float)X[(size_t)j * ldx + i];
+    const double f = scale ? *scale : 1.0;
+    Y[(size_t)j * ldy + i] = (float)(X[(size_t)j * ldx + i] * f);
 }
-void convert_f64_f32(hipStream_t s, int rows, int cols, const double *X, int ldx, float *Y, int ldy) {
+void convert_f64_f32(hipStream_t s, int rows, int cols, const double *X, int ldx, float *Y, int ldy,
+                     const double *scale) {
     hipLaunchKernelGGL(k_f64_f32, grid1((size_t)rows * cols), dim3(256), 0, s, rows, cols, X, ldx, Y,
-                       ldy);
+                       ldy, scale);
+}
+
+// scale[0] = 2^e with e chosen so that the largest of the n column norms
+// becomes about 2^56 (e = 56 - ceil(log2(max norm)), clamped to the FP64
+// exponent range; 1 for an all-zero matrix).  An FP32 copy of the columns
+// times this scale keeps every squared norm and dot product inside the FP32
+// range for column norms spanning up to about 2^118: at most 2^112 at the
+// top, and above the FP32 normal minimum 2^-126 down to norms 2^-63 times
+// the largest.  Scaling by a power of two is exact, and the FP32 stages only
+// use scale-invariant quantities (pivot order, rotation angles, normalised
+// columns).
+__global__ void k_pow2_scale(int n, const double *nrm, double *scale) {
+    __shared__ double mx[4];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) a = fmax(a, nrm[i]);
+    a = wave_max(a);
+    if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double m = fmax(fmax(mx[0], mx[1]), fmax(mx[2], mx[3]));
+        double f = 1.0;
+        if (m > 0.0 && isfinite(m)) {
+            int e = 56 - ilogb(m) - 1;
+            e = e < -1000 ? -1000 : (e > 1000 ? 1000 : e);
+            f = ldexp(1.0, e);
+        }
+        scale[0] = f;
+    }
+}
+void pow2_scale(hipStream_t s, int n, const double *nrm, double *scale) {
+    hipLaunchKernelGGL(k_pow2_scale, dim3(1), dim3(256), 0, s, n, nrm, scale);
 }
 
 __global__ void k_f32_f64(int rows, int cols, const float *X, int ldx, double *Y, int ldy) {
@@ -259,7 +297,7 @@ __global__ void k_rank(int n, const double *sig, int *rank) {
 // Column j of Y / V goes to column rank_j of U_X / V_X (n x n, ld n).
 __global__ __launch_bounds__(256) void k_scatter(int n, int N, const double *Y, const double *V,
                                                  const double *sig, const int *rank, double *UX,
-                                                 double *VX, double *S, int *nzero) {
+                                                 double *VX, double *S, int *nzero, int *nonfinite) {
     const int lane = threadIdx.x & 63;
     const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (j >= n) return;
@@ -273,15 +311,17 @@ __global__ __launch_bounds__(256) void k_scatter(int n, int N, const double *Y, 
     if (lane == 0) {
         S[d] = sj;
         if (sj == 0.0) atomicAdd(nzero, 1);
+        if (!isfinite(sj)) *nonfinite = 1;
     }
 }
 
 void finalize_sort(hipStream_t s, int n, int N, const double *Y, const double *V, double *sig,
-                   int *rank, double *UX, double *VX, double *S, int *nzero, bool want_v) {
+                   int *rank, double *UX, double *VX, double *S, int *nzero, int *nonfinite,
+                   bool want_v) {
     col_norms(s, N, n, Y, N, sig);
     hipLaunchKernelGGL(k_rank, dim3(cdiv(n, 256)), dim3(256), 0, s, n, sig, rank);
     hipLaunchKernelGGL(k_scatter, dim3(cdiv(n, 4)), dim3(256), 0, s, n, N, Y, want_v ? V : nullptr,
-                       sig, rank, UX, VX, S, nzero);
+                       sig, rank, UX, VX, S, nzero, nonfinite);
 }
 
 __global__ void k_place_u(int m, int n, const double *W, int ldw, double *U, int ldu) {
@@ -313,7 +353,7 @@ __global__ __launch_bounds__(256) void k_sign(int m, int n, double *U, int ldu, 
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
     double best = -1.0;
-    int bk = n;
+    int bk = 0;   // a valid row even when no |V(k, i)| compares greater (NaN)
     for (int k = lane; k < n; k += 64) {
         const double a = fabs(V[(size_t)i * ldv + k]);
         if (a > best) { best = a; bk = k; }

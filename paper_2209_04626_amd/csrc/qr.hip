@@ -13,6 +13,7 @@
 // a value another one is writing.
 // Trailing matrix: compact WY form H_0..H_{nb-1} = I - V T V^T with the LAPACK
 // xLARFT recurrence for T, applied with MFMA GEMMs.
+#include <atomic>
 #include <utility>
 
 #include "common.hpp"
@@ -181,7 +182,7 @@ struct CoopShared {
 template <int J>
 __device__ __forceinline__ void coop_column(double (&a)[QR_NB], CoopShared &sh, int mp, int nb,
                                             double *part, double *head, double *tau, int *flags,
-                                            int base) {
+                                            int base, int spin) {
     if (J >= nb) return;
     constexpr int GR = QR_RC / QR_NB;
     const int G = gridDim.x;
@@ -219,10 +220,12 @@ __device__ __forceinline__ void coop_column(double (&a)[QR_NB], CoopShared &sh, 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (t == 0) coh_store(flags + g, base + J + 1);
-    if (t < G) {
+    // (a workgroup's own flag needs no wait; spin < 0 gives up on every
+    // other workgroup at once, a test hook for the time-out path)
+    if (t < G && t != g) {
         int it = 0;
-        while (coh_load(flags + t) < base + J + 1) {
-            if (++it > QR_COOP_SPIN) { sh.bad = 1; break; }
+        while (spin < 0 || coh_load(flags + t) < base + J + 1) {
+            if (spin < 0 || ++it > spin) { sh.bad = 1; break; }
             __builtin_amdgcn_s_sleep(1);
         }
     }
@@ -266,8 +269,9 @@ __device__ __forceinline__ void coop_column(double (&a)[QR_NB], CoopShared &sh, 
 template <int... J>
 __device__ __forceinline__ void coop_columns(std::integer_sequence<int, J...>, double (&a)[QR_NB],
                                              CoopShared &sh, int mp, int nb, double *part,
-                                             double *head, double *tau, int *flags, int base) {
-    (coop_column<J>(a, sh, mp, nb, part, head, tau, flags, base), ...);
+                                             double *head, double *tau, int *flags, int base,
+                                             int spin) {
+    (coop_column<J>(a, sh, mp, nb, part, head, tau, flags, base, spin), ...);
 }
 
 // After the last column: G = V^T V of the panel, each workgroup's rows on
@@ -280,7 +284,8 @@ __device__ __forceinline__ void coop_columns(std::integer_sequence<int, J...>, d
 __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P, int ld,
                                                       double *part, double *head, double *tau,
                                                       int *flags, int base, double *Vb,
-                                                      double *Gpart, double *T, int ldt) {
+                                                      double *Gpart, double *T, int ldt, int *err,
+                                                      int spin) {
     __shared__ CoopShared sh;
     const int i = blockIdx.x * QR_RC + threadIdx.x;
     const bool live = i < mp;
@@ -289,7 +294,7 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
     for (int k = 0; k < QR_NB; ++k) a[k] = (live && k < nb) ? P[(size_t)k * ld + i] : 0.0;
     if (threadIdx.x == 0) sh.bad = 0;
     coop_columns(std::make_integer_sequence<int, QR_NB>{}, a, sh, mp, nb, part, head, tau, flags,
-                 base);
+                 base, spin);
 #pragma unroll
     for (int k = 0; k < QR_NB; ++k)
         if (live && k < nb) P[(size_t)k * ld + i] = a[k];
@@ -322,15 +327,19 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (t == 0) coh_store(flags + g, base + QR_NB + 1);
+    // a wait that ran out leaves this panel's factors invalid: report it in
+    // the caller's error word (read back with the run's status)
+    if (t == 0 && sh.bad && err) *err = 1;
     if (g != 0) return;
-    if (t < G) {
+    if (t < G && t != 0) {
         int it = 0;
-        while (coh_load(flags + t) < base + QR_NB + 1) {
-            if (++it > QR_COOP_SPIN) { sh.bad = 1; break; }
+        while (spin < 0 || coh_load(flags + t) < base + QR_NB + 1) {
+            if (spin < 0 || ++it > spin) { sh.bad = 1; break; }
             __builtin_amdgcn_s_sleep(1);
         }
     }
     __syncthreads();
+    if (t == 0 && sh.bad && err) *err = 1;
     double *Gs = sh.red;   // G (ld QR_NB), the rows of V are no longer needed
     for (int e = t; e < QR_NB * QR_NB; e += QR_RC) {
         double sacc = 0.0;
@@ -455,15 +464,43 @@ static void extract_v(hipStream_t s, int mp, int nb, const double *P, int ld, do
 
 // Factor one panel (mp x nb at P), leave its explicit V in Vb and build its T
 // from V^T V (FP64 matrix-core product).
+// Workgroups of qr_panel_coop that the current device holds at once (its
+// compute units times the kernel's occupancy per unit); cached per device.
+static int coop_capacity() {
+    static std::atomic<int> cap[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    int c = cap[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+    int ncu = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)qr_panel_coop, QR_RC, 0) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    c = ncu * per_cu;
+    cap[dev].store(c, std::memory_order_relaxed);
+    return c;
+}
+
 static void panel_factor(hipStream_t s, int mp, int nb, double *P, int ld, double *tau,
                          double *T, int ldt, QRScratch &q, int panel) {
     const int G = cdiv(mp, QR_RC);
-    if (G <= QR_COOP_MAXG) {
+    // the one-launch panel waits on every one of its workgroups, so it runs
+    // only when all of them fit on the device at once; its waits are bounded
+    // all the same (another stream may hold compute units), and one that runs
+    // out is reported through q.err
+    if (G <= QR_COOP_MAXG && G <= coop_capacity()) {
         // algorithmic work: the panel read and written once, 2 mp nb^2 flops
         if (q.kc) q.kc->begin(s, 7, 2.0 * mp * nb * sizeof(double), 2.0 * mp * nb * nb);
         // the panel, its explicit V and its T in one launch
         hipLaunchKernelGGL(qr_panel_coop, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.part, q.head,
-                           tau, q.flags, panel * 64, q.vb, q.vtv, T, ldt);
+                           tau, q.flags, panel * 64, q.vb, q.vtv, T, ldt, q.err,
+                           q.spin == 0 ? QR_COOP_SPIN : q.spin);
         if (q.kc) q.kc->end(s);
     } else {
         hipLaunchKernelGGL(qr_panel_init, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.part, q.head);

@@ -26,14 +26,15 @@ constexpr int CP_MAXN = 8192;    // pivot column cached in LDS
 
 template <typename T>
 __global__ __launch_bounds__(CP_NT) void qrcp_init(int n, const double *A1, int lda, T *W,
-                                                   T *nrm) {
+                                                   T *nrm, const double *scale) {
     // one wavefront per column: convert and take the full column norm
     const int lane = threadIdx.x & 63;
     const int j = blockIdx.x * (CP_NT / 64) + (threadIdx.x >> 6);
     if (j >= n) return;
+    const double f = scale ? *scale : 1.0;
     T s = 0;
     for (int i = lane; i < n; i += 64) {
-        const T v = (T)A1[(size_t)j * lda + i];
+        const T v = (T)(A1[(size_t)j * lda + i] * f);
         W[(size_t)j * n + i] = v;
         s += v * v;
     }
@@ -159,15 +160,17 @@ __device__ __forceinline__ bool cand_better(T v, int c, T bv, int bc) {
 
 template <typename T>
 __global__ __launch_bounds__(Q2_NT) void qrcp_init2(int n, const double *A1, int lda, T *W,
-                                                    int *perm, Cand<T> *cout) {
+                                                    int *perm, Cand<T> *cout,
+                                                    const double *scale) {
     __shared__ T cv[Q2_W];
     __shared__ int cc[Q2_W];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int j = blockIdx.x * Q2_W + w;
+    const double f = scale ? *scale : 1.0;
     T s = 0;
     if (j < n) {
         for (int i = lane; i < n; i += 64) {
-            const T v = (T)A1[(size_t)j * lda + i];
+            const T v = (T)(A1[(size_t)j * lda + i] * f);
             W[(size_t)j * n + i] = v;
             s += v * v;
         }
@@ -334,7 +337,8 @@ template <int RPL>
 __global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__restrict__ A1,
                                                      int lda, float *__restrict__ cbuf,
                                                      unsigned long long *__restrict__ keys,
-                                                     int *err, int *__restrict__ piv) {
+                                                     int *err, int *__restrict__ piv,
+                                                     const double *ascale, int spin) {
     typedef float T;
     // The step's pivot column in LDS, lane-major: row lane + 64 r of the
     // column sits at pc[lane * PL + r], so a lane reads the entries of its
@@ -352,11 +356,12 @@ __global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__res
     T x[RPL];
     T nv;
     {
+        const double f = ascale ? *ascale : 1.0;
         T ns = 0;
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int i = lane + 64 * r;
-            x[r] = (live && i < n) ? (T)A1[(size_t)j * lda + i] : T(0);
+            x[r] = (live && i < n) ? (T)(A1[(size_t)j * lda + i] * f) : T(0);
             ns += x[r] * x[r];
         }
         nv = live ? tsqrt(wave_sum(ns)) : T(-1);
@@ -400,8 +405,8 @@ __global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__res
             int it = 0;
             for (;;) {
                 gk = coh_load(keys + (size_t)buf * nwg + t);
-                if ((int)(gk >> QP_TAG) == k + 1) break;
-                if (++it > QP_SPIN) { bad = 1; gk = 0ull; break; }
+                if ((int)(gk >> QP_TAG) == k + 1 && spin >= 0) break;
+                if (spin < 0 || ++it > spin) { bad = 1; gk = 0ull; break; }
                 __builtin_amdgcn_s_sleep(1);
             }
         }
@@ -536,7 +541,9 @@ size_t qrcp_scratch_bytes(int n, int elem) {
 // The one-launch FP32 pass; false when it does not apply or could not run
 // (then nothing observable has changed and the caller takes the step path).
 static bool qrcp_persist_pass(hipStream_t s, int n, const double *A1, int lda, float *W,
-                              void *scratch, int *piv, KernelClock *kc) {
+                              void *scratch, int *piv, KernelClock *kc, const double *scale,
+                              int spin) {
+    const int sp = spin == 0 ? QP_SPIN : spin;
     if (n < 128 || n > 64 * 64) return false;
     const int nwg = cdiv(n, QP_W);
     unsigned long long *keys = (unsigned long long *)scratch;
@@ -561,13 +568,13 @@ static bool qrcp_persist_pass(hipStream_t s, int n, const double *A1, int lda, f
     if (kc) kc->begin(s, SVD_K_QRCP, qrcp_pass_bytes(n, sizeof(float)), qrcp_pass_flops(n));
     if (n <= 64 * 16)
         hipLaunchKernelGGL((qrcp_persist<16>), dim3(nwg), dim3(QP_NT), 0, s, n, A1, lda, cbuf, keys,
-                           err, piv);
+                           err, piv, scale, sp);
     else if (n <= 64 * 32)
         hipLaunchKernelGGL((qrcp_persist<32>), dim3(nwg), dim3(QP_NT), 0, s, n, A1, lda, cbuf, keys,
-                           err, piv);
+                           err, piv, scale, sp);
     else
         hipLaunchKernelGGL((qrcp_persist<64>), dim3(nwg), dim3(QP_NT), 0, s, n, A1, lda, cbuf, keys,
-                           err, piv);
+                           err, piv, scale, sp);
     if (kc) kc->end(s);
     if (hipGetLastError() != hipSuccess) return false;
     int h_err = 1;
@@ -581,12 +588,12 @@ static bool qrcp_persist_pass(hipStream_t s, int n, const double *A1, int lda, f
 
 template <typename T>
 int qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, void *scratch, int *piv,
-                KernelClock *kc) {
+                KernelClock *kc, const double *scale, int spin) {
     if (n <= 0) return 0;
     if (n > 64 * 64) {
         T *norms2 = (T *)scratch;
         hipLaunchKernelGGL((qrcp_init<T>), dim3(cdiv(n, CP_NT / 64)), dim3(CP_NT), 0, s, n, A1, lda,
-                           W, norms2);
+                           W, norms2, scale);
         for (int k = 0; k < n; ++k) {
             const T *nin = norms2 + (size_t)(k & 1) * n;
             T *nout = norms2 + (size_t)((k + 1) & 1) * n;
@@ -597,13 +604,13 @@ int qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, void *scr
         }
         return n;
     }
-    if (sizeof(T) == 4 && qrcp_persist_pass(s, n, A1, lda, (float *)W, scratch, piv, kc))
+    if (sizeof(T) == 4 && qrcp_persist_pass(s, n, A1, lda, (float *)W, scratch, piv, kc, scale, spin))
         return 1;
     int *perm = (int *)scratch;
     const size_t ncand = (size_t)cdiv(n, Q2_W) + 1;
     Cand<T> *cand = (Cand<T> *)((char *)scratch + (((size_t)n * sizeof(int) + 63) / 64) * 64);
     hipLaunchKernelGGL((qrcp_init2<T>), dim3(cdiv(n, Q2_W)), dim3(Q2_NT), 0, s, n, A1, lda, W, perm,
-                       cand);
+                       cand, scale);
     for (int k = 0; k < n; ++k) {
         const Cand<T> *cin = cand + (size_t)(k & 1) * ncand;
         Cand<T> *cout = cand + (size_t)((k + 1) & 1) * ncand;
@@ -625,8 +632,8 @@ int qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, void *scr
 }
 
 template int qrcp_pivots<float>(hipStream_t, int, const double *, int, float *, void *, int *,
-                                KernelClock *);
+                                KernelClock *, const double *, int);
 template int qrcp_pivots<double>(hipStream_t, int, const double *, int, double *, void *, int *,
-                                 KernelClock *);
+                                 KernelClock *, const double *, int);
 
 } // namespace mpj
