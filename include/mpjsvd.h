@@ -67,6 +67,8 @@ extern "C" {
 #define SVD_BRANCH_SKIP 2        /* Q = I: go straight to FP64 sweeps       */
 
 #define SVD_ERR_HIP (-100)
+#define SVD_ERR_SCRATCH_LIMIT (-101) /* svd_backward_noalloc: the problem needs
+                                        more than its fixed scratch array     */
 
 typedef struct {
     /* Section 7.1 parameters.  tol_alg is recorded only: the low-precision
@@ -311,7 +313,32 @@ int svd_backward(int batch, int m, int n,
                  double *gA, long long sA, double eps_deg,
                  void *work, size_t work_bytes, void *stream);
 
-/* Human-readable name of a status or return code. */
+/*
+ * svd_backward_noalloc: svd_backward for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  It computes exactly what svd_backward computes, with the
+ * same kernel, but takes no workspace: its scratch is a fixed array of
+ * SVD_BACKWARD_NOALLOC_SCRATCH_BYTES in device memory inside the library
+ * (one per GPU, held from the library's first use on that GPU until the
+ * process ends).  Arguments 1-15 and `stream` as for svd_backward; call it
+ * with the stream's device current.
+ * Returns 0; -k for an invalid argument k as svd_backward; SVD_ERR_SCRATCH_LIMIT
+ * (nothing launched) when svd_backward_workspace_size(batch, m, n) exceeds the
+ * array; SVD_ERR_HIP on a runtime failure (svd_last_error() says which).
+ * The call allocates nothing (no hipMalloc, no hipFree, no allocating library
+ * routine) and is stream-ordered.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (different streams, or host threads
+ * without ordering) race and give undefined results; calls ordered on one
+ * stream are safe.  The kernel writes every scratch word before reading it,
+ * so the previous call's contents do not matter.
+ */
+#define SVD_BACKWARD_NOALLOC_SCRATCH_BYTES (64u << 20)
+int svd_backward_noalloc(int batch, int m, int n,
+                         const double *U, long long sU, const double *S, long long sS,
+                         const double *V, long long sV,
+                         const double *gU, const double *gS, const double *gV,
+                         double *gA, long long sA, double eps_deg, void *stream);
+
 /*
  * Mixed-precision symmetric eigensolver (Section 8, Algorithm 6):
  *   A = X diag(W) X^T for a symmetric n x n A (both triangles are read as
@@ -356,6 +383,7 @@ int eig_mixed(int n, const double *A, int lda, double *W, double *X, int ldx,
               void *work, size_t work_bytes, const svd_opts *o, eig_info *info,
               void *stream);
 
+/* Human-readable name of a status or return code. */
 const char *svd_status_string(int code);
 
 /* Description of the HIP failure behind the last SVD_ERR_HIP return of a

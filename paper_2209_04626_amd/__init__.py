@@ -23,13 +23,17 @@ TUNE_PATH = os.path.join(_HERE, "tune_gfx950.json")
 EXPORTS = [
     "svd_default_opts", "svd_workspace_size", "svd_plain", "svd_mixed",
     "svd_batched_plan_create", "svd_batched", "svd_batched_plan_destroy",
-    "svd_backward_workspace_size", "svd_backward", "svd_status_string", "svd_last_error",
+    "svd_backward_workspace_size", "svd_backward", "svd_backward_noalloc",
+    "svd_status_string", "svd_last_error",
     "svd_set_tuning", "svd_tuning_lookup", "eig_workspace_size", "eig_mixed",
 ]
 
 SVD_OK, SVD_WARN_NOCONV, SVD_ERR_NONFINITE, SVD_WARN_RANK_DEFICIENT = 0, 1, 2, 3
 EIG_ERR_CLUSTER = 4
 SVD_ERR_WAIT_TIMEOUT, SVD_ERR_BREAKDOWN = 5, 6
+SVD_ERR_HIP, SVD_ERR_SCRATCH_LIMIT = -100, -101
+# bytes of the fixed scratch array behind svd_backward_noalloc
+BACKWARD_NOALLOC_SCRATCH_BYTES = 64 << 20
 KERNEL_CLASSES = ["jac_gram<f32>", "jac_inner<f32>", "jac_update<f32>", "jac_gram<f64>",
                   "jac_inner<f64>", "jac_update<f64>", "qrcp", "qr_panel", "gemm", "-", "-", "-"]
 NCLASS = 12
@@ -140,6 +144,9 @@ def load():
                                  _ll, _vp, _vp, _vp, _vp, _ll, ctypes.c_double, _vp,
                                  ctypes.c_size_t, _vp]
     lib.svd_backward.restype = ctypes.c_int
+    lib.svd_backward_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _ll, _vp, _ll,
+                                         _vp, _ll, _vp, _vp, _vp, _vp, _ll, ctypes.c_double, _vp]
+    lib.svd_backward_noalloc.restype = ctypes.c_int
     lib.eig_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(SvdOpts)]
     lib.eig_workspace_size.restype = ctypes.c_size_t
     lib.eig_mixed.argtypes = [ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp,
@@ -382,10 +389,11 @@ def unpack_batch(plan: BatchedPlan, S, U, V):
 
 # ----------------------------------------------------------------------------- backward
 def svd_backward(U, S, V, gU=None, gS=None, gV=None, eps_deg: float = 1e-12,
-                 workspace: Workspace | None = None):
+                 workspace: Workspace | None = None, noalloc: bool = False):
     """Batched adjoint.  U (B, m, n), S (B, n), V (B, n, n) float64 CUDA
     tensors (any strides); cotangents of the same shapes or None.  Returns gA
-    (B, m, n)."""
+    (B, m, n).  noalloc=True calls svd_backward_noalloc (the library's fixed
+    scratch array instead of a workspace)."""
     import torch
     lib = load()
     for t, nm in ((U, "U"), (S, "S"), (V, "V")):
@@ -401,6 +409,18 @@ def svd_backward(U, S, V, gU=None, gS=None, gV=None, eps_deg: float = 1e-12,
     gUc, gVc = cm(gU), cm(gV)
     gSc = None if gS is None else gS.contiguous()
     gA = torch.empty((Bt, n, m), dtype=torch.float64, device=dev)
+    if noalloc:
+        with torch.cuda.device(dev):
+            rc = lib.svd_backward_noalloc(
+                Bt, m, n, Uc.data_ptr(), m * n, Sc.data_ptr(), n, Vc.data_ptr(), n * n,
+                gUc.data_ptr() if gUc is not None else None,
+                gSc.data_ptr() if gSc is not None else None,
+                gVc.data_ptr() if gVc is not None else None,
+                gA.data_ptr(), m * n, float(eps_deg), _stream_ptr(dev))
+        if rc != 0:
+            raise RuntimeError(f"svd_backward_noalloc returned {rc}: "
+                               f"{lib.svd_last_error().decode()}")
+        return gA.transpose(1, 2)
     nbytes = int(lib.svd_backward_workspace_size(Bt, m, n))
     ws = (workspace or _ws_default).get(nbytes, dev)
     with torch.cuda.device(dev):

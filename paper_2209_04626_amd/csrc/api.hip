@@ -17,6 +17,7 @@ static thread_local char g_last_error[256] = "";
 void note_hip_error(hipError_t e, const char *where) {
     snprintf(g_last_error, sizeof(g_last_error), "%s: %s", where, hipGetErrorString(e));
 }
+void note_error_text(const char *msg) { snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
 } // namespace mpj
 
 extern "C" const char *svd_last_error(void) { return mpj::g_last_error; }
@@ -604,6 +605,7 @@ extern "C" const char *svd_status_string(int code) {
     case SVD_ERR_WAIT_TIMEOUT: return "error: a bounded cross-workgroup wait ran out; outputs undefined";
     case SVD_ERR_BREAKDOWN: return "error: a non-finite singular value from finite input; outputs undefined";
     case SVD_ERR_HIP: return "error: HIP runtime failure";
+    case SVD_ERR_SCRATCH_LIMIT: return "error: the problem needs more scratch than the fixed array holds";
     default: return code < 0 ? "error: invalid argument" : "unknown status";
     }
 }

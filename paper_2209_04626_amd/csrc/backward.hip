@@ -8,6 +8,10 @@
 // where the last term and gU S^-1 together are (I - U U^T) gU S^-1 V^T.
 // One workgroup per matrix; the products run on the FP64 matrix cores with
 // 64 x 64 output tiles staged through LDS; J, K, M, Z live in the workspace.
+#include <stdio.h>
+
+#include <mutex>
+
 #include "../../include/mpjsvd.h"
 #include "common.hpp"
 #include "internal.hpp"
@@ -69,6 +73,44 @@ __global__ __launch_bounds__(BW_NT) void k_svd_backward(
     wg_gemm<false, true>(m, n, n, Zw, m, v, n, ga, m, false, As, Bs);
 }
 
+// Scratch of svd_backward_noalloc: a fixed device array in place of the
+// caller's workspace.  Each GPU the library runs on holds its own copy from
+// the load of the code object until the process ends.  Host code never uses
+// the array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device.
+static __device__ __align__(256) double scratch[SVD_BACKWARD_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+constexpr int BW_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[BW_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device).  0, or SVD_ERR_HIP with svd_last_error() set.
+int scratch_address(double **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) { note_hip_error(e, "svd_backward_noalloc: hipGetDevice"); return SVD_ERR_HIP; }
+    if (dev < 0 || dev >= BW_MAX_DEVICES) {
+        note_hip_error(hipErrorInvalidDevice, "svd_backward_noalloc: device index");
+        return SVD_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            note_hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                           "svd_backward_noalloc: hipGetSymbolAddress(scratch)");
+            return SVD_ERR_HIP;
+        }
+        g_scratch_dev[dev] = (double *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return 0;
+}
+} // namespace
+
 } // namespace mpj
 
 using namespace mpj;
@@ -78,10 +120,10 @@ extern "C" size_t svd_backward_workspace_size(int batch, int m, int n) {
     return (size_t)batch * (3 * (size_t)n * n + (size_t)m * n) * sizeof(double) + 256;
 }
 
-extern "C" int svd_backward(int batch, int m, int n, const double *U, long long sU, const double *S,
-                            long long sS, const double *V, long long sV, const double *gU,
-                            const double *gS, const double *gV, double *gA, long long sA,
-                            double eps_deg, void *work, size_t work_bytes, void *stream) {
+// Arguments 1-14 and 16 (stream) as for svd_backward; nothing is allocated.
+static int check_backward_args(int batch, int m, int n, const double *U, long long sU,
+                               const double *S, long long sS, const double *V, long long sV,
+                               double *gA, long long sA) {
     if (batch < 0) return -1;
     if (m < 1 || m < n) return -2;
     if (n < 1) return -3;
@@ -93,6 +135,15 @@ extern "C" int svd_backward(int batch, int m, int n, const double *U, long long 
     if (sV < (long long)n * n && batch > 1) return -9;
     if (!gA) return -13;
     if (sA < (long long)m * n && batch > 1) return -14;
+    return 0;
+}
+
+extern "C" int svd_backward(int batch, int m, int n, const double *U, long long sU, const double *S,
+                            long long sS, const double *V, long long sV, const double *gU,
+                            const double *gS, const double *gV, double *gA, long long sA,
+                            double eps_deg, void *work, size_t work_bytes, void *stream) {
+    const int rc = check_backward_args(batch, m, n, U, sU, S, sS, V, sV, gA, sA);
+    if (rc) return rc;
     if (batch == 0) return 0;
     if (!work) return -16;
     if (work_bytes < svd_backward_workspace_size(batch, m, n)) return -17;
@@ -100,4 +151,32 @@ extern "C" int svd_backward(int batch, int m, int n, const double *U, long long 
     hipLaunchKernelGGL(k_svd_backward, dim3(batch), dim3(BW_NT), 0, (hipStream_t)stream, m, n, U, sU,
                        S, sS, V, sV, gU, gS, gV, gA, sA, eps_deg, (double *)work);
     return hipGetLastError() == hipSuccess ? 0 : SVD_ERR_HIP;
+}
+
+extern "C" int svd_backward_noalloc(int batch, int m, int n, const double *U, long long sU,
+                                    const double *S, long long sS, const double *V, long long sV,
+                                    const double *gU, const double *gS, const double *gV, double *gA,
+                                    long long sA, double eps_deg, void *stream) {
+    const int rc = check_backward_args(batch, m, n, U, sU, S, sS, V, sV, gA, sA);
+    if (rc) return rc;
+    if (batch == 0) return 0;
+    const size_t need = svd_backward_workspace_size(batch, m, n);
+    if (need > SVD_BACKWARD_NOALLOC_SCRATCH_BYTES) {
+        char msg[160];
+        snprintf(msg, sizeof(msg), "svd_backward_noalloc: %zu bytes of scratch needed, the fixed "
+                 "array holds %zu", need, (size_t)SVD_BACKWARD_NOALLOC_SCRATCH_BYTES);
+        note_error_text(msg);
+        return SVD_ERR_SCRATCH_LIMIT;
+    }
+    double *work = nullptr;
+    const int ra = scratch_address(&work);
+    if (ra) return ra;
+    if (!(eps_deg > 0.0)) eps_deg = 1e-12;
+    // every word of the scratch the kernel reads it writes first (J, K, M, Z
+    // per matrix), so the previous call's contents need no clearing
+    hipLaunchKernelGGL(k_svd_backward, dim3(batch), dim3(BW_NT), 0, (hipStream_t)stream, m, n, U, sU,
+                       S, sS, V, sV, gU, gS, gV, gA, sA, eps_deg, work);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { note_hip_error(e, "svd_backward_noalloc launch"); return SVD_ERR_HIP; }
+    return 0;
 }

@@ -250,6 +250,8 @@ namespace mpj {
 // Records the first HIP failure of the current call (thread-local) so that
 // svd_last_error() can report it.
 void note_hip_error(hipError_t e, const char *where);
+// Records a message (no HIP error behind it) for svd_last_error().
+void note_error_text(const char *msg);
 }
 
 #define MPJ_CHECK(x)                                                        \
