@@ -160,7 +160,16 @@ typedef struct {
                               -1 = give up at the first check (a test hook
                               for the time-out paths: the pivot pass then
                               falls back to per-step launches, the panel
-                              reports SVD_ERR_WAIT_TIMEOUT); < -1 invalid */
+                              reports SVD_ERR_WAIT_TIMEOUT, the fused FP32
+                              round restarts the FP32 stage with separate
+                              kernels); < -1 invalid */
+    int fused_rounds;      /* FP32 stage without V_low (switch method 1):
+                              0 (default) = one launch per block-Jacobi round
+                              (Gram, inner solve and update fused, 32-column
+                              blocks) for n >= 2048 when the device holds the
+                              whole grid at once, else separate kernels;
+                              1 = the fused round at any n where it fits;
+                              -1 = always the separate kernels */
 } svd_opts;
 
 /* Kernel classes reported by svd_info.kern_* (kernel_timing 1: SVD_K_QRCP
@@ -174,6 +183,8 @@ typedef struct {
 #define SVD_K_QRCP 6       /* pivot pass launches (one, or one per step) */
 #define SVD_K_QRPANEL 7    /* Householder panel factorisations        */
 #define SVD_K_GEMM 8       /* matrix-core GEMMs (with their split-K sums) */
+#define SVD_K_ROUND32 9    /* fused FP32 Jacobi round (Gram, inner solve
+                              and update in one launch)               */
 #define SVD_K_NCLASS 12
 
 typedef struct {
@@ -203,6 +214,8 @@ typedef struct {
                               measured */
     int n_y2;              /* columns in Y2 (0: the safeguard did not act) */
     int sweeps_y2;         /* FP64 sweeps run on Y2 alone */
+    int fused_fallback;    /* 1: a fused FP32 round gave up waiting and the
+                              FP32 stage was run again with separate kernels */
 } svd_info;
 
 /* Load the tuning table measured by the autotuner (not part of the paper's

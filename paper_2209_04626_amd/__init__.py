@@ -35,7 +35,8 @@ SVD_ERR_HIP, SVD_ERR_SCRATCH_LIMIT = -100, -101
 # bytes of the fixed scratch array behind svd_backward_noalloc
 BACKWARD_NOALLOC_SCRATCH_BYTES = 64 << 20
 KERNEL_CLASSES = ["jac_gram<f32>", "jac_inner<f32>", "jac_update<f32>", "jac_gram<f64>",
-                  "jac_inner<f64>", "jac_update<f64>", "qrcp", "qr_panel", "gemm", "-", "-", "-"]
+                  "jac_inner<f64>", "jac_update<f64>", "qrcp", "qr_panel", "gemm", "jac_round<f32>",
+                  "-", "-"]
 NCLASS = 12
 BRANCH_AUTO, BRANCH_LOW, BRANCH_SKIP = 0, 1, 2
 
@@ -56,6 +57,7 @@ class SvdOpts(ctypes.Structure):
         ("inner_pairs", ctypes.c_int), ("tol_cluster", ctypes.c_double),
         ("y2_safeguard", ctypes.c_int), ("tol_y2", ctypes.c_double),
         ("kernel_timing_every", ctypes.c_int), ("wait_polls", ctypes.c_int),
+        ("fused_rounds", ctypes.c_int),
     ]
 
 
@@ -69,7 +71,7 @@ class SvdInfo(ctypes.Structure):
         ("kern_bytes", ctypes.c_double * NCLASS), ("kern_flops", ctypes.c_double * NCLASS),
         ("v_method_taken", ctypes.c_int), ("sweeps_vfix", ctypes.c_int),
         ("orth_vx", ctypes.c_double), ("orth_y", ctypes.c_double),
-        ("n_y2", ctypes.c_int), ("sweeps_y2", ctypes.c_int),
+        ("n_y2", ctypes.c_int), ("sweeps_y2", ctypes.c_int), ("fused_fallback", ctypes.c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -85,6 +87,7 @@ class SvdInfo(ctypes.Structure):
             "v_method_taken": self.v_method_taken, "sweeps_vfix": self.sweeps_vfix,
             "orth_vx": self.orth_vx, "orth_y": self.orth_y,
             "n_y2": self.n_y2, "sweeps_y2": self.sweeps_y2,
+            "fused_fallback": self.fused_fallback,
         }
 
 

@@ -54,6 +54,7 @@ extern "C" void svd_default_opts(svd_opts *o, int mixed) {
     o->tol_y2 = 0.0;
     o->kernel_timing_every = 1;
     o->wait_polls = 0;
+    o->fused_rounds = 0;
 }
 
 namespace {
@@ -68,6 +69,13 @@ struct Layout {
         off_v32, off_v2, off_idx, total;
 };
 
+// Whether the FP32 stage asks for the fused round (it still falls back to
+// the separate kernels where the grid does not fit the device).
+bool fused_low(int n, const svd_opts &o) {
+    if (o.fused_rounds < 0 || o.switch_method != 1) return false;
+    return o.fused_rounds > 0 || n >= 2048;
+}
+
 // Jacobi block width per stage: the FP32 stage is bound by the latency of
 // the inner 2b x 2b solves (b = 16 keeps them short), the FP64 stage with V by
 // the traffic of the block updates (b = 32 halves the rounds per sweep).
@@ -76,6 +84,8 @@ int pick_b(int n, const svd_opts &o, bool low) {
     const int stage = low ? o.block_cols_low : o.block_cols_work;
     if (ok(stage)) return stage;
     if (ok(o.block_cols)) return o.block_cols;
+    // the fused FP32 round works on 32-column blocks
+    if (low && fused_low(n, o)) return 32;
     const int t = tuned_block_cols(n, low);
     if (ok(t)) return t;
     if (low) return 16;
@@ -216,6 +226,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     if (o.y2_safeguard != 0 && o.y2_safeguard != 1) return -12;
     if (o.kernel_timing_every < 0) return -12;
     if (o.wait_polls < -1) return -12;
+    if (o.fused_rounds < -1 || o.fused_rounds > 1) return -12;
     if (info) {
         memset(info, 0, sizeof(*info));
         info->orth = -1.0;
@@ -348,7 +359,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
 
     const double eps_low = o.eps_low > 0 ? o.eps_low : sqrt((double)n) * ldexp(1.0, -24);
     const double eps_work = o.eps_work > 0 ? o.eps_work : sqrt((double)n) * ldexp(1.0, -53);
-    int sweeps_low = 0, conv_low = 1;
+    int sweeps_low = 0, conv_low = 1, fused_fallback = 0;
     if (branch == SVD_BRANCH_LOW) {
         // a6: FP32 one-sided Jacobi on low(X) (Section 3.2); V_low is only
         // accumulated for switch methods 2 and 3
@@ -367,8 +378,23 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         jw.off_hist = off_low;
         jw.stop_off = o.low_stop_off > 0 ? o.low_stop_off
                                          : (o.low_stop_off == 0 ? sqrt((double)n) * eps_low : 0.0);
+        jw.fused = fused_low(n, o) ? 1 : 0;
+        jw.spin = o.wait_polls;
         sweeps_low = jacobi_sweeps<float>(s, N, L.b32, Y32, V32, eps_low, o.maxsweep_low, inner,
                                           jw, &conv_low);
+        if (sweeps_low == -2) {
+            // a fused round gave up waiting (another stream held compute
+            // units): the stage starts again from low(X) with separate kernels
+            (void)hipGetLastError();
+            mpj::g_last_error[0] = 0;
+            fused_fallback = 1;
+            convert_f64_f32(s, N, N, X, N, Y32, N, &sm->lowscale);
+            jw.fused = 0;
+            for (int i = 0; i < 32; ++i) off_low[i] = 0.f;
+            sweeps_low = jacobi_sweeps<float>(s, N, L.b32, Y32, V32, eps_low, o.maxsweep_low, inner,
+                                              jw, &conv_low);
+        }
+        jw.fused = 0;
         jw.stop_off = 0.0;
         if (sweeps_low < 0) return SVD_ERR_HIP;
         tm.mark(5);
@@ -563,6 +589,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         info->orth_y = orth_y;
         info->n_y2 = n_y2;
         info->sweeps_y2 = sweeps_y2;
+        info->fused_fallback = fused_fallback;
         int st = SVD_OK;
         if (!conv_work) st = SVD_WARN_NOCONV;
         if (hs.nzero) st = SVD_WARN_RANK_DEFICIENT;

@@ -68,10 +68,10 @@ __device__ __forceinline__ int block_or(int v, int *red) {
 
 // Loads and stores that are coherent across the chip's L2 caches (relaxed
 // atomics at device scope).  Workgroups of one launch exchange data through
-// them: the writer stores, waits for its stores to complete (a
-// workgroup-scope release fence), then raises a flag with coh_store; the
-// reader polls the flag with coh_load and reads the data with coh_load.  No
-// cache-wide write-back or invalidate is involved.
+// them: the writer stores with coh_store, waits for its stores to complete
+// (publish_fence), then one thread raises a flag with coh_store after a
+// barrier; the reader polls the flag with coh_load and reads the data with
+// coh_load.  No cache-wide write-back or invalidate is involved.
 template <typename U>
 __device__ __forceinline__ void coh_store(U *p, U v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -79,6 +79,24 @@ __device__ __forceinline__ void coh_store(U *p, U v) {
 template <typename U>
 __device__ __forceinline__ U coh_load(const U *p) {
     return __hip_atomic_load(const_cast<U *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Every thread's coherent stores complete before the barrier that precedes
+// the flag: s_waitcnt vmcnt(0).  (A workgroup-scope release fence emits no
+// wait on gfx950, and stores to different addresses may complete out of
+// order, so without it the flag could become visible before the data.)
+__device__ __forceinline__ void publish_fence() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt unchanged
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+}
+
+// 16-byte form of coh_load for FP32 data: a buffer load with the same cache
+// policy (sc1) as a device-scope relaxed atomic load.  byte_off from base,
+// 16-byte aligned.
+__device__ __forceinline__ flt4 coh_load4(const float *base, int byte_off) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), 0, 0x7fffffff, 0x00020000);
+    return __builtin_amdgcn_raw_buffer_load_b128(rs, byte_off, 0, 16);
 }
 
 // 16x16x4 MFMA, FP64 and FP32.  Operand layout for lane l of the wavefront:

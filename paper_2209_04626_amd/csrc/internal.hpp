@@ -182,7 +182,8 @@ struct JacobiWork {
     void *gram;      // partial Gram blocks
     void *wmat;      // per-pair rotation blocks
     int *skip;       // per-pair "nothing to rotate" flags
-    int *flag;       // device: [0] any rotation this sweep
+    int *flag;       // device: [0] any rotation this sweep, [1] a fused
+                     // round's wait ran out
     int *hflag;      // host copy of flag[0..2]
     float *offp;     // device, per pair slot: max relative off-diagonal
                      // |g_pq| / sqrt(g_pp g_qq) seen this sweep
@@ -194,12 +195,18 @@ struct JacobiWork {
     int cross_pairs = 0;        // 1: after a sweep's first round, rotate only the
                                 // pairs between the two blocks of each block pair
     int *rotmap = nullptr;      // device: per round and pair slot, 1 if rotated
+    float *gpart = nullptr;     // device: partial Gram blocks of the fused FP32 round
+    int *gflag = nullptr;       // device: their flags
+    int fused = 0;              // 1: FP32 sweeps without V may use the fused round
+    int spin = 0;               // polls of the fused round's wait (0 = default,
+                                // < 0 = give up at once, a test hook)
 };
 size_t jacobi_scratch_bytes(int N, int b, int elem);
 void jacobi_carve(JacobiWork &j, char *base, int N, int b, int elem);
 // One-sided block-Jacobi sweeps on Y (N x N padded, ld N) with optional V
-// accumulation (V: N x N, ld N).  Returns the number of sweeps run; *conv set
-// to 1 if the last sweep rotated nothing.
+// accumulation (V: N x N, ld N).  Returns the number of sweeps run (-1 on a
+// HIP error, -2 when a bounded wait of the fused FP32 round ran out, which
+// leaves Y invalid); *conv set to 1 if the last sweep rotated nothing.
 template <typename T>
 int jacobi_sweeps(hipStream_t s, int N, int b, T *Y, T *V, double eps,
                   int maxsweep, int max_inner, JacobiWork &jw, int *conv);

@@ -19,9 +19,12 @@
 // in which no block pair needed a rotation on a freshly computed Gram block.
 #include <hip/hip_ext.h>
 
+#include <atomic>
+
 #include <utility>
 #include <vector>
 
+#include "../../include/mpjsvd.h"
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -30,6 +33,11 @@ namespace mpj {
 constexpr int JR_NT = 256;   // threads per workgroup
 
 constexpr int JU_RG = 256;   // rows per workgroup of the update
+
+constexpr int JF_MAX_WG = 512;      // workgroups of a fused FP32 round
+constexpr int JF_MAX_G = 16;        // workgroups per pair slot
+constexpr int JF_MAX_TILES = 10;    // upper 16 x 16 tiles of a 64-wide block
+constexpr int JF_SPIN = 1 << 22;    // default polls of the fused round's wait
 
 // Rows per workgroup of the Gram kernels: a quarter of N in whole 64-row
 // stripes, between 256 and 1024.  Each workgroup writes one partial Gram
@@ -248,21 +256,179 @@ __device__ __forceinline__ bool jac_rot_test(double al, double be, double ga, do
     return true;
 }
 
+template <typename T, int B2, int NT, int NTW, bool CROSS>
+__device__ __forceinline__ float inner_rounds_t(T (*G)[B2 * (B2 + 1)], T *W, int *ired, double eps2,
+                                                int max_inner) {
+    constexpr int LD = B2 + 1;
+    constexpr int H = B2 / 2;
+    constexpr int M = B2 - 1;
+    constexpr int CG = NTW / H;           // thread groups along c
+    constexpr int GPT = H / CG;           // 2x2 groups per thread
+    constexpr int RPT = B2 / CG;          // W rows per thread
+    constexpr int NRS = sizeof(T) == 4 ? 1 : 2;
+    static_assert(CG * H == NTW && GPT * CG == H && RPT * CG == B2, "tiling");
+    static_assert(64 % H == 0 && NTW % 64 == 0 && NTW <= NT, "every wavefront holds every pair index");
+    const int tid = threadIdx.x;
+    // threads from NTW on (whole wavefronts) only keep step with the barriers
+    const bool work = NTW == NT || tid < NTW;
+    const int a = tid % H, cg = tid / H;
+    const int c0 = cg * GPT, w0 = cg * RPT;
+    const bool own_diag = a / GPT == cg;      // this thread holds group (a, a)
+    const int kd = a % GPT;
+    // schedule positions of pair a and of the thread's pairs c at round 0
+    int ax = a, ay = CROSS ? H + a : (a == 0 ? M : M - a);
+    int cx[GPT], cy[GPT];
+#pragma unroll
+    for (int k = 0; k < GPT; ++k) {
+        const int c = c0 + k;
+        cx[k] = c;
+        cy[k] = CROSS ? H + c : (c == 0 ? M : M - c);
+    }
+    // Between the two blocks, pair a always rotates column a of the first
+    // block: its rows of W's column a, its entries (a, c) of G and g_aa stay
+    // in registers for the whole solve (only this thread writes them; every
+    // thread of pair a updates g_aa identically).  Those LDS copies go stale.
+    T wpr[RPT], greg[GPT];
+    double alp_r = 0.0;
+    if (CROSS && work) {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) wpr[j] = W[(w0 + j) * LD + a];
+#pragma unroll
+        for (int k = 0; k < GPT; ++k) greg[k] = G[0][a * LD + c0 + k];
+        alp_r = (double)G[0][a * LD + a];
+    }
+    const int nround = CROSS ? H : M;
+    float smax = 0.f;   // largest |sin| of the rotations of pair a (owner only)
+    int cur = 0;
+    for (int sw = 0; sw < max_inner; ++sw) {
+        int rotated = 0;
+        for (int rd = 0; rd < nround; ++rd) {
+          if (work) {
+            const T *g = G[cur];
+            T *gn = G[cur ^ 1];
+            const int p = min(ax, ay), q = max(ax, ay);
+            const double alp = CROSS ? alp_r : (double)g[p * LD + p];
+            const double bep = (double)g[q * LD + q];
+            const double gap = (double)g[p * LD + q];
+            int r[GPT], s[GPT];
+            T blk[GPT][4];
+#pragma unroll
+            for (int k = 0; k < GPT; ++k) {
+                r[k] = min(cx[k], cy[k]);
+                s[k] = max(cx[k], cy[k]);
+                blk[k][0] = CROSS ? greg[k] : g[p * LD + r[k]];
+                blk[k][1] = g[p * LD + s[k]];
+                blk[k][2] = g[q * LD + r[k]]; blk[k][3] = g[q * LD + s[k]];
+            }
+            T wp[RPT], wq[RPT];
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                wp[j] = CROSS ? wpr[j] : W[(w0 + j) * LD + p];
+                wq[j] = W[(w0 + j) * LD + q];
+            }
+            double ca, sa, ta;
+            const bool ra = jac_rot_test<NRS>(alp, bep, gap, eps2, &ca, &sa, &ta);
+            if (own_diag && ra) {
+                rotated = 1;
+                smax = fmaxf(smax, (float)fabs(sa));
+            }
+            const T c1 = (T)ca, s1 = (T)sa;
+            // W <- W J on the column pair (p, q): x_p' = c x_p - s x_q, x_q' = s x_p + c x_q
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                const T np_ = c1 * wp[j] - s1 * wq[j];
+                if constexpr (CROSS) wpr[j] = np_;
+                else W[(w0 + j) * LD + p] = np_;
+                W[(w0 + j) * LD + q] = s1 * wp[j] + c1 * wq[j];
+            }
+            // G <- J^T G J on the groups: rows (p, q) by pair a, columns (r, s) by pair c
+#pragma unroll
+            for (int k = 0; k < GPT; ++k) {
+                const T c2 = __shfl(c1, c0 + k, 64), s2 = __shfl(s1, c0 + k, 64);
+                const T h00 = c1 * blk[k][0] - s1 * blk[k][2], h01 = c1 * blk[k][1] - s1 * blk[k][3];
+                const T h10 = s1 * blk[k][0] + c1 * blk[k][2], h11 = s1 * blk[k][1] + c1 * blk[k][3];
+                T o00 = c2 * h00 - s2 * h01, o01 = s2 * h00 + c2 * h01;
+                T o10 = c2 * h10 - s2 * h11, o11 = s2 * h10 + c2 * h11;
+                if (own_diag && k == kd && ra) {
+                    // the diagonal group: the rotation zeroes g_pq exactly
+                    o00 = (T)(alp - ta * gap);
+                    o11 = (T)(bep + ta * gap);
+                    o01 = T(0); o10 = T(0);
+                }
+                if constexpr (CROSS) greg[k] = o00;
+                else gn[p * LD + r[k]] = o00;
+                gn[p * LD + s[k]] = o01;
+                gn[q * LD + r[k]] = o10; gn[q * LD + s[k]] = o11;
+            }
+            if constexpr (CROSS) {
+                if (ra) alp_r = (double)(T)(alp - ta * gap);
+            }
+          }
+            __syncthreads();
+            cur ^= 1;
+            if constexpr (CROSS) {
+                // next round: the second block's partner advances by one (mod b)
+                ay = ay + 1 == B2 ? H : ay + 1;
+#pragma unroll
+                for (int k = 0; k < GPT; ++k) cy[k] = cy[k] + 1 == B2 ? H : cy[k] + 1;
+            } else {
+                // next round: every schedule position advances by one (mod
+                // 2b-1), except the fixed partner 2b-1 of pair 0
+                ax = ax + 1 == M ? 0 : ax + 1;
+                if (a != 0) ay = ay + 1 == M ? 0 : ay + 1;
+#pragma unroll
+                for (int k = 0; k < GPT; ++k) {
+                    cx[k] = cx[k] + 1 == M ? 0 : cx[k] + 1;
+                    if (c0 + k != 0) cy[k] = cy[k] + 1 == M ? 0 : cy[k] + 1;
+                }
+            }
+        }
+        // positions after a full cycle are back where they started
+        if (!block_or<NT>(rotated, ired)) break;
+    }
+    if constexpr (CROSS) {
+        if (work) {
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) W[(w0 + j) * LD + a] = wpr[j];
+        }
+        __syncthreads();
+    }
+    return smax;
+}
+
+// Cyclic rounds of disjoint rotations on the 2b x 2b block G (LDS, row
+// stride B2 + 1, double-buffered: G[0] holds the symmetric block on entry),
+// accumulating W = prod J (LDS, the identity on entry), until a full cycle
+// rotates nothing or max_inner cycles have run.  Round rd rotates the column
+// pairs of the round-robin schedule (pair k joins (rd + k) mod (2b-1) and
+// (rd - k) mod (2b-1); pair 0 joins rd and 2b-1); 2b - 1 rounds reach every
+// pair of the 2b columns.  With cross set, only the b^2 pairs between the two
+// blocks are rotated: round rd joins column k of the first block with column
+// (k + rd) mod b of the second, b rounds.  Thread (a, g) computes the rotation
+// of pair a from the current G and owns the 2x2 groups {p_a, q_a} x {p_c, q_c}
+// of G for its GPT pairs c (the groups tile G) and RPT rows of W's column
+// pair a.  Pair c's rotation comes from the lane of the same wavefront whose
+// pair is c (every wavefront holds every pair index), so a round reads G from
+// one LDS buffer, writes the rotated G to the other, and needs a single
+// barrier; no thread branches on its role.  Every thread of the workgroup
+// calls it; only the first NTW threads work, the rest (whole wavefronts) keep
+// step with the barriers.  Returns the largest |sin| of the rotations of this
+// thread's pair (0 for threads that do not own a diagonal group).  W is
+// complete in LDS on return; G is not (with cross set, part of it was kept in
+// registers).
+template <typename T, int B2, int NT, int NTW = NT>
+__device__ __forceinline__ float inner_rounds(T (*G)[B2 * (B2 + 1)], T *W, int *ired, double eps2,
+                                              int max_inner, int cross) {
+    return cross ? inner_rounds_t<T, B2, NT, NTW, true>(G, W, ired, eps2, max_inner)
+                 : inner_rounds_t<T, B2, NT, NTW, false>(G, W, ired, eps2, max_inner);
+}
+
 // Inner solve of one block pair.  G and the accumulated W are held in the
 // stage's precision T (FP32 in the FP32 stage, FP64 in the FP64 stage); every
-// rotation angle and threshold test is evaluated in FP64.
-//
-// Round rd rotates the column pairs of the round-robin schedule (pair k joins
-// (rd + k) mod (2b-1) and (rd - k) mod (2b-1); pair 0 joins rd and 2b-1);
-// 2b - 1 rounds reach every pair of the 2b columns.  With cross set, only the
-// b^2 pairs between the two blocks are rotated: round rd joins column k of
-// the first block with column (k + rd) mod b of the second, b rounds.
-// Thread (a, g) computes the rotation of pair a from the current G and owns
-// the 2x2 groups {p_a, q_a} x {p_c, q_c} of G for its GPT pairs c (the groups
-// tile G) and RPT rows of W's column pair a.  Pair c's rotation comes from the
-// lane of the same wavefront whose pair is c (every wavefront holds every
-// pair index), so a round reads G from one LDS buffer, writes the rotated G
-// to the other, and needs a single barrier; no thread branches on its role.
+// rotation angle and threshold test is evaluated in FP64.  The partial Gram
+// blocks of the pair are reduced into G, the pairs are tested, and when any
+// needs it the rotation rounds of inner_rounds produce W, written out for the
+// update.
 template <typename T, int B2, int NT>
 __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict__ Gp,
                                                 T *__restrict__ Wm, int *skip, int *flag,
@@ -270,15 +436,8 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
                                                 int max_inner, int cross) {
     constexpr int LD = B2 + 1;
     constexpr int H = B2 / 2;
-    constexpr int M = B2 - 1;
-    constexpr int CG = NT / H;            // thread groups along c
-    constexpr int GPT = H / CG;           // 2x2 groups per thread
-    constexpr int RPT = B2 / CG;          // W rows per thread
     constexpr int TE = (B2 * B2) / NT;    // Gram entries per thread (set-up)
-    constexpr int NRS = sizeof(T) == 4 ? 1 : 2;
-    static_assert(CG * H == NT && GPT * CG == H && RPT * CG == B2 && TE * NT == B2 * B2,
-                  "tiling");
-    static_assert(64 % H == 0, "every wavefront holds every pair index");
+    static_assert(TE * NT == B2 * B2, "tiling");
     __shared__ T G[2][B2 * LD];
     __shared__ T W[B2 * LD];
     __shared__ int ired[NT / 64];
@@ -396,97 +555,7 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
     if (!need) return;
 
     // 3. cyclic rounds of disjoint rotations on G, accumulating W = prod J
-    const int a = tid % H, cg = tid / H;
-    const int c0 = cg * GPT, w0 = cg * RPT;
-    const bool own_diag = a / GPT == cg;      // this thread holds group (a, a)
-    const int kd = a % GPT;
-    // schedule positions of pair a and of the thread's pairs c at round 0
-    int ax = a, ay = cross ? H + a : (a == 0 ? M : M - a);
-    int cx[GPT], cy[GPT];
-#pragma unroll
-    for (int k = 0; k < GPT; ++k) {
-        const int c = c0 + k;
-        cx[k] = c;
-        cy[k] = cross ? H + c : (c == 0 ? M : M - c);
-    }
-    const int nround = cross ? H : M;
-    float smax = 0.f;   // largest |sin| of the rotations of pair a (owner only)
-    int cur = 0;
-    for (int sw = 0; sw < max_inner; ++sw) {
-        int rotated = 0;
-        for (int rd = 0; rd < nround; ++rd) {
-            const T *g = G[cur];
-            T *gn = G[cur ^ 1];
-            const int p = min(ax, ay), q = max(ax, ay);
-            const double alp = (double)g[p * LD + p], bep = (double)g[q * LD + q];
-            const double gap = (double)g[p * LD + q];
-            int r[GPT], s[GPT];
-            T blk[GPT][4];
-#pragma unroll
-            for (int k = 0; k < GPT; ++k) {
-                r[k] = min(cx[k], cy[k]);
-                s[k] = max(cx[k], cy[k]);
-                blk[k][0] = g[p * LD + r[k]]; blk[k][1] = g[p * LD + s[k]];
-                blk[k][2] = g[q * LD + r[k]]; blk[k][3] = g[q * LD + s[k]];
-            }
-            T wp[RPT], wq[RPT];
-#pragma unroll
-            for (int j = 0; j < RPT; ++j) {
-                wp[j] = W[(w0 + j) * LD + p];
-                wq[j] = W[(w0 + j) * LD + q];
-            }
-            double ca, sa, ta;
-            const bool ra = jac_rot_test<NRS>(alp, bep, gap, eps2, &ca, &sa, &ta);
-            if (own_diag && ra) {
-                rotated = 1;
-                smax = fmaxf(smax, (float)fabs(sa));
-            }
-            const T c1 = (T)ca, s1 = (T)sa;
-            // W <- W J on the column pair (p, q): x_p' = c x_p - s x_q, x_q' = s x_p + c x_q
-#pragma unroll
-            for (int j = 0; j < RPT; ++j) {
-                W[(w0 + j) * LD + p] = c1 * wp[j] - s1 * wq[j];
-                W[(w0 + j) * LD + q] = s1 * wp[j] + c1 * wq[j];
-            }
-            // G <- J^T G J on the groups: rows (p, q) by pair a, columns (r, s) by pair c
-#pragma unroll
-            for (int k = 0; k < GPT; ++k) {
-                const T c2 = (T)__shfl(ca, c0 + k, 64), s2 = (T)__shfl(sa, c0 + k, 64);
-                const T h00 = c1 * blk[k][0] - s1 * blk[k][2], h01 = c1 * blk[k][1] - s1 * blk[k][3];
-                const T h10 = s1 * blk[k][0] + c1 * blk[k][2], h11 = s1 * blk[k][1] + c1 * blk[k][3];
-                T o00 = c2 * h00 - s2 * h01, o01 = s2 * h00 + c2 * h01;
-                T o10 = c2 * h10 - s2 * h11, o11 = s2 * h10 + c2 * h11;
-                if (own_diag && k == kd && ra) {
-                    // the diagonal group: the rotation zeroes g_pq exactly
-                    o00 = (T)(alp - ta * gap);
-                    o11 = (T)(bep + ta * gap);
-                    o01 = T(0); o10 = T(0);
-                }
-                gn[p * LD + r[k]] = o00; gn[p * LD + s[k]] = o01;
-                gn[q * LD + r[k]] = o10; gn[q * LD + s[k]] = o11;
-            }
-            __syncthreads();
-            cur ^= 1;
-            if (cross) {
-                // next round: the second block's partner advances by one (mod b)
-                ay = ay + 1 == B2 ? H : ay + 1;
-#pragma unroll
-                for (int k = 0; k < GPT; ++k) cy[k] = cy[k] + 1 == B2 ? H : cy[k] + 1;
-            } else {
-                // next round: every schedule position advances by one (mod
-                // 2b-1), except the fixed partner 2b-1 of pair 0
-                ax = ax + 1 == M ? 0 : ax + 1;
-                if (a != 0) ay = ay + 1 == M ? 0 : ay + 1;
-#pragma unroll
-                for (int k = 0; k < GPT; ++k) {
-                    cx[k] = cx[k] + 1 == M ? 0 : cx[k] + 1;
-                    if (c0 + k != 0) cy[k] = cy[k] + 1 == M ? 0 : cy[k] + 1;
-                }
-            }
-        }
-        // positions after a full cycle are back where they started
-        if (!block_or<NT>(rotated, ired)) break;
-    }
+    float smax = inner_rounds<T, B2, NT>(G, W, ired, eps2, max_inner, cross);
 
     smax = wave_max(smax);
     if ((tid & 63) == 0) wsm[tid >> 6] = smax;
@@ -648,6 +717,247 @@ __global__ __launch_bounds__(JR_NT, 2) void jac_update_f64(int N, int nblk, int 
     }
 }
 
+// Fused round of the FP32 stage: the Gram block, the inner solve and the
+// update of every block pair in one launch.  The G workgroups of pair slot k
+// (blockIdx.x = k G + part) share the slot's rows: workgroup `part` holds rows
+// [part R, min(N, part R + R)) of the slot's 2b columns in registers from the
+// load to the store, so Y is read once and written once per round (the
+// separate kernels read it twice).  Each workgroup forms the partial Gram
+// block of its rows, publishes it with device-coherent stores and a flag
+// (raised to `tag`), waits (bounded) for the other workgroups of its slot,
+// and adds the G partials in a fixed order in FP64, so every workgroup of the
+// slot holds the same block and computes the same W.  Rows of a slot are
+// never touched by another slot within a round, and rounds are separate
+// launches, so nothing else is exchanged.
+//
+// Register layout of a 64-row stripe: lane (g, l) holds rows 4 l .. 4 l + 3
+// (one 16-byte vector) of the columns c(g, s) = 16 (s / 4) + 4 g + s % 4,
+// s = 0 .. B2/4 - 1, the layout in which the update's MFMA produces its
+// result (the update sums over the pair's columns in any order, so its k
+// index is mapped to these columns).  The Gram needs the rows on the k index
+// instead: each wave writes its stripe to LDS column by column and reads it
+// back in the layout of jac_gram_f32.
+//
+// A wait that runs out sets *err and the workgroup leaves without touching Y;
+// the stage is then invalid and the caller starts it again with the separate
+// kernels.
+template <int B2, int NT, int SPW>
+__global__ __launch_bounds__(NT) void jac_round_f32(int N, int nblk, int r, float *__restrict__ Y,
+                                                    int ldy, int G, int R, float *__restrict__ gpart,
+                                                    int *__restrict__ gflag, int tag, int *flag,
+                                                    float *offp, float *smxp, int *rot, double eps,
+                                                    int max_inner, int cross, int spin,
+                                                    int *__restrict__ err) {
+    constexpr int b = B2 / 2, KS = B2 / 4, NTI = B2 / 16, NW = NT / 64;
+    constexpr int NTT = B2 / 16, NUT = NTT * (NTT + 1) / 2;
+    constexpr int LD = B2 + 1;
+    constexpr int LDT = 64 + 4;            // a transposed stripe: column c at c LDT
+    constexpr int H = b;
+    static_assert(KS % 4 == 0 && NUT * 256 % 4 == 0, "layout");
+    struct Tr { float t[NW][B2 * LDT]; };             // per-wave transposed stripe
+    struct Red { float t[NW][NUT * 256]; };           // per-wave partial Gram tiles
+    struct In { float G[2][B2 * LD]; float W[B2 * LD]; };
+    __shared__ union { Tr tr; Red red; In in; } sm;
+    __shared__ int ired[NW];
+    __shared__ float wmx[NW], wsm[NW];
+    __shared__ int bad;
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int g4 = lane >> 4, li = lane & 15;
+    const int slot = blockIdx.x / G, part = blockIdx.x % G;
+    int I, J;
+    rr_slot(nblk, r, slot, &I, &J);
+    const int r0 = part * R, r1 = min(N, r0 + R);
+    const int nstripe = (r1 - r0) / 64;
+    if (tid == 0) bad = 0;
+    // columns s < KS/2 lie in block I, the others in block J
+    const float *srcI = Y + (size_t)(I * b + 4 * g4) * ldy + r0 + 4 * li;
+    const float *srcJ = Y + (size_t)(J * b - b + 4 * g4) * ldy + r0 + 4 * li;
+
+    // 1. load this wave's stripes
+    flt4 a[SPW][KS];
+#pragma unroll
+    for (int i = 0; i < SPW; ++i) {
+        const int st = w + i * NW;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int co = 16 * (s / 4) + (s % 4);
+            const float *src = (s < KS / 2 ? srcI : srcJ) + (size_t)co * ldy + 64 * st;
+            a[i][s] = st < nstripe ? *(const flt4 *)src : flt4{0, 0, 0, 0};
+        }
+    }
+
+    // 2. partial Gram block over this workgroup's rows (upper tiles)
+    flt4 acc[NUT];
+#pragma unroll
+    for (int q = 0; q < NUT; ++q) acc[q] = flt4{0, 0, 0, 0};
+    float *tr = sm.tr.t[w];
+#pragma unroll
+    for (int i = 0; i < SPW; ++i) {
+        const bool live = w + i * NW < nstripe;
+        if (live) {
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const int c = 16 * (s / 4) + 4 * g4 + (s % 4);
+                *(flt4 *)(tr + c * LDT + 4 * li) = a[i][s];
+            }
+        }
+        __syncthreads();
+        if (live) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                flt4 v[NTT];
+#pragma unroll
+                for (int h = 0; h < NTT; ++h) v[h] = *(const flt4 *)(tr + (16 * h + li) * LDT + 16 * u + 4 * g4);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    int q = 0;
+#pragma unroll
+                    for (int ta = 0; ta < NTT; ++ta)
+#pragma unroll
+                        for (int tc = ta; tc < NTT; ++tc, ++q) acc[q] = mfma16(v[ta][t], v[tc][t], acc[q]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // wave partials summed in wave order; the workgroup's partial published
+    {
+        float *red = sm.red.t[w];
+#pragma unroll
+        for (int q = 0; q < NUT; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) red[q * 256 + lane * 4 + e] = acc[q][e];
+    }
+    __syncthreads();
+    float *gout = gpart + ((size_t)slot * G + part) * NUT * 256;
+    for (int idx = tid; idx < NUT * 256; idx += NT) {
+        float sacc = sm.red.t[0][idx];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) sacc += sm.red.t[q][idx];
+        coh_store(gout + idx, sacc);
+    }
+    publish_fence();
+    __syncthreads();
+    if (tid == 0) coh_store(gflag + (size_t)slot * G + part, tag);
+
+    // 3. wait for the slot's other partials (bounded; spin < 0 gives up at once)
+    if (tid < G && tid != part) {
+        int it = 0;
+        while (spin < 0 || coh_load(gflag + (size_t)slot * G + tid) < tag) {
+            if (spin < 0 || ++it > spin) { bad = 1; break; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    if (bad) {
+        if (tid == 0) coh_store(err, 1);
+        return;
+    }
+
+    // 4. G = sum of the partials (FP64, partial order) in LDS, symmetric; W = I.
+    // Four entries per 16-byte coherent load, every partial's load in flight
+    // together.
+    const float *gin = gpart + (size_t)slot * G * NUT * 256;
+    for (int v = tid; v < NUT * 64; v += NT) {
+        flt4 x[JF_MAX_G];
+#pragma unroll
+        for (int q = 0; q < JF_MAX_G; ++q)
+            if (q < G) x[q] = coh_load4(gin, (q * NUT * 256 + 4 * v) * (int)sizeof(float));
+        double sacc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < JF_MAX_G; ++q)
+            if (q < G)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) sacc[e] += (double)x[q][e];
+        // tile q, lane l, element e: entry (4 (l / 16) + e, l % 16) of tile (ta, tc)
+        const int q = v >> 6, l = v & 63;
+        int ta = 0, qq = q;
+        while (qq >= NTT - ta) { qq -= NTT - ta; ++ta; }
+        const int tc = ta + qq;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = 16 * ta + 4 * (l >> 4) + e, j = 16 * tc + (l & 15);
+            sm.in.G[0][i * LD + j] = (float)sacc[e];
+            sm.in.G[0][j * LD + i] = (float)sacc[e];
+        }
+    }
+    for (int e = tid; e < B2 * B2; e += NT) sm.in.W[(e / B2) * LD + e % B2] = (e / B2 == e % B2) ? 1.f : 0.f;
+    __syncthreads();
+
+    // 5. test the pairs (Algorithm 1's rule, FP64), the largest relative
+    // off-diagonal; part 0 keeps the slot's bookkeeping
+    // (thread t tests column q = t mod B2 against the rows p = t / B2 + k NT / B2:
+    // g_qq is read once; the largest g_pq^2 / (g_pp g_qq) is kept and its root
+    // taken once)
+    const double eps2 = eps * eps;
+    static_assert(NT % B2 == 0, "test layout");
+    int need = 0;
+    double offsq = 0.0;
+    {
+        const int q = tid % B2;
+        const double gqq = (double)sm.in.G[0][q * LD + q];
+        for (int p = tid / B2; p < q; p += NT / B2) {
+            const double g = (double)sm.in.G[0][p * LD + q];
+            const double pq = (double)sm.in.G[0][p * LD + p] * gqq;
+            if (g * g > eps2 * pq && pq > 0.0 && (!cross || (p < H && q >= H))) need = 1;
+            if (pq > 0.0) offsq = fmax(offsq, g * g * __builtin_amdgcn_rcp(pq));
+        }
+    }
+    float offmax = (float)sqrt(offsq);
+    offmax = wave_max(offmax);
+    if (lane == 0) wmx[w] = offmax;
+    need = block_or<NT>(need, ired);
+    if (part == 0 && tid == 0) {
+        float m = 0.f;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) m = fmaxf(m, wmx[q]);
+        if (m > offp[slot]) offp[slot] = m;
+        rot[slot] = need ? 1 : 0;
+        if (need) *flag = 1;
+    }
+    if (!need) return;   // nothing rotates: Y keeps this slot's columns
+
+    // 6. rotations
+    float smax = inner_rounds<float, B2, NT>(sm.in.G, sm.in.W, ired, eps2, max_inner, cross);
+    smax = wave_max(smax);
+    if (lane == 0) wsm[w] = smax;
+    __syncthreads();
+    if (part == 0 && tid == 0) {
+        float m = 0.f;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) m = fmaxf(m, wsm[q]);
+        if (m > smxp[slot]) smxp[slot] = m;
+    }
+
+    // 7. update from registers: [Y_I Y_J]^T <- W^T [Y_I Y_J]^T per stripe; the
+    // output tile ti holds columns 16 ti + 4 g + e, rows 4 l + t
+    float *dstI = Y + (size_t)(I * b + 4 * g4) * ldy + r0 + 4 * li;
+    float *dstJ = Y + (size_t)(J * b - b + 4 * g4) * ldy + r0 + 4 * li;
+#pragma unroll
+    for (int ti = 0; ti < NTI; ++ti) {
+        float wr[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) wr[s] = sm.in.W[(16 * (s / 4) + 4 * g4 + (s % 4)) * LD + 16 * ti + li];
+#pragma unroll
+        for (int i = 0; i < SPW; ++i) {
+            const int st = w + i * NW;
+            if (st >= nstripe) continue;
+            flt4 o[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) o[t] = flt4{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) o[t] = mfma16(wr[s], a[i][s][t], o[t]);
+            float *dst = (ti < NTI / 2 ? dstI : dstJ) + (size_t)(16 * ti) * ldy + 64 * st;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                *(flt4 *)(dst + (size_t)e * ldy) = flt4{o[0][e], o[1][e], o[2][e], o[3][e]};
+        }
+    }
+}
+
 size_t jacobi_scratch_bytes(int N, int b, int elem) {
     const int B2 = 2 * b;
     const int npairs = N / B2;
@@ -658,6 +968,11 @@ size_t jacobi_scratch_bytes(int N, int b, int elem) {
     bytes += 256;                                             // flag
     bytes += 2 * ((size_t)npairs * sizeof(float) + 256);     // per-slot maxima
     bytes += (size_t)(N / b) * npairs * sizeof(int) + 256;   // rotated map per round
+    if (elem == 4) {                                          // fused FP32 rounds
+        bytes += 256;                                                            // alignment
+        bytes += (size_t)JF_MAX_WG * JF_MAX_TILES * 256 * sizeof(float) + 256;   // partial Grams
+        bytes += (size_t)JF_MAX_WG * sizeof(int) + 256;                          // their flags
+    }
     return bytes + 1024;
 }
 
@@ -672,14 +987,85 @@ void jacobi_carve(JacobiWork &jw, char *base, int N, int b, int elem) {
     jw.flag = (int *)p; p += 256;
     jw.offp = (float *)p; p += (size_t)npairs * sizeof(float) + 256;
     jw.smxp = (float *)p; p += (size_t)npairs * sizeof(float) + 256;
-    jw.rotmap = (int *)p;
+    jw.rotmap = (int *)p; p += (size_t)(N / b) * npairs * sizeof(int) + 256;
+    if (elem == 4) {
+        p = base + ((p - base + 255) & ~(size_t)255);   // 16-byte loads of the partials
+        jw.gpart = (float *)p; p += (size_t)JF_MAX_WG * JF_MAX_TILES * 256 * sizeof(float) + 256;
+        jw.gflag = (int *)p;
+    } else {
+        jw.gpart = nullptr;
+        jw.gflag = nullptr;
+    }
+}
+
+// ---------------------------------------------------------------- fused FP32 rounds
+typedef void (*RoundFn)(int, int, int, float *, int, int, int, float *, int *, int, int *, float *,
+                        float *, int *, double, int, int, int, int *);
+
+struct FusedCfg {
+    int G = 0, R = 0, nt = 0;   // workgroups per pair slot, rows per workgroup, threads
+    RoundFn fn = nullptr;
+};
+
+// Workgroups of `fn` the current device holds at once (compute units times
+// the kernel's occupancy per unit), cached per device and variant.
+static int round_capacity(int variant, RoundFn fn, int nt) {
+    static std::atomic<int> cap[64][3];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    int c = cap[dev][variant].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+    int ncu = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, nt, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    c = ncu * per_cu;
+    cap[dev][variant].store(c, std::memory_order_relaxed);
+    return c;
+}
+
+// The fused round needs every workgroup of a pair slot resident at once (they
+// wait for each other's partial Gram blocks): the whole grid must fit on the
+// device, one pair slot's rows split over G workgroups of at most 16 stripes.
+static bool fused_config(int N, int B2, FusedCfg *fc) {
+    if (B2 != 64 || N % 64 != 0) return false;
+    const int npairs = N / B2;
+    int ncu = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    int G = ncu / npairs;
+    G = G < 1 ? 1 : (G > JF_MAX_G ? JF_MAX_G : G);
+    const int R = cdiv(cdiv(N, G), 64) * 64;
+    G = cdiv(N, R);
+    const int stripes = R / 64;
+    int variant, nt;
+    RoundFn fn;
+    if (stripes <= 4) { variant = 0; nt = 256; fn = jac_round_f32<64, 256, 1>; }
+    else if (stripes <= 8) { variant = 1; nt = 256; fn = jac_round_f32<64, 256, 2>; }
+    else if (stripes <= 16) { variant = 2; nt = 512; fn = jac_round_f32<64, 512, 2>; }
+    else return false;
+    if (npairs * G > JF_MAX_WG || npairs * G > round_capacity(variant, fn, nt)) return false;
+    fc->G = G; fc->R = R; fc->nt = nt; fc->fn = fn;
+    return true;
 }
 
 // Sweeps over the ncols columns of Y (N rows, ld N; ncols a multiple of 2b,
 // at most N) and of V (N rows).
+//
+// fc (FP32 stage, 64-wide blocks, no V): each round is one launch of the
+// fused kernel instead of the Gram, inner and update launches.  Returns -2 if
+// a wait of the fused kernel ran out (Y is then invalid).
 template <typename T, int B2, int INNER_NT>
 static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, int maxsweep,
-                       int max_inner, JacobiWork &jw, int *conv) {
+                       int max_inner, JacobiWork &jw, int *conv, const FusedCfg *fc = nullptr) {
     constexpr int b = B2 / 2;
     const int nblk = ncols / b;
     const int npairs = nblk / 2;
@@ -695,7 +1081,13 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
     // written once, 2 N (2b)^2 flops per matrix
     const double pair_upd_bytes = 2.0 * N * B2 * sizeof(T) * (V ? 2 : 1);
     const double pair_upd_flops = 2.0 * N * B2 * B2 * (V ? 2 : 1);
+    std::vector<std::pair<size_t, int>> round_slots;   // clocked fused launches (slot, round)
+    if (fc) {
+        const hipError_t e = hipMemsetAsync(jw.gflag, 0, (size_t)npairs * fc->G * sizeof(int), s);
+        if (e != hipSuccess) { note_hip_error(e, "fused round flag reset"); return -1; }
+    }
     for (; sw < maxsweep; ++sw) {
+        round_slots.clear();
         hipError_t e = hipMemsetAsync(jw.flag, 0, 3 * sizeof(int), s);
         if (e == hipSuccess) e = hipMemsetAsync(jw.offp, 0, (size_t)npairs * sizeof(float), s);
         if (e == hipSuccess) e = hipMemsetAsync(jw.smxp, 0, (size_t)npairs * sizeof(float), s);
@@ -718,6 +1110,31 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
             // optional per-launch clock: events recorded by the dispatch itself
             hipEvent_t e0, e1;
             const int cross = (jw.cross_pairs && r > 0) ? 1 : 0;
+            if constexpr (sizeof(T) == 4 && B2 == 64) {
+                if (fc) {
+                    // algorithmic work: Y read once, the Gram blocks, the inner
+                    // solves; the rotated pairs' writes and updates are added
+                    // after the sweep
+                    const int tag = 1 + sw * (nblk - 1) + r;
+                    const int spin = jw.spin == 0 ? JF_SPIN : jw.spin;
+                    const dim3 grid(npairs * fc->G), blk(fc->nt);
+                    const bool clk = jw.kc && jw.kc->slot(SVD_K_ROUND32, gram_bytes,
+                                                          gram_flops + inner_flops, &e0, &e1);
+                    if (clk) {
+                        round_slots.push_back({jw.kc->used / 2 - 1, r});
+                        hipExtLaunchKernelGGL(fc->fn, grid, blk, 0, s, e0, e1, 0, N, nblk, r, (float *)Y,
+                                              N, fc->G, fc->R, jw.gpart, jw.gflag, tag, jw.flag, jw.offp,
+                                              jw.smxp, jw.rotmap + (size_t)r * npairs, eps, max_inner,
+                                              cross, spin, jw.flag + 1);
+                    } else {
+                        hipLaunchKernelGGL(fc->fn, grid, blk, 0, s, N, nblk, r, (float *)Y, N, fc->G,
+                                           fc->R, jw.gpart, jw.gflag, tag, jw.flag, jw.offp, jw.smxp,
+                                           jw.rotmap + (size_t)r * npairs, eps, max_inner, cross, spin,
+                                           jw.flag + 1);
+                    }
+                    continue;
+                }
+            }
             const bool gclk = jw.kc && jw.kc->slot(kbase + 0, gram_bytes, gram_flops, &e0, &e1);
             if constexpr (sizeof(T) == 4) {
                 if (gclk)
@@ -771,7 +1188,7 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
             e = hipMemcpyAsync(hoff.data(), jw.offp, (size_t)npairs * sizeof(float), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(hsmx.data(), jw.smxp, (size_t)npairs * sizeof(float), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess && !upd_slots.empty())
+        if (e == hipSuccess && (!upd_slots.empty() || !round_slots.empty()))
             e = hipMemcpyAsync(hrot.data(), jw.rotmap, (size_t)(nblk - 1) * npairs * sizeof(int),
                                hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -783,6 +1200,17 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
             for (int q = 0; q < npairs; ++q) k += hrot[(size_t)us.second * npairs + q];
             jw.kc->bytes[us.first] = k * pair_upd_bytes;
             jw.kc->flops[us.first] = k * pair_upd_flops;
+        }
+        // a fused round writes the columns of the pairs it rotated, once
+        for (auto &us : round_slots) {
+            double k = 0.0;
+            for (int q = 0; q < npairs; ++q) k += hrot[(size_t)us.second * npairs + q];
+            jw.kc->bytes[us.first] += k * 0.5 * pair_upd_bytes;
+            jw.kc->flops[us.first] += k * pair_upd_flops;
+        }
+        if (jw.hflag[1]) {
+            note_error_text("fused Jacobi round: a bounded wait ran out");
+            return -2;
         }
         if (jw.kc) jw.kc->collect();
         float off = 0.f, smx = 0.f;
@@ -815,6 +1243,11 @@ int jacobi_sweeps_cols(hipStream_t s, int N, int ncols, int b, T *Y, T *V, doubl
     if (N % 64 != 0) {
         note_hip_error(hipErrorInvalidValue, "jacobi_sweeps_cols: row count not a multiple of 64");
         return -1;
+    }
+    if constexpr (sizeof(T) == 4) {
+        FusedCfg fc;
+        if (jw.fused && !V && b == 32 && ncols == N && fused_config(N, 64, &fc))
+            return sweeps_impl<T, 64, 256>(s, N, ncols, Y, V, eps, maxsweep, max_inner, jw, conv, &fc);
     }
     if (b == 16) return sweeps_impl<T, 32, 256>(s, N, ncols, Y, V, eps, maxsweep, max_inner, jw, conv);
     // 64-wide FP64 blocks: 512 threads shorten each round's per-thread work

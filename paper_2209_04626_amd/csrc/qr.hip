@@ -217,7 +217,7 @@ __device__ __forceinline__ void coop_column(double (&a)[QR_NB], CoopShared &sh, 
     }
     // 2. publish (stores complete, then the flag), then wait for every
     // workgroup's column J
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    publish_fence();
     __syncthreads();
     if (t == 0) coh_store(flags + g, base + J + 1);
     // (a workgroup's own flag needs no wait; spin < 0 gives up on every
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
         for (int e = 0; e < 4; ++e)
             coh_store(pg + (16 * ti + mfma_row<double>(lane, e)) + (size_t)(16 * tj + lane % 16) * QR_NB, acc[e]);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    publish_fence();
     __syncthreads();
     if (t == 0) coh_store(flags + g, base + QR_NB + 1);
     // a wait that ran out leaves this panel's factors invalid: report it in

@@ -396,7 +396,7 @@ __global__ __launch_bounds__(QP_NT) void qrcp_persist(int n, const double *__res
             for (int i = k + t; i < n; i += QP_NT) coh_store(cb + i, pc[pidx(i)]);
         }
         // every wavefront's stores are complete before the key goes out
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        publish_fence();
         __syncthreads();
         if (t == 0) coh_store(keys + (size_t)buf * nwg + b, bk);
         // 2. every workgroup's key of step k; the largest is the pivot
