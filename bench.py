@@ -45,14 +45,17 @@ FP64_PEAK_TF = 78.6            # dense FP64 (vector and MFMA)
 FP32_PEAK_TF = 157.3           # dense FP32 (vector and MFMA)
 
 
-def algorithmic_flops(n: int, info: dict, mixed: bool) -> float:
-    """Algorithmic flop count of one SVD (square n, U and V formed), from the
-    stage formulas: pivot pass 4n^3/3, QR of A1 P 4n^3/3, LQ 4n^3/3, branch
+def algorithmic_flops(n: int, info: dict, mixed: bool, m: int | None = None) -> float:
+    """Algorithmic flop count of one SVD (m x n, U and V formed), from the
+    stage formulas: tall QR 2mn^2 - 2n^3/3 and its back-transform 4mn^2 - 2n^3
+    (m > n only), pivot pass 4n^3/3, QR of A1 P 4n^3/3, LQ 4n^3/3, branch
     SYRK n^3, FP32 sweeps 4n^2(n-1) each, switch 4.7 n^3, FP64 sweeps with V
     7n^2(n-1) each (without V 4n^2(n-1) each, then the triangular solve for
     V_X n^3; its fallback adds X^T U_X 2n^3, a QR 4n^3/3, X Q 2n^3 and sweeps
     with V), back-transforms 4n^3."""
     f = 4 * n ** 3 / 3 * 3 + 4 * n ** 3
+    if m is not None and m > n:
+        f += 2 * m * n ** 2 - 2 * n ** 3 / 3 + 4 * m * n ** 2 - 2 * n ** 3
     if mixed:
         f += n ** 3
         if info["branch_taken"] == 1:
@@ -116,7 +119,13 @@ CLASS_ROOF = {
     "jac_gram<f64>": ("hbm", None), "jac_update<f64>": ("hbm", None),
     "jac_inner<f32>": ("latency", FP64_PEAK_TF), "jac_inner<f64>": ("latency", FP64_PEAK_TF),
     "qrcp": ("hbm", None), "qr_panel": ("latency", FP64_PEAK_TF), "gemm": ("mfma", FP64_PEAK_TF),
+    # the fused FP32 round: its Gram and update products on the FP32 matrix
+    # cores, its inner solve a chain of dependent LDS rounds
+    "jac_round<f32>": ("mfma", FP32_PEAK_TF),
+    "trsm_diag": ("latency", FP64_PEAK_TF),
 }
+GEMM_CLASS = 8                 # many shapes in one class: listed, never the dominant kernel
+SURVEY_CLASSES = range(0, 11)
 
 
 def class_survey(mp, A, ws, mode: str, classes) -> dict:
@@ -148,10 +157,11 @@ def kernel_table(survey: dict, mp) -> list:
         tfs = flops / sec / 1e12 if sec > 0 else 0.0
         bound, fpk = CLASS_ROOF.get(name, ("hbm", None))
         frac = gbs / HBM_PEAK_GBS if bound == "hbm" else tfs / (fpk or FP64_PEAK_TF)
+        peak = HBM_PEAK_GBS if bound == "hbm" else (fpk or FP64_PEAK_TF)
         rows.append({"kernel": name, "class": c, "launches": calls, "ms": round(ms, 3),
                      "avg_us": round(ms * 1e3 / calls, 2), "bytes_per_launch": round(byts / calls),
                      "flops_per_launch": round(flops / calls), "GB_s": round(gbs, 1),
-                     "TFLOP_s": round(tfs, 3), "bound": bound, "frac": round(frac, 4)})
+                     "TFLOP_s": round(tfs, 3), "bound": bound, "peak": peak, "frac": round(frac, 4)})
     rows.sort(key=lambda r: -r["ms"])
     return rows
 
@@ -177,6 +187,43 @@ def gates_gpu(A, U, S, V, s_ref, kappa_s):
     return r
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_full(n_full: int, n_one: int) -> dict:
+    """The oracle measured without extrapolation: one full SVD of the n_full
+    workload on all host cores (round-robin ordering, OpenMP over the pairs of
+    a round), and one SVD of the n_one instance on one thread (row-cyclic
+    ordering).  Minutes of CPU time: run separately (--cpu-full), not in the
+    default bench line."""
+    import oracle
+    import testmats
+    out = {"cpu_model": cpu_model(), "host_threads": os.cpu_count()}
+    oracle.set_verbose(True)
+    oracle.set_threads(os.cpu_count() or 1)
+    A, _ = testmats.config_c3b(n=n_full)
+    t0 = time.perf_counter()
+    _, _, _, info = oracle.svd(A, order="rr")
+    out["all_cores"] = {"n": n_full, "threads": oracle.max_threads(), "order": "round-robin",
+                        "s": round(time.perf_counter() - t0, 2), "sweeps": info["sweeps"]}
+    print(f"[bench] oracle n={n_full} all cores {out['all_cores']['s']} s", file=sys.stderr, flush=True)
+    oracle.set_threads(1)
+    A, _ = testmats.config_c3b(n=n_one)
+    t0 = time.perf_counter()
+    _, _, _, info = oracle.svd(A, order="cyclic")
+    out["one_thread"] = {"n": n_one, "threads": 1, "order": "cyclic",
+                         "s": round(time.perf_counter() - t0, 2), "sweeps": info["sweeps"]}
+    return out
+
+
 def cpu_baseline(n_full: int, n_sample: int) -> dict:
     """The FP64 oracle timed on this host's cores on a bounded sample: the
     full oracle SVD (QRCP + LQ preconditioning, round-robin Jacobi on all
@@ -196,8 +243,122 @@ def cpu_baseline(n_full: int, n_sample: int) -> dict:
         "sample": (f"full oracle SVD of the {n_sample}x{n_sample} instance of the same "
                    f"construction ({dt:.2f} s, {info['sweeps']} sweeps), scaled by "
                    f"({n_full}/{n_sample})^3 = {scale:.0f} to one {n_full}x{n_full} SVD"),
-        "est_ms_per_svd": est * 1e3,
+        "est_ms_per_svd": est * 1e3, "cpu_model": cpu_model(),
+        "measured_full": recorded_cpu_full(),
     }
+
+
+def recorded_cpu_full():
+    """The oracle's full-size run on the same kind of host, measured once with
+    --cpu-full and recorded in profiles/oracle_cpu_n4096.md (None if absent)."""
+    path = os.path.join(ROOT, "profiles", "oracle_cpu_n4096.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            m = re.match(r"^- (\w+): `?([^`\s]+)`?", line.strip())
+            if m:
+                rec[m.group(1)] = m.group(2)
+    try:
+        return {"n4096_all_cores_s": float(rec["all_cores_s"]), "n1024_one_thread_s": float(rec["one_thread_s"]),
+                "source": "profiles/oracle_cpu_n4096.md"}
+    except (KeyError, ValueError):
+        return None
+
+
+def secondary(mp, ws, steps: int) -> dict:
+    """The other workloads, timed the same way (inputs resident in HBM,
+    synchronised around the timed calls): the 1024^2 graded matrix and the
+    8192 x 2048 tall matrix (mixed and plain, gates against the stored oracle
+    sigma), the ragged batch of 2000 (graph replays of the persistent
+    kernel), and the adjoint of 256 128 x 64 SVDs."""
+    import numpy as np
+    import torch
+    import testmats
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    from make_oracle_sigma import load
+    out = {}
+    gens = {"C2": testmats.config_c2, "C3a": testmats.config_c3a}
+    for name, gen in gens.items():
+        A_np, _ = gen()
+        A = torch.from_numpy(np.ascontiguousarray(A_np)).cuda()
+        m, n = A_np.shape
+        s_ref, kappa, _, _ = load(name)
+        row = {"m": m, "n": n}
+        for mode in ("mixed", "plain"):
+            mp.svd(A, mode, workspace=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                U, S, V, info = mp.svd(A, mode, workspace=ws)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / steps
+            g = gates_gpu(A, U, S, V, s_ref, kappa)
+            row[mode] = {"ms": round(t * 1e3, 2), "svd_per_s": round(1.0 / t, 3),
+                         "gflops": round(algorithmic_flops(n, info, mode == "mixed", m) / t / 1e9, 1),
+                         "sweeps_low": info["sweeps_low"], "sweeps_work": info["sweeps_work"],
+                         "branch_taken": info["branch_taken"], "gates_pass": g["pass"],
+                         "e_sigma": g.get("e_sigma")}
+        row["ratio"] = round(row["plain"]["ms"] / row["mixed"]["ms"], 4)
+        out[name] = row
+        print(f"[bench] {name}: mixed {row['mixed']['ms']} ms, plain {row['plain']['ms']} ms",
+              file=sys.stderr, flush=True)
+        del A
+    # the ragged batch: one persistent launch per graph replay
+    shapes, mats, _ = testmats.config_c4()
+    plan = mp.batched_plan(shapes)
+    Ab = mp.pack_batch(mats, "cuda")
+    res = mp.svd_batched(plan, Ab)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = mp.svd_batched(plan, Ab, out=res)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    info = res[3].cpu().numpy()
+    flops = 0.0
+    for (m, n), inf in zip(shapes, info):
+        sw_low, sw_work = int(inf[2]), int(inf[3])
+        f = 4 * n ** 3 / 3 * 3 + n ** 3 + 4.7 * n ** 3 + 4 * n ** 3
+        f += sw_low * 4 * n * n * (n - 1) + sw_work * 7 * n * n * (n - 1)
+        if m > n:
+            f += 2 * m * n * n - 2 * n ** 3 / 3 + 4 * m * n * n - 2 * n ** 3
+        flops += f
+    ach = flops / t / 1e12
+    out["C4"] = {"batch": len(shapes), "ms": round(t * 1e3, 2), "svd_per_s": round(len(shapes) / t, 1),
+                 "gflops": round(flops / t / 1e9, 1), "all_ok": bool(np.all(info[:, 0] == 0)),
+                 "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": FP64_PEAK_TF,
+                              "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TF, 4)}}
+    print(f"[bench] C4: {out['C4']['ms']} ms per batch", file=sys.stderr, flush=True)
+    # the adjoint of the gradient workload: forward by the batched path,
+    # then svd_backward timed alone
+    d = testmats.config_c5(batch=256, ndir=1)
+    plan = mp.batched_plan([M.shape for M in d["A"]])
+    S, U, V, _ = mp.svd_batched(plan, mp.pack_batch(d["A"], "cuda"))
+    outs = mp.unpack_batch(plan, S, U, V)
+    Ut = torch.stack([o[0] for o in outs]).contiguous()
+    St = torch.stack([o[1] for o in outs]).contiguous()
+    Vt = torch.stack([o[2] for o in outs]).contiguous()
+    gU, gS, gV = (torch.from_numpy(d[k]).cuda() for k in ("gU", "gS", "gV"))
+    mp.svd_backward(Ut, St, Vt, gU, gS, gV)
+    torch.cuda.synchronize()
+    reps = max(steps, 10)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mp.svd_backward(Ut, St, Vt, gU, gS, gV)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    B, m, n = Ut.shape
+    flops = B * (6.0 * m * n * n + 2.0 * n ** 3)          # J, Z = U M, gA = Z V^T; K
+    byts = B * (3.0 * m * n + 2.0 * n * n + 2.0 * n) * 8   # U, gU, gA; V, gV; S, gS
+    out["C5"] = {"batch": B, "m": m, "n": n, "backward_us": round(t * 1e6, 1),
+                 "gflops": round(flops / t / 1e9, 1), "GB_s": round(byts / t / 1e9, 1),
+                 "roofline": {"bound": "mfma", "achieved": round(flops / t / 1e12, 3),
+                              "peak": FP64_PEAK_TF, "unit": "TFLOP/s",
+                              "frac": round(flops / t / 1e12 / FP64_PEAK_TF, 4)}}
+    print(f"[bench] C5: backward {out['C5']['backward_us']} us per batch", file=sys.stderr, flush=True)
+    return out
 
 
 def main() -> int:
@@ -211,7 +372,15 @@ def main() -> int:
     ap.add_argument("--no-survey", action="store_true",
                     help="skip the per-class clocked SVDs (no kernels table, no roofline)")
     ap.add_argument("--cpu-sample-n", type=int, default=1024)
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the other workloads (1024^2 graded, 8192 x 2048, batch, adjoint)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only measure the oracle on the host: a full SVD at --n on all cores and "
+                         "the 1024^2 instance on one thread (minutes); prints one JSON line")
     args = ap.parse_args()
+    if args.cpu_full:
+        print(json.dumps({"cpu_full": cpu_full(args.n, 1024)}), flush=True)
+        return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr, flush=True)
@@ -248,24 +417,26 @@ def main() -> int:
     # only; the GEMM class (many shapes) is listed but never picked
     survey = {}
     if do_mixed and not args.no_survey:
-        survey["mixed"] = class_survey(mp, A, ws, "mixed", range(0, 8))
+        survey["mixed"] = class_survey(mp, A, ws, "mixed", SURVEY_CLASSES)
     if do_plain and not args.no_survey:
-        survey["plain"] = class_survey(mp, A, ws, "plain", range(0, 9))
+        survey["plain"] = class_survey(mp, A, ws, "plain", SURVEY_CLASSES)
     kernels = {k: kernel_table(v, mp) for k, v in survey.items()}
     # the dominant kernel: the class with the largest total time in the mixed
     # step (the Jacobi kernels are clocked by events that their dispatch
     # records, so clocking them in the timed region costs no extra packets)
     dom_class = None
     if do_mixed and "mixed" in survey:
-        dom_class = max(survey["mixed"].items(), key=lambda kv: kv[1][0])[0]
+        cand = {c: v for c, v in survey["mixed"].items() if c != GEMM_CLASS}
+        dom_class = max(cand.items(), key=lambda kv: kv[1][0])[0]
     print(f"[bench] class survey done; dominant class {dom_class}", file=sys.stderr, flush=True)
 
     # timed: K mixed SVDs (the step) with the dominant kernel clocked by HIP
     # events on the library's stream (the pivot pass as one interval per
     # pass); K plain SVDs without events
     opts_mixed.kernel_timing = 1 if dom_class == 6 else (100 + dom_class if dom_class is not None else 0)
-    # a Jacobi class is clocked on every CLOCK_EVERY-th launch (a uniform
-    # sample over rounds and sweeps) so that its events barely touch the step
+    # a Jacobi class (or the fused FP32 round) is clocked on every
+    # CLOCK_EVERY-th launch (a uniform sample over rounds and sweeps) so that
+    # its events barely touch the step
     opts_mixed.kernel_timing_every = CLOCK_EVERY
     opts_plain.kernel_timing = 0
     infos, infos_p = [], []
@@ -333,12 +504,12 @@ def main() -> int:
         name = mp.KERNEL_CLASSES[c]
         avg_s = ms / 1e3 / max(calls, 1)
         bytes_per_launch = byts / max(calls, 1)
-        bound, _ = CLASS_ROOF.get(name, ("hbm", None))
+        bound, fpk = CLASS_ROOF.get(name, ("hbm", None))
         traffic = recorded_traffic(n, name)
         if bound == "mfma":
             ach = flops / (ms / 1e3) / 1e12
-            roofline = {"bound": "mfma", "achieved": round(ach, 2), "peak": FP64_PEAK_TF,
-                        "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TF, 4)}
+            roofline = {"bound": "mfma", "achieved": round(ach, 2), "peak": fpk,
+                        "unit": "TFLOP/s", "frac": round(ach / fpk, 4)}
         elif bound == "latency":
             # a chain of dependent LDS rounds: priced against the FP64 vector
             # ALU peak (256 CUs x 128 FP64 flop/clk x 2.4 GHz)
@@ -353,7 +524,7 @@ def main() -> int:
             "traffic": None if traffic is None else round(traffic),
             "kernel": name, "avg_us": round(avg_s * 1e6, 2), "launches": calls,
             "bytes_per_launch": round(bytes_per_launch),
-            "measured": "timed region" + (f", every {CLOCK_EVERY}th launch" if c < 6 else ""),
+            "measured": "timed region" + (f", every {CLOCK_EVERY}th launch" if c < 6 or c == 9 else ""),
         })
 
     line = {
@@ -398,6 +569,8 @@ def main() -> int:
         }
     line["roofline"] = roofline
     line["kernels"] = kernels
+    if do_mixed and do_plain and not args.no_secondary:
+        line["secondary"] = secondary(mp, ws, args.steps)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_sample_n)

@@ -166,7 +166,7 @@ typedef struct {
     int fused_rounds;      /* FP32 stage without V_low (switch method 1):
                               0 (default) = one launch per block-Jacobi round
                               (Gram, inner solve and update fused, 32-column
-                              blocks) for n >= 2048 when the device holds the
+                              blocks) for n > 2048 when the device holds the
                               whole grid at once, else separate kernels;
                               1 = the fused round at any n where it fits;
                               -1 = always the separate kernels */
@@ -185,6 +185,7 @@ typedef struct {
 #define SVD_K_GEMM 8       /* matrix-core GEMMs (with their split-K sums) */
 #define SVD_K_ROUND32 9    /* fused FP32 Jacobi round (Gram, inner solve
                               and update in one launch)               */
+#define SVD_K_TRSM 10      /* diagonal-block solves of V_X = X^-1 Y     */
 #define SVD_K_NCLASS 12
 
 typedef struct {

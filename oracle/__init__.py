@@ -64,6 +64,11 @@ def set_threads(t: int) -> None:
     _lib().oracle_set_threads(int(t))
 
 
+def set_verbose(v: bool) -> None:
+    """Progress lines on stderr during long oracle runs (phase ends, sweeps)."""
+    _lib().oracle_set_verbose(int(bool(v)))
+
+
 def max_threads() -> int:
     return int(_lib().oracle_max_threads())
 

@@ -20,6 +20,7 @@
  * of squares: entries must stay within about 1e-150 .. 1e150 in magnitude.
  */
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -38,6 +39,15 @@ void oracle_set_threads(int t)
     (void)t;
 #endif
 }
+
+/* Progress lines on stderr (phase ends, sweeps) for long timed runs; no
+   effect on what is computed. */
+static int g_verbose = 0;
+void oracle_set_verbose(int v) { g_verbose = v; }
+#define ORC_PROGRESS(...)                                                     \
+    do {                                                                      \
+        if (g_verbose) { fprintf(stderr, "[oracle] " __VA_ARGS__); fflush(stderr); } \
+    } while (0)
 
 int oracle_max_threads(void)
 {
@@ -269,6 +279,7 @@ int oracle_gesvj(int m, int n, double *X, int ldx, int nv, double *V, int ldv,
         }
         ++it;
         converged = !rotated;
+        ORC_PROGRESS("sweep %d done\n", it);
     }
     if (sweeps) *sweeps = it;
     return converged ? ORC_OK : ORC_NOCONV;
@@ -394,13 +405,16 @@ int oracle_svd(int m, int n, const double *A, int lda, double *S,
     /* 2. QRCP */
     int *jpvt = (int *)malloc((size_t)n * sizeof(int));
     double *tau1 = (double *)malloc((size_t)n * sizeof(double));
+    ORC_PROGRESS("tall reduction done\n");
     oracle_geqp3(n, n, A1, n, jpvt, tau1);
+    ORC_PROGRESS("QRCP done\n");
     /* 3. LQ of R via QR of R^T */
     double *Rt = (double *)calloc((size_t)n * n, sizeof(double));
     for (int j = 0; j < n; ++j)
         for (int i = 0; i <= j; ++i) Rt[IX(j, i, n)] = A1[IX(i, j, n)];
     double *tau2 = (double *)malloc((size_t)n * sizeof(double));
     oracle_geqr2(n, n, Rt, n, tau2);
+    ORC_PROGRESS("LQ done\n");
     double *X = (double *)calloc((size_t)n * n, sizeof(double));
     for (int j = 0; j < n; ++j)
         for (int i = j; i < n; ++i) X[IX(i, j, n)] = Rt[IX(j, i, n)];
@@ -414,6 +428,7 @@ int oracle_svd(int m, int n, const double *A, int lda, double *S,
     if (status == ORC_OK && z) status = ORC_RANKDEF;
     /* 6. U = Q0 Q1 U_X */
     oracle_apply_q(0, n, n, A1, n, tau1, n, X, n);
+    ORC_PROGRESS("U back-transform done\n");
     for (int j = 0; j < n; ++j) {
         for (int i = 0; i < n; ++i) U[IX(i, j, ldu)] = X[IX(i, j, n)];
         for (int i = n; i < m; ++i) U[IX(i, j, ldu)] = 0.0;

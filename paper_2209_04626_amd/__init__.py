@@ -36,7 +36,7 @@ SVD_ERR_HIP, SVD_ERR_SCRATCH_LIMIT = -100, -101
 BACKWARD_NOALLOC_SCRATCH_BYTES = 64 << 20
 KERNEL_CLASSES = ["jac_gram<f32>", "jac_inner<f32>", "jac_update<f32>", "jac_gram<f64>",
                   "jac_inner<f64>", "jac_update<f64>", "qrcp", "qr_panel", "gemm", "jac_round<f32>",
-                  "-", "-"]
+                  "trsm_diag", "-"]
 NCLASS = 12
 BRANCH_AUTO, BRANCH_LOW, BRANCH_SKIP = 0, 1, 2
 

@@ -73,7 +73,10 @@ struct Layout {
 // the separate kernels where the grid does not fit the device).
 bool fused_low(int n, const svd_opts &o) {
     if (o.fused_rounds < 0 || o.switch_method != 1) return false;
-    return o.fused_rounds > 0 || n >= 2048;
+    // measured: at n = 2048 the separate 16-column kernels are faster (the
+    // fused round's inner solve dominates a round there), at n = 4096 the
+    // fused round is
+    return o.fused_rounds > 0 || n > 2048;
 }
 
 // Jacobi block width per stage: the FP32 stage is bound by the latency of

@@ -7,6 +7,7 @@
 // QRCP + LQ preconditioning keeps small.  The caller checks the result's
 // orthogonality and falls back to the QR of X^T U_X followed by sweeps with
 // accumulation when it is not good enough.
+#include "../../include/mpjsvd.h"
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -55,8 +56,14 @@ void trsm_lower(hipStream_t s, int n, int nrhs, const double *L, int ldl, double
     if (n <= 0 || nrhs <= 0) return;
     for (int r0 = 0; r0 < n; r0 += TRSM_NB) {
         const int kb = n - r0 < TRSM_NB ? n - r0 : TRSM_NB;
+        // algorithmic work: the kb x kb block read, kb rows of B read and
+        // written, kb^2 flops per right-hand side
+        if (kc)
+            kc->begin(s, SVD_K_TRSM, ((double)kb * kb + 2.0 * kb * nrhs) * sizeof(double),
+                      (double)kb * kb * nrhs);
         hipLaunchKernelGGL((k_trsm_diag<TRSM_NB>), dim3(cdiv(nrhs, 64)), dim3(64), 0, s, kb, nrhs,
                            L + (size_t)r0 * ldl + r0, ldl, B + r0, ldb);
+        if (kc) kc->end(s);
         const int r1 = r0 + kb;
         if (r1 < n)
             gemm<double>(s, false, false, n - r1, nrhs, kb, -1.0, L + (size_t)r0 * ldl + r1, ldl,
