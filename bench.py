@@ -78,6 +78,8 @@ TRAFFIC = {
                         ["paper_2209_04626_amd/csrc/jacobi.hip", "paper_2209_04626_amd/csrc/common.hpp"]),
     "qr_panel": ("qr_panel_coop_n4096_traffic.md",
                  ["paper_2209_04626_amd/csrc/qr.hip", "paper_2209_04626_amd/csrc/common.hpp"]),
+    "jac_round<f32>": ("jac_round_f32_n4096_traffic.md",
+                       ["paper_2209_04626_amd/csrc/jacobi.hip", "paper_2209_04626_amd/csrc/common.hpp"]),
 }
 
 
