@@ -23,10 +23,11 @@
  *     is the caller's `work` buffer, sized by the matching *_workspace_size
  *     query.  A is never modified.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
- *     Work is enqueued on that stream.  svd_plain / svd_mixed read convergence
- *     and branch flags back to the host between sweeps, so they return only
- *     when the result is complete; svd_batched and svd_backward are fully
- *     asynchronous (stream-ordered).
+ *     Work is enqueued on that stream.  By default svd_plain / svd_mixed read
+ *     convergence and branch flags back to the host between sweeps, so they
+ *     return only when the result is complete; with svd_opts.capture = 1
+ *     they are stream-ordered and graph-capturable like svd_batched and
+ *     svd_backward (every decision on the device, svd_info written there).
  *   - The return value checks arguments only, LAPACK style: 0 on success,
  *     -k when argument k is invalid (k counts from 1), -100 on a HIP runtime
  *     error.  The numerical outcome is in svd_info.status.
@@ -60,6 +61,11 @@ extern "C" {
                                     and does not report this)              */
 #define SVD_ERR_BREAKDOWN 6      /* a singular value came out NaN or Inf
                                     from finite input; outputs undefined    */
+#define SVD_WARN_VSOLVE 7        /* svd_opts.capture = 1, v_method 1: the
+                                    solved V_X = X^{-1} Y failed its
+                                    orthogonality test and the fallback
+                                    (which the host drives) did not run; S
+                                    and U are valid, V is not accurate      */
 
 /* svd_opts.branch / svd_info.branch_taken (Algorithm 4's special cases) */
 #define SVD_BRANCH_AUTO 0
@@ -170,6 +176,31 @@ typedef struct {
                               whole grid at once, else separate kernels;
                               1 = the fused round at any n where it fits;
                               -1 = always the separate kernels */
+    int capture;           /* 1: stream-ordered, with no host
+                              synchronisation inside the call, so it can be
+                              captured in a HIP graph and replayed.  The
+                              branch tests of Section 3.5, the stopping rules
+                              of every sweep stage and v_method 1's
+                              acceptance test are decided on the device;
+                              info must then be DEVICE memory (or NULL) and
+                              is written by the call's last kernel.  Every
+                              sweep up to maxsweep_low / maxsweep_work is
+                              enqueued and those after the stop exit at
+                              once, so the caps set the launch count.  The
+                              FP32 stage and the switch are enqueued even
+                              when the tests choose the skip branch (their
+                              result is then replaced by Y = X); all three
+                              tests are measured.  Not available here:
+                              kernel_timing (must be 0), stage_ms (0), the
+                              Y2 safeguard (not run), v_method 1's fallback
+                              (SVD_WARN_VSOLVE instead), restarting the FP32
+                              stage after a fused round's wait ran out (the
+                              stage stops there: fused_fallback = 2, still a
+                              valid preconditioner by Proposition 1) and the
+                              step-by-step pivot pass after the one-launch
+                              pass's wait ran out (SVD_ERR_WAIT_TIMEOUT);
+                              switch_method 3 needs branch = SVD_BRANCH_LOW.
+                              0 (default): the host-synchronised call. */
 } svd_opts;
 
 /* Kernel classes reported by svd_info.kern_* (kernel_timing 1: SVD_K_QRCP
@@ -207,7 +238,8 @@ typedef struct {
     double kern_flops[SVD_K_NCLASS]; /* algorithmic flops of those launches */
     int v_method_taken;    /* -1: V not wanted; 0: accumulated; 1: triangular
                               solve accepted; 2: solve rejected, V_X from the
-                              QR of X^T U_X and further sweeps */
+                              QR of X^T U_X and further sweeps; 3 (capture =
+                              1): solve rejected, no fallback */
     int sweeps_vfix;       /* FP64 sweeps of that fallback */
     double orth_vx;        /* max|V_X^T V_X - I| of the solve, -1 if none */
     double orth_y;         /* diagnostics: max|D^-1 Y^T Y D^-1 - I| of Y
@@ -216,7 +248,8 @@ typedef struct {
     int n_y2;              /* columns in Y2 (0: the safeguard did not act) */
     int sweeps_y2;         /* FP64 sweeps run on Y2 alone */
     int fused_fallback;    /* 1: a fused FP32 round gave up waiting and the
-                              FP32 stage was run again with separate kernels */
+                              FP32 stage was run again with separate kernels;
+                              2 (capture = 1): the FP32 stage stopped there */
 } svd_info;
 
 /* Load the tuning table measured by the autotuner (not part of the paper's
@@ -257,7 +290,8 @@ size_t svd_workspace_size(int m, int n, const svd_opts *o);
  *   8 V, 9 ldv      output n x n (ignored when want_v = 0; may be NULL then)
  *   10 work, 11 work_bytes  device scratch, >= svd_workspace_size(m, n, o)
  *   12 o            options (NULL = svd_default_opts(.., 0))
- *   13 info         HOST pointer, filled before return (may be NULL)
+ *   13 info         HOST pointer, filled before return (may be NULL); with
+ *                   o->capture = 1 a DEVICE pointer written on the stream
  *   14 stream       hipStream_t
  */
 int svd_plain(int m, int n, const double *A, int lda, double *S,

@@ -30,7 +30,7 @@ EXPORTS = [
 
 SVD_OK, SVD_WARN_NOCONV, SVD_ERR_NONFINITE, SVD_WARN_RANK_DEFICIENT = 0, 1, 2, 3
 EIG_ERR_CLUSTER = 4
-SVD_ERR_WAIT_TIMEOUT, SVD_ERR_BREAKDOWN = 5, 6
+SVD_ERR_WAIT_TIMEOUT, SVD_ERR_BREAKDOWN, SVD_WARN_VSOLVE = 5, 6, 7
 SVD_ERR_HIP, SVD_ERR_SCRATCH_LIMIT = -100, -101
 # bytes of the fixed scratch array behind svd_backward_noalloc
 BACKWARD_NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -57,7 +57,7 @@ class SvdOpts(ctypes.Structure):
         ("inner_pairs", ctypes.c_int), ("tol_cluster", ctypes.c_double),
         ("y2_safeguard", ctypes.c_int), ("tol_y2", ctypes.c_double),
         ("kernel_timing_every", ctypes.c_int), ("wait_polls", ctypes.c_int),
-        ("fused_rounds", ctypes.c_int),
+        ("fused_rounds", ctypes.c_int), ("capture", ctypes.c_int),
     ]
 
 
@@ -89,6 +89,19 @@ class SvdInfo(ctypes.Structure):
             "n_y2": self.n_y2, "sweeps_y2": self.sweeps_y2,
             "fused_fallback": self.fused_fallback,
         }
+
+
+class DeviceInfo:
+    """svd_info written on the device by a stream-ordered call (capture=1):
+    valid once the stream has reached the end of that call."""
+
+    def __init__(self, device):
+        import torch
+        self.buf = torch.zeros(ctypes.sizeof(SvdInfo), dtype=torch.uint8, device=device)
+
+    def read(self) -> dict:
+        raw = bytes(self.buf.cpu().numpy().tobytes())
+        return SvdInfo.from_buffer_copy(raw).as_dict()
 
 
 class EigInfo(ctypes.Structure):
@@ -131,7 +144,7 @@ def load():
     for fn in (lib.svd_plain, lib.svd_mixed):
         fn.argtypes = [ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp,
                        ctypes.c_int, _vp, ctypes.c_size_t, ctypes.POINTER(SvdOpts),
-                       ctypes.POINTER(SvdInfo), _vp]
+                       _vp, _vp]   # info: host SvdInfo, or device memory with capture=1
         fn.restype = ctypes.c_int
     lib.svd_batched_plan_create.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SvdOpts),
@@ -233,11 +246,15 @@ _ws_default = Workspace()
 
 
 def svd(A, mode: str = "mixed", workspace: Workspace | None = None, opts: SvdOpts | None = None,
-        **kw):
+        out=None, **kw):
     """A = U diag(S) V^T for an m x n float64 CUDA tensor, m >= n.
 
     mode: "mixed" (Algorithm 4) or "plain" (Algorithm 2).  Keyword arguments
-    set svd_opts fields.  Returns (U, S, V, info dict); U is m x n, V is n x n.
+    set svd_opts fields.  Returns (U, S, V, info); U is m x n, V is n x n.
+    info is a dict, or with capture=1 (stream-ordered: nothing synchronises,
+    so the call can be captured in a CUDA/HIP graph) a DeviceInfo to read()
+    after the stream has run.  out: the (U, S, V, DeviceInfo) of an earlier
+    capture=1 call of the same shape, written again in place.
     """
     import torch
     lib = load()
@@ -251,21 +268,31 @@ def svd(A, mode: str = "mixed", workspace: Workspace | None = None, opts: SvdOpt
     o = opts if opts is not None else default_opts(mixed, **kw)
     dev = A.device
     Acm = A.t().contiguous()              # storage = column-major m x n
-    Ut = torch.empty((n, m), dtype=torch.float64, device=dev)
-    Vt = torch.empty((n, n), dtype=torch.float64, device=dev)
-    S = torch.empty((n,), dtype=torch.float64, device=dev)
+    if out is not None:
+        if not o.capture:
+            raise ValueError("out= is for capture=1 calls")
+        Ut, S, Vt, dinfo = out[0].t(), out[1], out[2].t(), out[3]
+        if Ut.shape != (n, m) or S.shape != (n,) or Vt.shape != (n, n) or not (
+                Ut.is_contiguous() and Vt.is_contiguous()):
+            raise ValueError("out does not match A")
+    else:
+        Ut = torch.empty((n, m), dtype=torch.float64, device=dev)
+        Vt = torch.empty((n, n), dtype=torch.float64, device=dev)
+        S = torch.empty((n,), dtype=torch.float64, device=dev)
+        dinfo = DeviceInfo(dev) if o.capture else None
     nbytes = int(lib.svd_workspace_size(m, n, ctypes.byref(o)))
     ws = (workspace or _ws_default).get(nbytes, dev)
     info = SvdInfo()
+    info_ptr = dinfo.buf.data_ptr() if o.capture else ctypes.addressof(info)
     fn = lib.svd_mixed if mixed else lib.svd_plain
     with torch.cuda.device(dev):
         rc = fn(m, n, Acm.data_ptr(), max(m, 1), S.data_ptr(), Ut.data_ptr(), max(m, 1),
                 Vt.data_ptr(), max(n, 1), ws.data_ptr(), ws.numel(), ctypes.byref(o),
-                ctypes.byref(info), _stream_ptr(dev))
+                info_ptr, _stream_ptr(dev))
     if rc != 0:
         raise RuntimeError(f"svd_{mode} returned {rc}: {lib.svd_status_string(rc).decode()} "
                            f"[{lib.svd_last_error().decode()}]")
-    return Ut.t(), S, Vt.t(), info.as_dict()
+    return Ut.t(), S, Vt.t(), (dinfo if o.capture else info.as_dict())
 
 
 def eigh(A, workspace: Workspace | None = None, opts: SvdOpts | None = None, **kw):

@@ -160,7 +160,89 @@ struct Small {
     double condl;        // max|l_ii| / min|l_ii| of X = L (before the solve for V)
     double pivscale;     // power of two for the FP32 copy of A1 (pivots)
     double lowscale;     // power of two for the FP32 copy of X (FP32 stage)
+    // stream-ordered mode (svd_opts.capture): decisions taken on the device
+    int branch;          // SVD_BRANCH_LOW or SVD_BRANCH_SKIP
+    int vtaken;          // v_method 1: 1 solve accepted, 3 rejected
+    SweepCtl ctl_low, ctl_work;
 };
+static_assert(sizeof(Small) <= 4096, "small-scalar block");
+
+inline dim3 grid_n(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+__global__ void k_zero_words(int *p, int n) {
+    for (int i = threadIdx.x; i < n; i += 256) p[i] = 0;
+}
+
+// Section 3.5's three tests on the device: skip the FP32 stage when
+// max|r_ii| / min|r_ii| <= tol_cond, when at least nsmall_min trailing
+// columns of X are small, or when max|X_t^T X_t - I| <= tol_orth; a forced
+// branch overrides them.  A skip switches the FP32 stage's sweeps off.
+__global__ void k_branch_decide(Small *sm, double tol_cond, int nsmall_min, double tol_orth,
+                                int forced) {
+    if (threadIdx.x != 0) return;
+    bool skip = sm->cond <= tol_cond || sm->nsmall >= nsmall_min || (double)sm->orth <= tol_orth;
+    if (forced == SVD_BRANCH_LOW) skip = false;
+    if (forced == SVD_BRANCH_SKIP) skip = true;
+    sm->branch = skip ? SVD_BRANCH_SKIP : SVD_BRANCH_LOW;
+    sm->ctl_low.stop = skip ? 1 : 0;
+}
+
+// Skip branch in the stream-ordered mode: the switch ran on the unrotated
+// FP32 copy, and its result is replaced by Q = I: Y = X (and V_acc = I
+// when V is accumulated).
+__global__ void k_select_skip(const Small *sm, int N, const double *X, double *Y, double *Vacc) {
+    if (sm->branch != SVD_BRANCH_SKIP) return;
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)N * N) return;
+    Y[e] = X[e];
+    if (Vacc) Vacc[e] = (e % (size_t)N == e / (size_t)N) ? 1.0 : 0.0;
+}
+
+// v_method 1's acceptance test on the device (the same rule as on the host).
+__global__ void k_vsolve_decide(Small *sm, double tol_v) {
+    if (threadIdx.x != 0) return;
+    sm->vtaken = ((double)sm->orthv <= tol_v && sm->condl < INFINITY) ? 1 : 3;
+}
+
+// svd_info of a stream-ordered call, written by its last kernel.
+__global__ void k_write_info(const Small *sm, svd_info *info, int mixed, int want_v, int vsolve,
+                             int diagnostics) {
+    if (threadIdx.x != 0) return;
+    svd_info r;
+    memset(&r, 0, sizeof(r));
+    if (!sm) {   // n = 0
+        r.orth = -1.0;
+        r.orth_vx = -1.0;
+        r.orth_y = -1.0;
+        r.v_method_taken = want_v ? 0 : -1;
+        *info = r;
+        return;
+    }
+    const bool low = mixed && sm->branch == SVD_BRANCH_LOW;
+    r.branch_taken = mixed ? sm->branch : SVD_BRANCH_SKIP;
+    r.sweeps_low = low ? sm->ctl_low.sweeps : 0;
+    r.sweeps_work = sm->ctl_work.sweeps;
+    r.n_small = mixed ? sm->nsmall : 0;
+    r.orth = mixed ? (double)sm->orth : -1.0;
+    r.cond_r = mixed ? sm->cond : 0.0;
+    for (int i = 0; i < 32; ++i) {
+        r.off_low[i] = (low && i < sm->ctl_low.sweeps) ? sm->ctl_low.off[i] : 0.f;
+        r.off_work[i] = i < sm->ctl_work.sweeps ? sm->ctl_work.off[i] : 0.f;
+    }
+    r.v_method_taken = !want_v ? -1 : (vsolve ? sm->vtaken : 0);
+    r.orth_vx = vsolve ? (double)sm->orthv : -1.0;
+    r.orth_y = diagnostics ? (double)sm->orthy : -1.0;
+    r.fused_fallback = (low && sm->ctl_low.timeout) ? 2 : 0;
+    int st = SVD_OK;
+    if (!sm->ctl_work.conv) st = SVD_WARN_NOCONV;
+    if (sm->nzero) st = SVD_WARN_RANK_DEFICIENT;
+    if (vsolve && sm->vtaken == 3) st = SVD_WARN_VSOLVE;
+    if (sm->nonfinite_out) st = SVD_ERR_BREAKDOWN;
+    if (sm->err_wait || sm->ctl_work.timeout) st = SVD_ERR_WAIT_TIMEOUT;
+    if (sm->nonfinite) st = SVD_ERR_NONFINITE;
+    r.status = st;
+    *info = r;
+}
 
 // Per-stage HIP events; a failed event call leaves stage_ms at 0 instead of
 // failing the SVD.
@@ -169,7 +251,8 @@ struct Timer {
     bool ok = false;
     hipStream_t s;
     int last = 0;
-    explicit Timer(hipStream_t st) : s(st) {
+    Timer(hipStream_t st, bool on) : s(st) {
+        if (!on) return;
         ok = true;
         for (int i = 0; i < 9; ++i)
             if (hipEventCreate(&ev[i]) != hipSuccess) { ev[i] = nullptr; ok = false; }
@@ -230,7 +313,19 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     if (o.kernel_timing_every < 0) return -12;
     if (o.wait_polls < -1) return -12;
     if (o.fused_rounds < -1 || o.fused_rounds > 1) return -12;
-    if (info) {
+    if (o.capture != 0 && o.capture != 1) return -12;
+    const bool cap = o.capture != 0;
+    // the stream-ordered mode has no host-side clock, and Algorithm 3's
+    // route (no triangular factor for V) needs the branch known on the host
+    if (cap && o.kernel_timing != 0) return -12;
+    if (cap && mixed && o.switch_method == 3 && o.branch != SVD_BRANCH_LOW) return -12;
+    if (cap) {
+        // info is device memory, written by the call's last kernel
+        if (n == 0 && info)
+            hipLaunchKernelGGL(k_write_info, dim3(1), dim3(64), 0, (hipStream_t)stream,
+                               (const Small *)nullptr, info, mixed ? 1 : 0, o.want_v, 0, 0);
+        if (n == 0) return hipGetLastError() == hipSuccess ? 0 : SVD_ERR_HIP;
+    } else if (info) {
         memset(info, 0, sizeof(*info));
         info->orth = -1.0;
         info->orth_vx = -1.0;
@@ -276,16 +371,21 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     q.kc = jw.kc;
     float off_low[32] = {0}, off_work[32] = {0};
 
-    Timer tm(s);
+    Timer tm(s, !cap);
     Small hs;
-    MPJ_CHECK(hipMemsetAsync(sm, 0, sizeof(Small), s));
+    memset(&hs, 0, sizeof(hs));
+    // (a kernel, not a memset: the call may be captured in a graph)
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, (int *)sm, (int)(sizeof(Small) / 4));
+    if (cap) jw.off_hist = nullptr;
 
-    // a0: ingest (A is const) and non-finite scan
+    // a0: ingest (A is const) and non-finite scan; non-finite entries are
+    // copied as 0 so that the stream-ordered mode runs on finite data (its
+    // status then reports SVD_ERR_NONFINITE)
     double *Ain = (m > n) ? Atall : A1;
     const int ldin = (m > n) ? m : n;
     copy_scan(s, m, n, A, lda, Ain, ldin, &sm->nonfinite);
     MPJ_CHECK(hipGetLastError());
-    if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
+    if (!cap && read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
     if (hs.nonfinite) {
         if (info) info->status = SVD_ERR_NONFINITE;
         return 0;
@@ -307,7 +407,8 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         col_norms(s, n, n, A1, n, nrmX);
         pow2_scale(s, n, nrmX, &sm->pivscale);
         piv_launches = qrcp_pivots<float>(s, n, A1, n, (float *)D(L.off_wp), w + L.off_nrm2, piv,
-                                          jw.kc, &sm->pivscale, o.wait_polls);
+                                          jw.kc, &sm->pivscale, o.wait_polls,
+                                          cap ? &sm->err_wait : nullptr);
     } else {
         piv_launches = qrcp_pivots<double>(s, n, A1, n, D(L.off_wp), w + L.off_nrm2, piv, jw.kc,
                                            nullptr, o.wait_polls);
@@ -341,6 +442,20 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         col_norms(s, n, n, X, N, nrmX);
         count_small(s, n, nrmX, o.small_col_rel, &sm->nsmall);
         pow2_scale(s, n, nrmX, &sm->lowscale);
+        if (cap) {
+            // every test measured, the branch taken on the device
+            make_xt32(s, n, X, N, Xt, n);
+            gemm_orth_maxdev(s, n, Xt, n, &sm->orth);
+            hipLaunchKernelGGL(k_branch_decide, dim3(1), dim3(64), 0, s, sm,
+                               o.tol_cond_coef * pow((double)n, 0.25),
+                               (int)ceil(o.small_col_frac * n), o.tol_orth, o.branch);
+            MPJ_CHECK(hipGetLastError());
+            // the host enqueues the FP32 stage and the switch; with a skip
+            // the stage's sweeps exit at once and k_select_skip sets Y = X
+            branch = SVD_BRANCH_LOW;
+        }
+    }
+    if (mixed && !cap) {
         if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
         cond = hs.cond;
         nsmall = hs.nsmall;
@@ -378,7 +493,8 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
             convert_f64_f32(s, N, N, Ulow, N, V32, N);
         }
         jacobi_carve(jw, w + L.off_jac, N, L.b32, (int)sizeof(float));
-        jw.off_hist = off_low;
+        jw.off_hist = cap ? nullptr : off_low;
+        jw.ctl = cap ? &sm->ctl_low : nullptr;
         jw.stop_off = o.low_stop_off > 0 ? o.low_stop_off
                                          : (o.low_stop_off == 0 ? sqrt((double)n) * eps_low : 0.0);
         jw.fused = fused_low(n, o) ? 1 : 0;
@@ -399,6 +515,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         }
         jw.fused = 0;
         jw.stop_off = 0.0;
+        jw.ctl = nullptr;
         if (sweeps_low < 0) return SVD_ERR_HIP;
         tm.mark(5);
         // a7: switch (Section 3.3).  Method 1 (Algorithm 4): B = X^T U_low;
@@ -417,7 +534,8 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
                          q.split_elems, jw.kc);
         }
         qr_factor(s, n, n, Bm, n, tau3, T3, q);
-        if ((!o.want_v || o.v_method == 1) && o.switch_method != 3) {
+        const bool q_implicit = (!o.want_v || o.v_method == 1) && o.switch_method != 3;
+        if (q_implicit) {
             // V is formed after the sweeps (Section 3.4) or not at all, so Q
             // itself is not needed: Y = X Q = (Q^T X^T)^T, the reflectors
             // applied to X^T (U_low's buffer is free once B is formed)
@@ -433,6 +551,11 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
                          o.switch_method == 3 ? n : N, Vacc, N, 0.0, Y, N, q.split, q.split_elems,
                          jw.kc);
         }
+        if (cap) {
+            hipLaunchKernelGGL(k_select_skip, grid_n((size_t)N * N), dim3(256), 0, s,
+                               (const Small *)sm, N, (const double *)X, Y,
+                               q_implicit ? (double *)nullptr : Vacc);
+        }
         tm.mark(6);
     } else {
         MPJ_CHECK(hipMemcpyAsync(Y, X, (size_t)N * N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -446,13 +569,16 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     const bool vsolve = o.want_v && o.v_method == 1 && !alg3;
     double orth_y = -1.0;
     int n_y2 = 0, sweeps_y2 = 0;
-    const bool y2check = o.y2_safeguard && branch == SVD_BRANCH_LOW && n >= 2;
+    // (the safeguard picks Y2 on the host: not in the stream-ordered mode)
+    const bool y2check = o.y2_safeguard && branch == SVD_BRANCH_LOW && n >= 2 && !cap;
     if (o.diagnostics && !y2check) {
         // how far the columns of Y are from orthogonal when the FP64 sweeps start
         normalize_cols64(s, n, n, Y, N, Ulow, N);
         gemm_orth_maxdev64(s, n, Ulow, N, &sm->orthy);
-        if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
-        orth_y = hs.orthy;
+        if (!cap) {
+            if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
+            orth_y = hs.orthy;
+        }
     }
     if (y2check) {
         // Section 3.4's safeguard: C = D^-1 Y^T Y D^-1; the columns whose
@@ -504,7 +630,8 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
 
     int conv_work = 0;
     jacobi_carve(jw, w + L.off_jac, N, L.b64, (int)sizeof(double));
-    jw.off_hist = off_work;
+    jw.off_hist = cap ? nullptr : off_work;
+    jw.ctl = cap ? &sm->ctl_work : nullptr;
     const int sweeps_work = jacobi_sweeps<double>(s, N, L.b64, Y, (o.want_v && !vsolve) ? Vacc : nullptr,
                                                   eps_work, o.maxsweep_work, inner, jw, &conv_work);
     if (sweeps_work < 0) return SVD_ERR_HIP;
@@ -516,15 +643,23 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         diag_cond(s, n, X, N, &sm->condl);
         trsm_lower(s, n, n, X, N, Vacc, N, jw.kc);
         gemm_orth_maxdev64(s, n, Vacc, N, &sm->orthv);
-        if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
+        const double tol_v = o.tol_vsolve > 0 ? o.tol_vsolve : n * ldexp(1.0, -50);
+        if (cap) {
+            // accepted or not, V_X stays the solve's (the fallback below
+            // needs the host); a rejection is reported in the status
+            hipLaunchKernelGGL(k_vsolve_decide, dim3(1), dim3(64), 0, s, sm, tol_v);
+        } else if (read_back(s, &hs, sm, sizeof(Small))) {
+            return SVD_ERR_HIP;
+        }
         orth_vx = hs.orthv;
         // default: n 2^-50 = 8 n u, the size of the rounding error that the
         // accumulated rotations of a few sweeps leave in V_X.  A zero on the
         // diagonal of L (rank-deficient X) makes the solve meaningless, and a
         // NaN from it reads as an infinite deviation: both take the other
         // route of Section 3.4.
-        const double tol_v = o.tol_vsolve > 0 ? o.tol_vsolve : n * ldexp(1.0, -50);
-        if (orth_vx <= tol_v && hs.condl < INFINITY) {
+        if (cap) {
+            v_taken = 1;
+        } else if (orth_vx <= tol_v && hs.condl < INFINITY) {
             v_taken = 1;
         } else {
             // not accurate enough: V_X from the QR of X^T U_X (U_X = the
@@ -567,6 +702,13 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         if (o.sign_normalize) sign_normalize(s, m, n, U, ldu, o.want_u != 0, V, ldv);
     }
     MPJ_CHECK(hipGetLastError());
+    if (cap) {
+        if (info)
+            hipLaunchKernelGGL(k_write_info, dim3(1), dim3(64), 0, s, (const Small *)sm, info,
+                               mixed ? 1 : 0, o.want_v, vsolve ? 1 : 0, o.diagnostics);
+        MPJ_CHECK(hipGetLastError());
+        return 0;
+    }
     tm.mark(7);
     if (read_back(s, &hs, sm, sizeof(Small))) return SVD_ERR_HIP;
     kclock.collect();

@@ -171,13 +171,26 @@ double qrcp_pass_flops(int n);
 // scale (device, may be NULL): a power of two applied to A1 before it is
 // rounded to T (pivots are invariant under it); spin: polls of the one-launch
 // pass's bounded waits (0 = default, < 0 = give up at once, which sends the
-// pass to the step-by-step fallback).
+// pass to the step-by-step fallback).  err_out (device, may be NULL): the
+// stream-ordered mode; the one-launch pass then sets *err_out when a wait ran
+// out instead of being checked from the host, and nothing falls back.
 template <typename T>
 int qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W,
                  void *scratch, int *piv, KernelClock *kc = nullptr,
-                 const double *scale = nullptr, int spin = 0);
+                 const double *scale = nullptr, int spin = 0, int *err_out = nullptr);
 
 // ---------------------------------------------------------------- Jacobi
+// Device-side state of one Jacobi stage in the stream-ordered mode (all
+// sweeps enqueued, stopping decided on the device).  Zero before the stage,
+// except `stop`, which may start at 1 to switch the whole stage off.
+struct SweepCtl {
+    int stop;       // 1: the enqueued sweeps that remain exit at once
+    int sweeps;     // sweeps run
+    int conv;       // 1: a stopping rule fired (not only the cap)
+    int timeout;    // a bounded wait of a fused round ran out (Y invalid)
+    float off[32];  // per sweep: max relative off-diagonal
+};
+
 struct JacobiWork {
     void *gram;      // partial Gram blocks
     void *wmat;      // per-pair rotation blocks
@@ -200,6 +213,7 @@ struct JacobiWork {
     int fused = 0;              // 1: FP32 sweeps without V may use the fused round
     int spin = 0;               // polls of the fused round's wait (0 = default,
                                 // < 0 = give up at once, a test hook)
+    SweepCtl *ctl = nullptr;    // device: stream-ordered mode (see SweepCtl)
 };
 size_t jacobi_scratch_bytes(int N, int b, int elem);
 void jacobi_carve(JacobiWork &j, char *base, int N, int b, int elem);

@@ -69,7 +69,9 @@ __device__ __forceinline__ int blk_col(int c, int b, int I, int J) {
 // partial tiles are then summed in a fixed order through LDS.
 template <int B2>
 __global__ __launch_bounds__(JR_NT) void jac_gram_f32(int N, int nblk, int r, const float *__restrict__ Y,
-                                                      int ldy, float *__restrict__ Gp, int nchunk, int RG) {
+                                                      int ldy, float *__restrict__ Gp, int nchunk, int RG,
+                                                      const int *__restrict__ stop) {
+    if (stop && *stop) return;
     constexpr int b = B2 / 2;
     constexpr int NTT = B2 / 16;                       // tiles per dimension
     constexpr int NUT = NTT * (NTT + 1) / 2;           // upper-triangle tiles
@@ -129,7 +131,9 @@ __global__ __launch_bounds__(JR_NT) void jac_gram_f32(int N, int nblk, int r, co
 // wavefront order through one LDS buffer.
 template <int B2>
 __global__ __launch_bounds__(JR_NT) void jac_gram_f64(int N, int nblk, int r, const double *__restrict__ Y,
-                                                      int ldy, double *__restrict__ Gp, int nchunk, int RG) {
+                                                      int ldy, double *__restrict__ Gp, int nchunk, int RG,
+                                                      const int *__restrict__ stop) {
+    if (stop && *stop) return;
     constexpr int b = B2 / 2;
     constexpr int NTT = B2 / 16;                       // tiles per dimension
     constexpr int NUT = NTT * (NTT + 1) / 2;           // upper-triangle tiles
@@ -433,7 +437,8 @@ template <typename T, int B2, int NT>
 __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict__ Gp,
                                                 T *__restrict__ Wm, int *skip, int *flag,
                                                 float *offp, float *smxp, int *rot, double eps,
-                                                int max_inner, int cross) {
+                                                int max_inner, int cross, const int *__restrict__ stop) {
+    if (stop && *stop) return;
     constexpr int LD = B2 + 1;
     constexpr int H = B2 / 2;
     constexpr int TE = (B2 * B2) / NT;    // Gram entries per thread (set-up)
@@ -593,7 +598,9 @@ template <int B2>
 __global__ __launch_bounds__(JR_NT) void jac_update_f32(int N, int nblk, int r, float *__restrict__ Y,
                                                         int ldy, float *__restrict__ V, int ldv,
                                                         int nchY, const float *__restrict__ Wm,
-                                                        const int *__restrict__ skip) {
+                                                        const int *__restrict__ skip,
+                                                        const int *__restrict__ stop) {
+    if (stop && *stop) return;
     constexpr int b = B2 / 2, KS = B2 / 4, NTI = B2 / 16;
     static_assert(KS % 4 == 0 && b % KS == 0, "k mapping");
     const int pair = blockIdx.x;
@@ -660,7 +667,9 @@ template <int B2>
 __global__ __launch_bounds__(JR_NT, 2) void jac_update_f64(int N, int nblk, int r, double *__restrict__ Y,
                                                         int ldy, double *__restrict__ V, int ldv,
                                                         int nchY, const double *__restrict__ Wm,
-                                                        const int *__restrict__ skip) {
+                                                        const int *__restrict__ skip,
+                                                        const int *__restrict__ stop) {
+    if (stop && *stop) return;
     constexpr int b = B2 / 2, KS = B2 / 4, NTI = B2 / 16, LDW = B2 + 1;
     constexpr int RG = JU_RG;
     constexpr int TP = NTI > 2 ? 2 : NTI;
@@ -747,7 +756,8 @@ __global__ __launch_bounds__(NT) void jac_round_f32(int N, int nblk, int r, floa
                                                     int *__restrict__ gflag, int tag, int *flag,
                                                     float *offp, float *smxp, int *rot, double eps,
                                                     int max_inner, int cross, int spin,
-                                                    int *__restrict__ err) {
+                                                    int *__restrict__ err, const int *__restrict__ stop) {
+    if (stop && *stop) return;
     constexpr int b = B2 / 2, KS = B2 / 4, NTI = B2 / 16, NW = NT / 64;
     constexpr int NTT = B2 / 16, NUT = NTT * (NTT + 1) / 2;
     constexpr int LD = B2 + 1;
@@ -998,9 +1008,61 @@ void jacobi_carve(JacobiWork &jw, char *base, int N, int b, int elem) {
     }
 }
 
+// ---------------------------------------------------------------- sweep control
+// Start of a sweep: the any-rotation and time-out flags and the per-slot
+// maxima cleared (a kernel, not a memset, so the call can be captured in a
+// graph).  With ctl: nothing once the stage has stopped.
+__global__ __launch_bounds__(256) void jac_sweep_begin(const SweepCtl *ctl, int *flag, float *offp,
+                                                       float *smxp, int npairs) {
+    if (ctl && ctl->stop) return;
+    for (int i = threadIdx.x; i < npairs; i += 256) {
+        offp[i] = 0.f;
+        smxp[i] = 0.f;
+    }
+    if (threadIdx.x < 3) flag[threadIdx.x] = 0;
+}
+
+// End of a sweep in the stream-ordered mode: the stopping rules that the
+// host applies otherwise (a sweep without rotations, Algorithm 1; the
+// remaining off-diagonal and rotation sizes, as xGESVJ; the FP32 stage's
+// off-diagonal target), evaluated on the device.  The sweeps still enqueued
+// after `stop` is set exit at their first instruction.
+__global__ __launch_bounds__(256) void jac_sweep_end(SweepCtl *ctl, const int *flag, const float *offp,
+                                                     const float *smxp, int npairs, double n_real,
+                                                     double eps, double stop_off) {
+    __shared__ float ro[4], rs[4];
+    if (ctl->stop) return;
+    float o = 0.f, m = 0.f;
+    for (int i = threadIdx.x; i < npairs; i += 256) {
+        o = fmaxf(o, offp[i]);
+        m = fmaxf(m, smxp[i]);
+    }
+    o = wave_max(o);
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) { ro[threadIdx.x >> 6] = o; rs[threadIdx.x >> 6] = m; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const float off = fmaxf(fmaxf(ro[0], ro[1]), fmaxf(ro[2], ro[3]));
+    const float smx = fmaxf(fmaxf(rs[0], rs[1]), fmaxf(rs[2], rs[3]));
+    const int k = ctl->sweeps;
+    if (k < 32) ctl->off[k] = off;
+    ctl->sweeps = k + 1;
+    if (flag[1]) { ctl->timeout = 1; ctl->stop = 1; return; }
+    bool done = flag[0] == 0;
+    if (!done && (double)off < sqrt(n_real) * eps && n_real * (double)off * (double)smx < eps)
+        done = true;
+    if (!done && stop_off > 0.0 && off <= stop_off) done = true;
+    if (done) { ctl->conv = 1; ctl->stop = 1; }
+}
+
+__global__ void jac_fill_zero(int *p, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 // ---------------------------------------------------------------- fused FP32 rounds
 typedef void (*RoundFn)(int, int, int, float *, int, int, int, float *, int *, int, int *, float *,
-                        float *, int *, double, int, int, int, int *);
+                        float *, int *, double, int, int, int, int *, const int *);
 
 struct FusedCfg {
     int G = 0, R = 0, nt = 0;   // workgroups per pair slot, rows per workgroup, threads
@@ -1063,6 +1125,12 @@ static bool fused_config(int N, int B2, FusedCfg *fc) {
 // fc (FP32 stage, 64-wide blocks, no V): each round is one launch of the
 // fused kernel instead of the Gram, inner and update launches.  Returns -2 if
 // a wait of the fused kernel ran out (Y is then invalid).
+//
+// jw.ctl set (stream-ordered mode): all maxsweep sweeps are enqueued with no
+// host synchronisation, each ended by jac_sweep_end, which applies the
+// stopping rules on the device; the kernels of a sweep after the stop exit at
+// once.  Returns maxsweep; the sweeps run, convergence and a fused round's
+// time-out are in *jw.ctl.
 template <typename T, int B2, int INNER_NT>
 static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, int maxsweep,
                        int max_inner, JacobiWork &jw, int *conv, const FusedCfg *fc = nullptr) {
@@ -1082,16 +1150,19 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
     const double pair_upd_bytes = 2.0 * N * B2 * sizeof(T) * (V ? 2 : 1);
     const double pair_upd_flops = 2.0 * N * B2 * B2 * (V ? 2 : 1);
     std::vector<std::pair<size_t, int>> round_slots;   // clocked fused launches (slot, round)
+    // stream-ordered mode: every sweep is enqueued and stops on the device
+    SweepCtl *ctl = jw.ctl;
+    const int *stop = ctl ? &ctl->stop : nullptr;
     if (fc) {
-        const hipError_t e = hipMemsetAsync(jw.gflag, 0, (size_t)npairs * fc->G * sizeof(int), s);
-        if (e != hipSuccess) { note_hip_error(e, "fused round flag reset"); return -1; }
+        const int nf = npairs * fc->G;
+        hipLaunchKernelGGL(jac_fill_zero, dim3(cdiv(nf, 256)), dim3(256), 0, s, jw.gflag, nf);
     }
     for (; sw < maxsweep; ++sw) {
         round_slots.clear();
-        hipError_t e = hipMemsetAsync(jw.flag, 0, 3 * sizeof(int), s);
-        if (e == hipSuccess) e = hipMemsetAsync(jw.offp, 0, (size_t)npairs * sizeof(float), s);
-        if (e == hipSuccess) e = hipMemsetAsync(jw.smxp, 0, (size_t)npairs * sizeof(float), s);
         upd_slots.clear();
+        hipLaunchKernelGGL(jac_sweep_begin, dim3(1), dim3(256), 0, s, (const SweepCtl *)ctl, jw.flag,
+                           jw.offp, jw.smxp, npairs);
+        hipError_t e = hipGetLastError();
         if (e != hipSuccess) { note_hip_error(e, "jacobi flag reset"); return -1; }
         // kernel-class ids for the optional per-launch clock
         const int kbase = sizeof(T) == 4 ? 0 : 3;
@@ -1125,12 +1196,12 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
                         hipExtLaunchKernelGGL(fc->fn, grid, blk, 0, s, e0, e1, 0, N, nblk, r, (float *)Y,
                                               N, fc->G, fc->R, jw.gpart, jw.gflag, tag, jw.flag, jw.offp,
                                               jw.smxp, jw.rotmap + (size_t)r * npairs, eps, max_inner,
-                                              cross, spin, jw.flag + 1);
+                                              cross, spin, jw.flag + 1, stop);
                     } else {
                         hipLaunchKernelGGL(fc->fn, grid, blk, 0, s, N, nblk, r, (float *)Y, N, fc->G,
                                            fc->R, jw.gpart, jw.gflag, tag, jw.flag, jw.offp, jw.smxp,
                                            jw.rotmap + (size_t)r * npairs, eps, max_inner, cross, spin,
-                                           jw.flag + 1);
+                                           jw.flag + 1, stop);
                     }
                     continue;
                 }
@@ -1139,27 +1210,28 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
             if constexpr (sizeof(T) == 4) {
                 if (gclk)
                     hipExtLaunchKernelGGL((jac_gram_f32<B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, e0,
-                                          e1, 0, N, nblk, r, (const T *)Y, N, (T *)jw.gram, nchG, rgG);
+                                          e1, 0, N, nblk, r, (const T *)Y, N, (T *)jw.gram, nchG, rgG, stop);
                 else
                     hipLaunchKernelGGL((jac_gram_f32<B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, N, nblk,
-                                       r, (const T *)Y, N, (T *)jw.gram, nchG, rgG);
+                                       r, (const T *)Y, N, (T *)jw.gram, nchG, rgG, stop);
             } else {
                 if (gclk)
                     hipExtLaunchKernelGGL((jac_gram_f64<B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, e0,
-                                          e1, 0, N, nblk, r, (const T *)Y, N, (T *)jw.gram, nchG, rgG);
+                                          e1, 0, N, nblk, r, (const T *)Y, N, (T *)jw.gram, nchG, rgG, stop);
                 else
                     hipLaunchKernelGGL((jac_gram_f64<B2>), dim3(npairs, nchG), dim3(JR_NT), 0, s, N, nblk,
-                                       r, (const T *)Y, N, (T *)jw.gram, nchG, rgG);
+                                       r, (const T *)Y, N, (T *)jw.gram, nchG, rgG, stop);
             }
             if (jw.kc && jw.kc->slot(kbase + 1, 0.0, inner_flops, &e0, &e1))
                 hipExtLaunchKernelGGL((jac_inner<T, B2, INNER_NT>), dim3(npairs), dim3(INNER_NT), 0, s,
                                       e0, e1, 0, nchG, (const T *)jw.gram, (T *)jw.wmat, jw.skip,
                                       jw.flag, jw.offp, jw.smxp, jw.rotmap + (size_t)r * npairs, eps,
-                                      max_inner, cross);
+                                      max_inner, cross, stop);
             else
                 hipLaunchKernelGGL((jac_inner<T, B2, INNER_NT>), dim3(npairs), dim3(INNER_NT), 0, s,
                                    nchG, (const T *)jw.gram, (T *)jw.wmat, jw.skip, jw.flag, jw.offp,
-                                   jw.smxp, jw.rotmap + (size_t)r * npairs, eps, max_inner, cross);
+                                   jw.smxp, jw.rotmap + (size_t)r * npairs, eps, max_inner, cross,
+                                   stop);
             const bool clk = jw.kc && jw.kc->slot(kbase + 2, upd_bytes, upd_flops, &e0, &e1);
             if (clk) upd_slots.push_back({jw.kc->used / 2 - 1, r});
             if constexpr (sizeof(T) == 4) {
@@ -1167,20 +1239,28 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
                 if (clk)
                     hipExtLaunchKernelGGL((jac_update_f32<B2>), ugrid, dim3(JR_NT), 0, s, e0, e1, 0, N,
                                           nblk, r, Y, N, V, N, nch, (const T *)jw.wmat,
-                                          (const int *)jw.skip);
+                                          (const int *)jw.skip, stop);
                 else
                     hipLaunchKernelGGL((jac_update_f32<B2>), ugrid, dim3(JR_NT), 0, s, N, nblk, r, Y, N,
-                                       V, N, nch, (const T *)jw.wmat, (const int *)jw.skip);
+                                       V, N, nch, (const T *)jw.wmat, (const int *)jw.skip, stop);
             } else {
                 const dim3 ugrid(npairs, nch + nchV);
                 if (clk)
                     hipExtLaunchKernelGGL((jac_update_f64<B2>), ugrid, dim3(JR_NT), 0, s, e0, e1, 0, N,
                                           nblk, r, Y, N, V, N, nch, (const T *)jw.wmat,
-                                          (const int *)jw.skip);
+                                          (const int *)jw.skip, stop);
                 else
                     hipLaunchKernelGGL((jac_update_f64<B2>), ugrid, dim3(JR_NT), 0, s, N, nblk, r, Y, N,
-                                       V, N, nch, (const T *)jw.wmat, (const int *)jw.skip);
+                                       V, N, nch, (const T *)jw.wmat, (const int *)jw.skip, stop);
             }
+        }
+        if (ctl) {
+            hipLaunchKernelGGL(jac_sweep_end, dim3(1), dim3(256), 0, s, ctl, (const int *)jw.flag,
+                               (const float *)jw.offp, (const float *)jw.smxp, npairs,
+                               (double)jw.n_real, eps, jw.stop_off);
+            e = hipGetLastError();
+            if (e != hipSuccess) { note_hip_error(e, "jacobi sweep"); return -1; }
+            continue;
         }
         e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(jw.hflag, jw.flag, 3 * sizeof(int), hipMemcpyDeviceToHost, s);

@@ -16,8 +16,11 @@ __global__ void k_copy_scan(int m, int n, const double *A, int lda, double *D, i
     if (e >= (size_t)m * n) return;
     const int i = (int)(e % m), j = (int)(e / m);
     const double v = A[(size_t)j * lda + i];
-    D[(size_t)j * ldd + i] = v;
-    if (!isfinite(v)) *nf = 1;
+    // a non-finite entry is flagged and copied as 0 (the outputs of such a
+    // call are undefined; the rest of the path then runs on finite data)
+    const bool fin = isfinite(v);
+    D[(size_t)j * ldd + i] = fin ? v : 0.0;
+    if (!fin) *nf = 1;
 }
 void copy_scan(hipStream_t s, int m, int n, const double *A, int lda, double *D, int ldd, int *nf) {
     if ((size_t)m * n == 0) return;

@@ -538,11 +538,19 @@ size_t qrcp_scratch_bytes(int n, int elem) {
     return m > c ? m : c;
 }
 
+// A wait of the one-launch pass that ran out, passed on to *out (OR).
+__global__ void qrcp_err_out(const int *err, int *out) {
+    if (threadIdx.x == 0 && *err) *out = 1;
+}
+
 // The one-launch FP32 pass; false when it does not apply or could not run
 // (then nothing observable has changed and the caller takes the step path).
+// err_out set (stream-ordered mode): the pass's time-out flag is passed on
+// to *err_out on the device instead of being read back, and there is no
+// fallback (the pivots are then a clamped, possibly repeating, column list).
 static bool qrcp_persist_pass(hipStream_t s, int n, const double *A1, int lda, float *W,
                               void *scratch, int *piv, KernelClock *kc, const double *scale,
-                              int spin) {
+                              int spin, int *err_out) {
     const int sp = spin == 0 ? QP_SPIN : spin;
     if (n < 128 || n > 64 * 64) return false;
     const int nwg = cdiv(n, QP_W);
@@ -577,6 +585,10 @@ static bool qrcp_persist_pass(hipStream_t s, int n, const double *A1, int lda, f
                            err, piv, scale, sp);
     if (kc) kc->end(s);
     if (hipGetLastError() != hipSuccess) return false;
+    if (err_out) {
+        hipLaunchKernelGGL(qrcp_err_out, dim3(1), dim3(64), 0, s, (const int *)err, err_out);
+        return hipGetLastError() == hipSuccess;
+    }
     int h_err = 1;
     if (hipMemcpyAsync(&h_err, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
@@ -588,7 +600,7 @@ static bool qrcp_persist_pass(hipStream_t s, int n, const double *A1, int lda, f
 
 template <typename T>
 int qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, void *scratch, int *piv,
-                KernelClock *kc, const double *scale, int spin) {
+                KernelClock *kc, const double *scale, int spin, int *err_out) {
     if (n <= 0) return 0;
     if (n > 64 * 64) {
         T *norms2 = (T *)scratch;
@@ -604,7 +616,8 @@ int qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, void *scr
         }
         return n;
     }
-    if (sizeof(T) == 4 && qrcp_persist_pass(s, n, A1, lda, (float *)W, scratch, piv, kc, scale, spin))
+    if (sizeof(T) == 4 &&
+        qrcp_persist_pass(s, n, A1, lda, (float *)W, scratch, piv, kc, scale, spin, err_out))
         return 1;
     int *perm = (int *)scratch;
     const size_t ncand = (size_t)cdiv(n, Q2_W) + 1;
@@ -632,8 +645,8 @@ int qrcp_pivots(hipStream_t s, int n, const double *A1, int lda, T *W, void *scr
 }
 
 template int qrcp_pivots<float>(hipStream_t, int, const double *, int, float *, void *, int *,
-                                KernelClock *, const double *, int);
+                                KernelClock *, const double *, int, int *);
 template int qrcp_pivots<double>(hipStream_t, int, const double *, int, double *, void *, int *,
-                                 KernelClock *, const double *, int);
+                                 KernelClock *, const double *, int, int *);
 
 } // namespace mpj
