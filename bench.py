@@ -363,6 +363,48 @@ def secondary(mp, ws, steps: int) -> dict:
     return out
 
 
+def graph_replay(mp, A, ws, steps: int, s_ref, kappa) -> dict:
+    """The step's svd_mixed in the stream-ordered mode (capture=1: no host
+    synchronisation, decisions on the device), eagerly and captured once in
+    a HIP graph and replayed.  Every sweep up to the caps (30 and 30) is
+    enqueued; those after the device-side stop exit at once."""
+    import torch
+    o = mp.default_opts(True, capture=1, y2_safeguard=0)
+    out = mp.svd(A, "mixed", workspace=ws, opts=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        mp.svd(A, "mixed", workspace=ws, opts=o, out=out)
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / steps
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        mp.svd(A, "mixed", workspace=ws, opts=o, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        mp.svd(A, "mixed", workspace=ws, opts=o, out=out)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / steps
+    info = out[3].read()
+    gates = gates_gpu(A, out[0], out[1], out[2], s_ref, kappa or 1.0)
+    del g
+    print(f"[bench] stream-ordered mixed: eager {t_eager * 1e3:.1f} ms, graph replay "
+          f"{t_graph * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    return {"eager_ms": round(t_eager * 1e3, 2), "graph_replay_ms": round(t_graph * 1e3, 2),
+            "caps": [o.maxsweep_low, o.maxsweep_work],
+            "info": {k: info[k] for k in ("status", "branch_taken", "sweeps_low", "sweeps_work",
+                                          "v_method_taken")},
+            "gates": gates}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -573,6 +615,7 @@ def main() -> int:
     line["kernels"] = kernels
     if do_mixed and do_plain and not args.no_secondary:
         line["secondary"] = secondary(mp, ws, args.steps)
+        line["secondary"]["C3b_stream_ordered"] = graph_replay(mp, A, ws, args.steps, s_ref, kappa)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_sample_n)

@@ -11,8 +11,10 @@ every entry point raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass, field
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -335,7 +337,14 @@ def call_raw(mode: str, m: int, n: int, A_ptr: int, lda: int, S_ptr: int, U_ptr:
 
 
 # ----------------------------------------------------------------------------- batched
-@dataclass
+# Live plans, destroyed by an exit handler that runs while the HIP runtime
+# and the library are still loaded (a plan holds a graph exec, a capture
+# stream and device metadata, which must not outlive the runtime's own
+# teardown at process exit).
+_live_plans = weakref.WeakSet()
+
+
+@dataclass(eq=False)
 class BatchedPlan:
     handle: int
     work_bytes: int
@@ -343,11 +352,22 @@ class BatchedPlan:
     offA: list = field(default_factory=list)
     offS: list = field(default_factory=list)
     offV: list = field(default_factory=list)
+    _lib = None          # the loaded library (kept so close() needs no module global)
+
+    def close(self):
+        """Release the plan's device resources (idempotent)."""
+        if self.handle and self._lib is not None:
+            self._lib.svd_batched_plan_destroy(self.handle)
+        self.handle = 0
 
     def __del__(self):
-        if self.handle and _lib is not None:
-            _lib.svd_batched_plan_destroy(self.handle)
-            self.handle = 0
+        self.close()
+
+
+@atexit.register
+def _close_plans():
+    for p in list(_live_plans):
+        p.close()
 
 
 def batched_plan(shapes, opts: SvdOpts | None = None) -> BatchedPlan:
@@ -367,7 +387,9 @@ def batched_plan(shapes, opts: SvdOpts | None = None) -> BatchedPlan:
         offA.append(a); offS.append(s); offV.append(v)
         a += m * n; s += n; v += n * n
     p = BatchedPlan(h.value or 0, int(wb.value), list(shapes), offA, offS, offV)
+    p._lib = lib
     p.totA, p.totS, p.totV = a, s, v
+    _live_plans.add(p)
     return p
 
 
@@ -404,6 +426,32 @@ def svd_batched(plan: BatchedPlan, A_packed, workspace: Workspace | None = None,
     if rc != 0:
         raise RuntimeError(f"svd_batched returned {rc}")
     return S, U, V, info
+
+
+_uniform_plans = {}
+
+
+def svd_batched_uniform(A, workspace: Workspace | None = None):
+    """svd_batched on a (B, m, n) float64 CUDA tensor of equal-size matrices
+    (n <= m <= 256): returns U (B, m, n), S (B, n), V (B, n, n) and the
+    (B, 4) per-matrix info tensor.  Plans are kept per shape and device."""
+    import torch
+    _check_device(A, "A")
+    if A.dim() != 3:
+        raise ValueError("A must be 3-D")
+    B, m, n = A.shape
+    if not (1 <= n <= m <= 256):
+        raise ValueError("svd_batched takes 1 <= n <= m <= 256")
+    key = (B, m, n, A.device)
+    plan = _uniform_plans.get(key)
+    if plan is None:
+        if len(_uniform_plans) >= 8:
+            _uniform_plans.pop(next(iter(_uniform_plans))).close()
+        plan = _uniform_plans[key] = batched_plan([(m, n)] * B)
+    packed = A.transpose(1, 2).contiguous().view(-1)     # column-major, ld = m
+    S, U, V, info = svd_batched(plan, packed, workspace)
+    return (U[:B * m * n].view(B, n, m).transpose(1, 2), S[:B * n].view(B, n),
+            V[:B * n * n].view(B, n, n).transpose(1, 2), info)
 
 
 def unpack_batch(plan: BatchedPlan, S, U, V):
@@ -469,8 +517,9 @@ def _autograd_fn():
     import torch
 
     class SVD(torch.autograd.Function):
-        """Differentiable SVD: forward svd_mixed per matrix (or batched),
-        backward svd_backward."""
+        """Differentiable SVD: forward svd_mixed (a 2-D input), svd_batched (a
+        3-D input of matrices with n <= m <= 256) or svd_mixed per matrix (a
+        3-D input of larger matrices); backward svd_backward."""
 
         @staticmethod
         def forward(ctx, A):
@@ -479,10 +528,13 @@ def _autograd_fn():
                 ctx.save_for_backward(U.unsqueeze(0), S.unsqueeze(0), V.unsqueeze(0))
                 ctx.single = True
                 return U, S, V
-            outs = [svd(A[b], "mixed")[:3] for b in range(A.shape[0])]
-            U = torch.stack([o[0] for o in outs])
-            S = torch.stack([o[1] for o in outs])
-            V = torch.stack([o[2] for o in outs])
+            if A.dim() == 3 and A.shape[0] > 0 and 1 <= A.shape[2] <= A.shape[1] <= 256:
+                U, S, V, _ = svd_batched_uniform(A.detach())
+            else:
+                outs = [svd(A[b], "mixed")[:3] for b in range(A.shape[0])]
+                U = torch.stack([o[0] for o in outs])
+                S = torch.stack([o[1] for o in outs])
+                V = torch.stack([o[2] for o in outs])
             ctx.save_for_backward(U, S, V)
             ctx.single = False
             return U, S, V
