@@ -125,9 +125,11 @@ CLASS_ROOF = {
     # cores, its inner solve a chain of dependent LDS rounds
     "jac_round<f32>": ("mfma", FP32_PEAK_TF),
     "trsm_diag": ("latency", FP64_PEAK_TF),
+    # the same round on BF16 storage (BF16 Gram products, FP32 update)
+    "jac_round<bf16>": ("mfma", FP32_PEAK_TF),
 }
 GEMM_CLASS = 8                 # many shapes in one class: listed, never the dominant kernel
-SURVEY_CLASSES = range(0, 11)
+SURVEY_CLASSES = range(0, 12)
 
 
 def class_survey(mp, A, ws, mode: str, classes) -> dict:
@@ -520,6 +522,28 @@ def main() -> int:
         t_plain_vs = (time.perf_counter() - t0) / args.steps
         print(f"[bench] plain with solved V {t_plain_vs * 1e3:.1f} ms/SVD", file=sys.stderr, flush=True)
 
+    # the three-precision variant: the first FP32-stage sweeps on a BF16 Y
+    # (BF16 Gram products), at most k of them
+    three = None
+    if do_mixed and not args.no_secondary:
+        three = {}
+        for k, hs in ((0, 0), (6, 0), (4, 1)):
+            o3 = mp.default_opts(True, half_sweeps=k, half_storage=hs)
+            mp.svd(A, "mixed", workspace=ws, opts=o3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                U3, S3, V3, i3 = mp.svd(A, "mixed", workspace=ws, opts=o3)
+            torch.cuda.synchronize()
+            t3 = (time.perf_counter() - t0) / args.steps
+            three[f"half_sweeps={k}" + (",bf16_storage" if hs else "")] = {"ms": round(t3 * 1e3, 2),
+                             "info": {q: i3[q] for q in ("status", "sweeps_half", "sweeps_low",
+                                                         "sweeps_work", "n_y2", "sweeps_y2")},
+                             "stage_ms": [round(x, 2) for x in i3["stage_ms"]],
+                             "out": (U3, S3, V3)}
+            print(f"[bench] three-precision half_sweeps={k} storage={hs}: {t3 * 1e3:.1f} ms/SVD",
+                  file=sys.stderr, flush=True)
+
     # gates against the stored oracle sigma (when this size has one)
     s_ref, kappa = None, None
     if n == 4096:
@@ -535,6 +559,9 @@ def main() -> int:
     g_plain = gates_gpu(A, Up, Sp, Vp, s_ref, kappa or 1.0) if do_plain else None
     if t_plain_vs is not None:
         g_plain_vs = gates_gpu(A, Upv, Spv, Vpv, s_ref, kappa or 1.0)
+    if three:
+        for v in three.values():
+            v["gates"] = gates_gpu(A, *v.pop("out"), s_ref, kappa or 1.0)
 
     # roofline of the dominant kernel class of the mixed step, from the
     # clocked launches of the timed region
@@ -611,6 +638,8 @@ def main() -> int:
             "info": {k: info_pv[k] for k in ("status", "sweeps_work", "v_method_taken", "orth_vx")},
             "stage_ms": [round(x, 2) for x in info_pv["stage_ms"]], "gates": g_plain_vs,
         }
+    if three:
+        line["three_precision"] = three
     line["roofline"] = roofline
     line["kernels"] = kernels
     if do_mixed and do_plain and not args.no_secondary:

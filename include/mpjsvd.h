@@ -201,6 +201,22 @@ typedef struct {
                               pass's wait ran out (SVD_ERR_WAIT_TIMEOUT);
                               switch_method 3 needs branch = SVD_BRANCH_LOW.
                               0 (default): the host-synchronised call. */
+    int half_sweeps;       /* three-precision variant (the GPU outlook of
+                              the paper's conclusions): the first sweeps of
+                              the FP32 stage form their Gram blocks with
+                              BF16 matrix-core products (operands rounded
+                              to BF16, FP32 sums); rotation angles, tests,
+                              the update and Y stay FP32 (FP64 angles).  At
+                              most half_sweeps such sweeps, fewer once a
+                              sweep ends with every relative off-diagonal
+                              <= half_stop_off; then the FP32 sweeps
+                              continue on the same Y.  Only where the fused
+                              round runs (see fused_rounds); default 4;
+                              0 = off */
+    double half_stop_off;  /* 0 -> 2^-6 */
+    int half_storage;      /* 1: those sweeps also keep Y in BF16 (the
+                              update's result rounded to BF16, Y widened to
+                              FP32 after them); 0 (default): Y stays FP32 */
 } svd_opts;
 
 /* Kernel classes reported by svd_info.kern_* (kernel_timing 1: SVD_K_QRCP
@@ -217,6 +233,8 @@ typedef struct {
 #define SVD_K_ROUND32 9    /* fused FP32 Jacobi round (Gram, inner solve
                               and update in one launch)               */
 #define SVD_K_TRSM 10      /* diagonal-block solves of V_X = X^-1 Y     */
+#define SVD_K_ROUND16 11   /* fused round of the BF16 sweeps (BF16 Gram
+                              products; Y in BF16 with half_storage)   */
 #define SVD_K_NCLASS 12
 
 typedef struct {
@@ -250,6 +268,7 @@ typedef struct {
     int fused_fallback;    /* 1: a fused FP32 round gave up waiting and the
                               FP32 stage was run again with separate kernels;
                               2 (capture = 1): the FP32 stage stopped there */
+    int sweeps_half;       /* BF16 sweeps run before the FP32 sweeps */
 } svd_info;
 
 /* Load the tuning table measured by the autotuner (not part of the paper's

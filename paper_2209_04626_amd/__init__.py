@@ -38,7 +38,7 @@ SVD_ERR_HIP, SVD_ERR_SCRATCH_LIMIT = -100, -101
 BACKWARD_NOALLOC_SCRATCH_BYTES = 64 << 20
 KERNEL_CLASSES = ["jac_gram<f32>", "jac_inner<f32>", "jac_update<f32>", "jac_gram<f64>",
                   "jac_inner<f64>", "jac_update<f64>", "qrcp", "qr_panel", "gemm", "jac_round<f32>",
-                  "trsm_diag", "-"]
+                  "trsm_diag", "jac_round<bf16>"]
 NCLASS = 12
 BRANCH_AUTO, BRANCH_LOW, BRANCH_SKIP = 0, 1, 2
 
@@ -60,6 +60,8 @@ class SvdOpts(ctypes.Structure):
         ("y2_safeguard", ctypes.c_int), ("tol_y2", ctypes.c_double),
         ("kernel_timing_every", ctypes.c_int), ("wait_polls", ctypes.c_int),
         ("fused_rounds", ctypes.c_int), ("capture", ctypes.c_int),
+        ("half_sweeps", ctypes.c_int), ("half_stop_off", ctypes.c_double),
+        ("half_storage", ctypes.c_int),
     ]
 
 
@@ -74,6 +76,7 @@ class SvdInfo(ctypes.Structure):
         ("v_method_taken", ctypes.c_int), ("sweeps_vfix", ctypes.c_int),
         ("orth_vx", ctypes.c_double), ("orth_y", ctypes.c_double),
         ("n_y2", ctypes.c_int), ("sweeps_y2", ctypes.c_int), ("fused_fallback", ctypes.c_int),
+        ("sweeps_half", ctypes.c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -89,7 +92,7 @@ class SvdInfo(ctypes.Structure):
             "v_method_taken": self.v_method_taken, "sweeps_vfix": self.sweeps_vfix,
             "orth_vx": self.orth_vx, "orth_y": self.orth_y,
             "n_y2": self.n_y2, "sweeps_y2": self.sweeps_y2,
-            "fused_fallback": self.fused_fallback,
+            "fused_fallback": self.fused_fallback, "sweeps_half": self.sweeps_half,
         }
 
 

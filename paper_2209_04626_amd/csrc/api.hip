@@ -55,6 +55,12 @@ extern "C" void svd_default_opts(svd_opts *o, int mixed) {
     o->kernel_timing_every = 1;
     o->wait_polls = 0;
     o->fused_rounds = 0;
+    o->capture = 0;
+    // measured at n = 4096: four BF16-Gram sweeps then FP32 sweeps beat
+    // FP32 sweeps alone; more BF16 sweeps do not shorten the FP32 ones
+    o->half_sweeps = 4;
+    o->half_stop_off = 0.0;
+    o->half_storage = 0;
 }
 
 namespace {
@@ -66,7 +72,7 @@ struct Layout {
     size_t off_atall, off_tau0, off_t0, off_a1, off_wp, off_nrm2, off_piv, off_a1p, off_tau1,
         off_t1, off_rt, off_tau2, off_t2, off_x, off_y, off_vacc, off_y32, off_xt, off_ulow, off_bm,
         off_tau3, off_t3, off_ux, off_vx, off_sig, off_rank, off_nrmx, off_small, off_qr, off_jac,
-        off_v32, off_v2, off_idx, total;
+        off_v32, off_v2, off_idx, off_y16, total;
 };
 
 // Whether the FP32 stage asks for the fused round (it still falls back to
@@ -125,6 +131,7 @@ Layout layout(int m, int n, const svd_opts &o) {
     L.off_vacc = take(NN * d);
     L.off_y32 = take(NN * f);
     L.off_v32 = take(o.switch_method >= 2 ? NN * f : 0);   // V_low for switch methods 2 and 3
+    L.off_y16 = take(o.half_sweeps > 0 && o.half_storage ? NN * 2 : 0);   // BF16 Y (half_storage)
     L.off_xt = take(nn * f);
     L.off_ulow = take(NN * d);
     L.off_bm = take(nn * d);
@@ -163,7 +170,7 @@ struct Small {
     // stream-ordered mode (svd_opts.capture): decisions taken on the device
     int branch;          // SVD_BRANCH_LOW or SVD_BRANCH_SKIP
     int vtaken;          // v_method 1: 1 solve accepted, 3 rejected
-    SweepCtl ctl_low, ctl_work;
+    SweepCtl ctl_low, ctl_work, ctl_half;
 };
 static_assert(sizeof(Small) <= 4096, "small-scalar block");
 
@@ -185,6 +192,7 @@ __global__ void k_branch_decide(Small *sm, double tol_cond, int nsmall_min, doub
     if (forced == SVD_BRANCH_SKIP) skip = true;
     sm->branch = skip ? SVD_BRANCH_SKIP : SVD_BRANCH_LOW;
     sm->ctl_low.stop = skip ? 1 : 0;
+    sm->ctl_half.stop = skip ? 1 : 0;
 }
 
 // Skip branch in the stream-ordered mode: the switch ran on the unrotated
@@ -232,7 +240,8 @@ __global__ void k_write_info(const Small *sm, svd_info *info, int mixed, int wan
     r.v_method_taken = !want_v ? -1 : (vsolve ? sm->vtaken : 0);
     r.orth_vx = vsolve ? (double)sm->orthv : -1.0;
     r.orth_y = diagnostics ? (double)sm->orthy : -1.0;
-    r.fused_fallback = (low && sm->ctl_low.timeout) ? 2 : 0;
+    r.fused_fallback = (low && (sm->ctl_low.timeout || sm->ctl_half.timeout)) ? 2 : 0;
+    r.sweeps_half = low ? sm->ctl_half.sweeps : 0;
     int st = SVD_OK;
     if (!sm->ctl_work.conv) st = SVD_WARN_NOCONV;
     if (sm->nzero) st = SVD_WARN_RANK_DEFICIENT;
@@ -314,6 +323,8 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     if (o.wait_polls < -1) return -12;
     if (o.fused_rounds < -1 || o.fused_rounds > 1) return -12;
     if (o.capture != 0 && o.capture != 1) return -12;
+    if (o.half_sweeps < 0 || o.half_stop_off < 0.0) return -12;
+    if (o.half_storage != 0 && o.half_storage != 1) return -12;
     const bool cap = o.capture != 0;
     // the stream-ordered mode has no host-side clock, and Algorithm 3's
     // route (no triangular factor for V) needs the branch known on the host
@@ -477,7 +488,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
 
     const double eps_low = o.eps_low > 0 ? o.eps_low : sqrt((double)n) * ldexp(1.0, -24);
     const double eps_work = o.eps_work > 0 ? o.eps_work : sqrt((double)n) * ldexp(1.0, -53);
-    int sweeps_low = 0, conv_low = 1, fused_fallback = 0;
+    int sweeps_low = 0, conv_low = 1, fused_fallback = 0, sweeps_half = 0;
     if (branch == SVD_BRANCH_LOW) {
         // a6: FP32 one-sided Jacobi on low(X) (Section 3.2); V_low is only
         // accumulated for switch methods 2 and 3
@@ -487,7 +498,45 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         // products of graded columns stay inside the FP32 range, and every
         // quantity the stage hands on (angles, normalised columns) is
         // invariant under the scale
-        convert_f64_f32(s, N, N, X, N, Y32, N, &sm->lowscale);
+        // three-precision variant (fused round only): the first sweeps form
+        // their Gram blocks on the BF16 matrix cores from Y rounded to BF16
+        // (half_storage 0: Y itself stays FP32), or keep Y in BF16 as well
+        // (half_storage 1: Y widened to FP32 afterwards); then FP32 sweeps
+        const int hmode = o.half_sweeps > 0 ? (o.half_storage ? 2 : 1) : 0;
+        const bool use_half = hmode > 0 && !vlow && fused_low(n, o) && L.b32 == 32 &&
+                              jacobi_fused_ok(N, hmode);
+        unsigned short *Y16 = (unsigned short *)(w + L.off_y16);
+        if (hmode == 2 && use_half)
+            convert_f64_bf16(s, N, N, X, N, Y16, N, &sm->lowscale);
+        else
+            convert_f64_f32(s, N, N, X, N, Y32, N, &sm->lowscale);
+        if (use_half) {
+            jacobi_carve(jw, w + L.off_jac, N, L.b32, (int)sizeof(float));
+            jw.half = hmode;
+            jw.fused = 1;
+            jw.spin = o.wait_polls;
+            jw.off_hist = nullptr;
+            jw.ctl = cap ? &sm->ctl_half : nullptr;
+            jw.stop_off = o.half_stop_off > 0 ? o.half_stop_off : ldexp(1.0, -6);
+            int conv_half = 0;
+            // rotate where the cosine of the columns exceeds the BF16 unit
+            sweeps_half = jacobi_sweeps<float>(s, N, L.b32, hmode == 2 ? (float *)Y16 : Y32, nullptr,
+                                               ldexp(1.0, -8), o.half_sweeps, inner, jw, &conv_half);
+            jw.half = 0;
+            jw.ctl = nullptr;
+            if (sweeps_half == -2) {
+                // a wait ran out: the stage starts from low(X) in FP32 instead
+                (void)hipGetLastError();
+                mpj::g_last_error[0] = 0;
+                fused_fallback = 1;
+                sweeps_half = 0;
+                convert_f64_f32(s, N, N, X, N, Y32, N, &sm->lowscale);
+            } else if (sweeps_half < 0) {
+                return SVD_ERR_HIP;
+            } else if (hmode == 2) {
+                widen_bf16_f32(s, N, N, Y16, N, Y32, N);
+            }
+        }
         if (vlow) {
             set_identity(s, N, Ulow, N);
             convert_f64_f32(s, N, N, Ulow, N, V32, N);
@@ -735,6 +784,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         info->n_y2 = n_y2;
         info->sweeps_y2 = sweeps_y2;
         info->fused_fallback = fused_fallback;
+        info->sweeps_half = sweeps_half;
         int st = SVD_OK;
         if (!conv_work) st = SVD_WARN_NOCONV;
         if (hs.nzero) st = SVD_WARN_RANK_DEFICIENT;

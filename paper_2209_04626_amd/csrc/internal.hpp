@@ -214,7 +214,13 @@ struct JacobiWork {
     int spin = 0;               // polls of the fused round's wait (0 = default,
                                 // < 0 = give up at once, a test hook)
     SweepCtl *ctl = nullptr;    // device: stream-ordered mode (see SweepCtl)
+    int half = 0;               // fused round only: 1 = Gram products on the BF16
+                                // matrix cores; 2 = that, and Y stored in BF16
+                                // (the float pointer passed in is the BF16 array)
 };
+// Whether the fused FP32 round (half: its BF16 variant 1 or 2) runs for N
+// rows and columns on the current device.
+bool jacobi_fused_ok(int N, int half);
 size_t jacobi_scratch_bytes(int N, int b, int elem);
 void jacobi_carve(JacobiWork &j, char *base, int N, int b, int elem);
 // One-sided block-Jacobi sweeps on Y (N x N padded, ld N) with optional V
@@ -255,6 +261,12 @@ void convert_f64_f32(hipStream_t s, int rows, int cols, const double *X, int ldx
 // to about 2^56 (range guard for FP32 copies; see misc.hip)
 void pow2_scale(hipStream_t s, int n, const double *nrm, double *scale);
 void convert_f32_f64(hipStream_t s, int rows, int cols, const float *X, int ldx, double *Y, int ldy);
+// Y16 = bf16(X * scale[0]) (round to nearest even; scale: device, NULL = 1),
+// and Y = fp32(Y16) (exact)
+void convert_f64_bf16(hipStream_t s, int rows, int cols, const double *X, int ldx,
+                      unsigned short *Y, int ldy, const double *scale);
+void widen_bf16_f32(hipStream_t s, int rows, int cols, const unsigned short *Y16, int ld16,
+                    float *Y, int ldy);
 void normalize_f32_to_f64(hipStream_t s, int rows, int cols, const float *Y, int ldy, double *U, int ldu);
 void finalize_sort(hipStream_t s, int n, int N, const double *Y, const double *V,
                    double *sig, int *rank, double *UX, double *VX, double *S, int *nzero,

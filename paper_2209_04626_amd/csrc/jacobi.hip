@@ -750,8 +750,40 @@ __global__ __launch_bounds__(JR_NT, 2) void jac_update_f64(int N, int nblk, int 
 // A wait that runs out sets *err and the workgroup leaves without touching Y;
 // the stage is then invalid and the caller starts it again with the separate
 // kernels.
-template <int B2, int NT, int SPW>
-__global__ __launch_bounds__(NT) void jac_round_f32(int N, int nblk, int r, float *__restrict__ Y,
+// Storage of Y in the fused round: FP32, or BF16 (the upper half of the
+// FP32 bit pattern, rounded to nearest even) for the first sweeps of the
+// three-precision variant.  Four consecutive rows of one column at a time.
+typedef unsigned short bf16_t;
+typedef short sh4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ flt4 ld4(const float *p) { return *(const flt4 *)p; }
+__device__ __forceinline__ flt4 ld4(const bf16_t *p) {
+    const uint2 u = *(const uint2 *)p;
+    return flt4{__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u)};
+}
+__device__ __forceinline__ unsigned bf16_rne(float x) {
+    const unsigned r = __float_as_uint(x);
+    return (r + 0x7fffu + ((r >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ void st4(float *p, flt4 v) { *(flt4 *)p = v; }
+__device__ __forceinline__ void st4(bf16_t *p, flt4 v) {
+    uint2 u;
+    u.x = bf16_rne(v[0]) | (bf16_rne(v[1]) << 16);
+    u.y = bf16_rne(v[2]) | (bf16_rne(v[3]) << 16);
+    *(uint2 *)p = u;
+}
+// FP32 values as the operand of a BF16 MFMA, rounded to nearest even (exact
+// when they are BF16 numbers already)
+__device__ __forceinline__ sh4 as_bf16x4(flt4 v) {
+    return sh4{(short)bf16_rne(v[0]), (short)bf16_rne(v[1]), (short)bf16_rne(v[2]),
+               (short)bf16_rne(v[3])};
+}
+
+// BG: Gram products on the BF16 matrix cores (operands rounded to BF16, FP32
+// sums), the three-precision variant's first sweeps; with ST = bf16_t, Y is
+// stored in BF16 as well.
+template <int B2, int NT, int SPW, typename ST, bool BG>
+__global__ __launch_bounds__(NT) void jac_round_f32(int N, int nblk, int r, void *__restrict__ Yv,
                                                     int ldy, int G, int R, float *__restrict__ gpart,
                                                     int *__restrict__ gflag, int tag, int *flag,
                                                     float *offp, float *smxp, int *rot, double eps,
@@ -780,9 +812,10 @@ __global__ __launch_bounds__(NT) void jac_round_f32(int N, int nblk, int r, floa
     const int r0 = part * R, r1 = min(N, r0 + R);
     const int nstripe = (r1 - r0) / 64;
     if (tid == 0) bad = 0;
+    ST *Y = (ST *)Yv;
     // columns s < KS/2 lie in block I, the others in block J
-    const float *srcI = Y + (size_t)(I * b + 4 * g4) * ldy + r0 + 4 * li;
-    const float *srcJ = Y + (size_t)(J * b - b + 4 * g4) * ldy + r0 + 4 * li;
+    const ST *srcI = Y + (size_t)(I * b + 4 * g4) * ldy + r0 + 4 * li;
+    const ST *srcJ = Y + (size_t)(J * b - b + 4 * g4) * ldy + r0 + 4 * li;
 
     // 1. load this wave's stripes
     flt4 a[SPW][KS];
@@ -792,8 +825,8 @@ __global__ __launch_bounds__(NT) void jac_round_f32(int N, int nblk, int r, floa
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             const int co = 16 * (s / 4) + (s % 4);
-            const float *src = (s < KS / 2 ? srcI : srcJ) + (size_t)co * ldy + 64 * st;
-            a[i][s] = st < nstripe ? *(const flt4 *)src : flt4{0, 0, 0, 0};
+            const ST *src = (s < KS / 2 ? srcI : srcJ) + (size_t)co * ldy + 64 * st;
+            a[i][s] = st < nstripe ? ld4(src) : flt4{0, 0, 0, 0};
         }
     }
 
@@ -819,13 +852,27 @@ __global__ __launch_bounds__(NT) void jac_round_f32(int N, int nblk, int r, floa
                 flt4 v[NTT];
 #pragma unroll
                 for (int h = 0; h < NTT; ++h) v[h] = *(const flt4 *)(tr + (16 * h + li) * LDT + 16 * u + 4 * g4);
+                if constexpr (BG) {
+                    // one 16x16x16 BF16 product (FP32 sums) per tile and 16
+                    // rows; lane (g, i) supplies k = 4 g .. 4 g + 3
+                    sh4 vb[NTT];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
+                    for (int h = 0; h < NTT; ++h) vb[h] = as_bf16x4(v[h]);
                     int q = 0;
 #pragma unroll
                     for (int ta = 0; ta < NTT; ++ta)
 #pragma unroll
-                        for (int tc = ta; tc < NTT; ++tc, ++q) acc[q] = mfma16(v[ta][t], v[tc][t], acc[q]);
+                        for (int tc = ta; tc < NTT; ++tc, ++q)
+                            acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(vb[ta], vb[tc], acc[q], 0, 0, 0);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        int q = 0;
+#pragma unroll
+                        for (int ta = 0; ta < NTT; ++ta)
+#pragma unroll
+                            for (int tc = ta; tc < NTT; ++tc, ++q) acc[q] = mfma16(v[ta][t], v[tc][t], acc[q]);
+                    }
                 }
             }
         }
@@ -942,8 +989,8 @@ __global__ __launch_bounds__(NT) void jac_round_f32(int N, int nblk, int r, floa
 
     // 7. update from registers: [Y_I Y_J]^T <- W^T [Y_I Y_J]^T per stripe; the
     // output tile ti holds columns 16 ti + 4 g + e, rows 4 l + t
-    float *dstI = Y + (size_t)(I * b + 4 * g4) * ldy + r0 + 4 * li;
-    float *dstJ = Y + (size_t)(J * b - b + 4 * g4) * ldy + r0 + 4 * li;
+    ST *dstI = Y + (size_t)(I * b + 4 * g4) * ldy + r0 + 4 * li;
+    ST *dstJ = Y + (size_t)(J * b - b + 4 * g4) * ldy + r0 + 4 * li;
 #pragma unroll
     for (int ti = 0; ti < NTI; ++ti) {
         float wr[KS];
@@ -960,10 +1007,9 @@ __global__ __launch_bounds__(NT) void jac_round_f32(int N, int nblk, int r, floa
             for (int s = 0; s < KS; ++s)
 #pragma unroll
                 for (int t = 0; t < 4; ++t) o[t] = mfma16(wr[s], a[i][s][t], o[t]);
-            float *dst = (ti < NTI / 2 ? dstI : dstJ) + (size_t)(16 * ti) * ldy + 64 * st;
+            ST *dst = (ti < NTI / 2 ? dstI : dstJ) + (size_t)(16 * ti) * ldy + 64 * st;
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                *(flt4 *)(dst + (size_t)e * ldy) = flt4{o[0][e], o[1][e], o[2][e], o[3][e]};
+            for (int e = 0; e < 4; ++e) st4(dst + (size_t)e * ldy, flt4{o[0][e], o[1][e], o[2][e], o[3][e]});
         }
     }
 }
@@ -1061,7 +1107,7 @@ __global__ void jac_fill_zero(int *p, int n) {
 }
 
 // ---------------------------------------------------------------- fused FP32 rounds
-typedef void (*RoundFn)(int, int, int, float *, int, int, int, float *, int *, int, int *, float *,
+typedef void (*RoundFn)(int, int, int, void *, int, int, int, float *, int *, int, int *, float *,
                         float *, int *, double, int, int, int, int *, const int *);
 
 struct FusedCfg {
@@ -1072,7 +1118,7 @@ struct FusedCfg {
 // Workgroups of `fn` the current device holds at once (compute units times
 // the kernel's occupancy per unit), cached per device and variant.
 static int round_capacity(int variant, RoundFn fn, int nt) {
-    static std::atomic<int> cap[64][3];
+    static std::atomic<int> cap[64][9];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
         (void)hipGetLastError();
@@ -1094,7 +1140,8 @@ static int round_capacity(int variant, RoundFn fn, int nt) {
 // The fused round needs every workgroup of a pair slot resident at once (they
 // wait for each other's partial Gram blocks): the whole grid must fit on the
 // device, one pair slot's rows split over G workgroups of at most 16 stripes.
-static bool fused_config(int N, int B2, FusedCfg *fc) {
+// half: 0 FP32, 1 BF16 Gram products, 2 BF16 Gram products and BF16 storage
+static bool fused_config(int N, int B2, FusedCfg *fc, int half = 0) {
     if (B2 != 64 || N % 64 != 0) return false;
     const int npairs = N / B2;
     int ncu = 0, dev = 0;
@@ -1110,10 +1157,23 @@ static bool fused_config(int N, int B2, FusedCfg *fc) {
     const int stripes = R / 64;
     int variant, nt;
     RoundFn fn;
-    if (stripes <= 4) { variant = 0; nt = 256; fn = jac_round_f32<64, 256, 1>; }
-    else if (stripes <= 8) { variant = 1; nt = 256; fn = jac_round_f32<64, 256, 2>; }
-    else if (stripes <= 16) { variant = 2; nt = 512; fn = jac_round_f32<64, 512, 2>; }
+    if (stripes <= 4) { variant = 0; nt = 256; fn = jac_round_f32<64, 256, 1, float, false>; }
+    else if (stripes <= 8) { variant = 1; nt = 256; fn = jac_round_f32<64, 256, 2, float, false>; }
+    else if (stripes <= 16) { variant = 2; nt = 512; fn = jac_round_f32<64, 512, 2, float, false>; }
     else return false;
+    if (half == 1) {
+        const RoundFn hf[3] = {jac_round_f32<64, 256, 1, float, true>,
+                               jac_round_f32<64, 256, 2, float, true>,
+                               jac_round_f32<64, 512, 2, float, true>};
+        fn = hf[variant];
+        variant += 3;
+    } else if (half == 2) {
+        const RoundFn hf[3] = {jac_round_f32<64, 256, 1, bf16_t, true>,
+                               jac_round_f32<64, 256, 2, bf16_t, true>,
+                               jac_round_f32<64, 512, 2, bf16_t, true>};
+        fn = hf[variant];
+        variant += 6;
+    }
     if (npairs * G > JF_MAX_WG || npairs * G > round_capacity(variant, fn, nt)) return false;
     fc->G = G; fc->R = R; fc->nt = nt; fc->fn = fn;
     return true;
@@ -1147,7 +1207,10 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
     std::vector<float> hoff(npairs), hsmx(npairs);
     // one rotated pair in the update: its 2b columns of Y (and V) read and
     // written once, 2 N (2b)^2 flops per matrix
-    const double pair_upd_bytes = 2.0 * N * B2 * sizeof(T) * (V ? 2 : 1);
+    // (element size: FP32, FP64, or BF16 for the fused round's BF16 sweeps)
+    const bool half = fc && jw.half;
+    const double Es = (fc && jw.half == 2) ? 2.0 : (double)sizeof(T);
+    const double pair_upd_bytes = 2.0 * N * B2 * Es * (V ? 2 : 1);
     const double pair_upd_flops = 2.0 * N * B2 * B2 * (V ? 2 : 1);
     std::vector<std::pair<size_t, int>> round_slots;   // clocked fused launches (slot, round)
     // stream-ordered mode: every sweep is enqueued and stops on the device
@@ -1166,7 +1229,7 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
         if (e != hipSuccess) { note_hip_error(e, "jacobi flag reset"); return -1; }
         // kernel-class ids for the optional per-launch clock
         const int kbase = sizeof(T) == 4 ? 0 : 3;
-        const double E = sizeof(T);
+        const double E = Es;
         // algorithmic work per round: the Gram blocks read Y once and cost
         // N (2b)^2 flops per pair for the symmetric product; the update reads
         // and writes Y (and V) once and costs 2 N (2b)^2 flops per pair and
@@ -1189,16 +1252,16 @@ static int sweeps_impl(hipStream_t s, int N, int ncols, T *Y, T *V, double eps, 
                     const int tag = 1 + sw * (nblk - 1) + r;
                     const int spin = jw.spin == 0 ? JF_SPIN : jw.spin;
                     const dim3 grid(npairs * fc->G), blk(fc->nt);
-                    const bool clk = jw.kc && jw.kc->slot(SVD_K_ROUND32, gram_bytes,
+                    const bool clk = jw.kc && jw.kc->slot(half ? SVD_K_ROUND16 : SVD_K_ROUND32, gram_bytes,
                                                           gram_flops + inner_flops, &e0, &e1);
                     if (clk) {
                         round_slots.push_back({jw.kc->used / 2 - 1, r});
-                        hipExtLaunchKernelGGL(fc->fn, grid, blk, 0, s, e0, e1, 0, N, nblk, r, (float *)Y,
+                        hipExtLaunchKernelGGL(fc->fn, grid, blk, 0, s, e0, e1, 0, N, nblk, r, (void *)Y,
                                               N, fc->G, fc->R, jw.gpart, jw.gflag, tag, jw.flag, jw.offp,
                                               jw.smxp, jw.rotmap + (size_t)r * npairs, eps, max_inner,
                                               cross, spin, jw.flag + 1, stop);
                     } else {
-                        hipLaunchKernelGGL(fc->fn, grid, blk, 0, s, N, nblk, r, (float *)Y, N, fc->G,
+                        hipLaunchKernelGGL(fc->fn, grid, blk, 0, s, N, nblk, r, (void *)Y, N, fc->G,
                                            fc->R, jw.gpart, jw.gflag, tag, jw.flag, jw.offp, jw.smxp,
                                            jw.rotmap + (size_t)r * npairs, eps, max_inner, cross, spin,
                                            jw.flag + 1, stop);
@@ -1326,8 +1389,12 @@ int jacobi_sweeps_cols(hipStream_t s, int N, int ncols, int b, T *Y, T *V, doubl
     }
     if constexpr (sizeof(T) == 4) {
         FusedCfg fc;
-        if (jw.fused && !V && b == 32 && ncols == N && fused_config(N, 64, &fc))
+        if (jw.fused && !V && b == 32 && ncols == N && fused_config(N, 64, &fc, jw.half))
             return sweeps_impl<T, 64, 256>(s, N, ncols, Y, V, eps, maxsweep, max_inner, jw, conv, &fc);
+    }
+    if (jw.half) {
+        note_hip_error(hipErrorInvalidValue, "jacobi_sweeps_cols: BF16 sweeps need the fused round");
+        return -1;
     }
     if (b == 16) return sweeps_impl<T, 32, 256>(s, N, ncols, Y, V, eps, maxsweep, max_inner, jw, conv);
     // 64-wide FP64 blocks: 512 threads shorten each round's per-thread work
@@ -1335,6 +1402,11 @@ int jacobi_sweeps_cols(hipStream_t s, int N, int ncols, int b, T *Y, T *V, doubl
     if (sizeof(T) == 8)
         return sweeps_impl<T, 64, 512>(s, N, ncols, Y, V, eps, maxsweep, max_inner, jw, conv);
     return sweeps_impl<T, 64, 256>(s, N, ncols, Y, V, eps, maxsweep, max_inner, jw, conv);
+}
+
+bool jacobi_fused_ok(int N, int half) {
+    FusedCfg fc;
+    return fused_config(N, 64, &fc, half);
 }
 
 template <typename T>

@@ -249,6 +249,37 @@ void pow2_scale(hipStream_t s, int n, const double *nrm, double *scale) {
     hipLaunchKernelGGL(k_pow2_scale, dim3(1), dim3(256), 0, s, n, nrm, scale);
 }
 
+// BF16 copies for the three-precision variant: Y16 = bf16(X * scale[0])
+// (round to nearest even), and the exact widening back to FP32.
+__device__ __forceinline__ unsigned short f32_to_bf16(float x) {
+    const unsigned r = __float_as_uint(x);
+    return (unsigned short)((r + 0x7fffu + ((r >> 16) & 1u)) >> 16);
+}
+__global__ void k_f64_bf16(int rows, int cols, const double *X, int ldx, unsigned short *Y, int ldy,
+                           const double *scale) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)rows * cols) return;
+    const int i = (int)(e % rows), j = (int)(e / rows);
+    const double f = scale ? *scale : 1.0;
+    Y[(size_t)j * ldy + i] = f32_to_bf16((float)(X[(size_t)j * ldx + i] * f));
+}
+void convert_f64_bf16(hipStream_t s, int rows, int cols, const double *X, int ldx, unsigned short *Y,
+                      int ldy, const double *scale) {
+    hipLaunchKernelGGL(k_f64_bf16, grid1((size_t)rows * cols), dim3(256), 0, s, rows, cols, X, ldx, Y,
+                       ldy, scale);
+}
+__global__ void k_bf16_f32(int rows, int cols, const unsigned short *Y16, int ld16, float *Y, int ldy) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)rows * cols) return;
+    const int i = (int)(e % rows), j = (int)(e / rows);
+    Y[(size_t)j * ldy + i] = __uint_as_float((unsigned)Y16[(size_t)j * ld16 + i] << 16);
+}
+void widen_bf16_f32(hipStream_t s, int rows, int cols, const unsigned short *Y16, int ld16, float *Y,
+                    int ldy) {
+    hipLaunchKernelGGL(k_bf16_f32, grid1((size_t)rows * cols), dim3(256), 0, s, rows, cols, Y16, ld16,
+                       Y, ldy);
+}
+
 __global__ void k_f32_f64(int rows, int cols, const float *X, int ldx, double *Y, int ldy) {
     const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (size_t)rows * cols) return;
