@@ -138,7 +138,12 @@ typedef struct {
                               the QR of X^T U_X followed by FP64 sweeps with
                               accumulation (the mixed path's default) */
     int diagnostics;       /* 1: also measure svd_info.orth_y (one more FP64
-                              Gram product); 0 (default): skip */
+                              Gram product); 2: that, and leave a copy of Y
+                              as the FP64 sweeps start (after the switch,
+                              before the Y2 safeguard; n x n, ld = n rounded
+                              up to a multiple of 64) in the workspace at
+                              byte offset svd_diag_y_offset(); 0 (default):
+                              skip */
     double tol_vsolve;     /* acceptance bound of v_method 1; 0 -> n 2^-50 */
     int inner_pairs;       /* pairs rotated in a block pair's inner solve:
                               0 (default): all pairs of its 2b columns in the
@@ -295,6 +300,11 @@ void svd_default_opts(svd_opts *o, int mixed);
 /* Bytes of device workspace svd_plain / svd_mixed need for an m x n problem
    with options o (NULL = defaults).  Returns 0 for invalid sizes. */
 size_t svd_workspace_size(int m, int n, const svd_opts *o);
+
+/* Byte offset in the workspace of the copy of Y that diagnostics = 2 leaves
+   (the switch study of Section 6); 0 when o->diagnostics != 2 or the sizes
+   are invalid. */
+size_t svd_diag_y_offset(int m, int n, const svd_opts *o);
 
 /*
  * svd_plain: Algorithm 2 (preconditioned one-sided Jacobi) in FP64:

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libmpjsvd.so")
 TUNE_PATH = os.path.join(_HERE, "tune_gfx950.json")
 
 EXPORTS = [
-    "svd_default_opts", "svd_workspace_size", "svd_plain", "svd_mixed",
+    "svd_default_opts", "svd_workspace_size", "svd_diag_y_offset", "svd_plain", "svd_mixed",
     "svd_batched_plan_create", "svd_batched", "svd_batched_plan_destroy",
     "svd_backward_workspace_size", "svd_backward", "svd_backward_noalloc",
     "svd_status_string", "svd_last_error",
@@ -146,6 +146,8 @@ def load():
     lib.svd_default_opts.restype = None
     lib.svd_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(SvdOpts)]
     lib.svd_workspace_size.restype = ctypes.c_size_t
+    lib.svd_diag_y_offset.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(SvdOpts)]
+    lib.svd_diag_y_offset.restype = ctypes.c_size_t
     for fn in (lib.svd_plain, lib.svd_mixed):
         fn.argtypes = [ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp,
                        ctypes.c_int, _vp, ctypes.c_size_t, ctypes.POINTER(SvdOpts),

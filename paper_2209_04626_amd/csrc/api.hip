@@ -72,7 +72,7 @@ struct Layout {
     size_t off_atall, off_tau0, off_t0, off_a1, off_wp, off_nrm2, off_piv, off_a1p, off_tau1,
         off_t1, off_rt, off_tau2, off_t2, off_x, off_y, off_vacc, off_y32, off_xt, off_ulow, off_bm,
         off_tau3, off_t3, off_ux, off_vx, off_sig, off_rank, off_nrmx, off_small, off_qr, off_jac,
-        off_v32, off_v2, off_idx, off_y16, total;
+        off_v32, off_v2, off_idx, off_y16, off_ydiag, total;
 };
 
 // Whether the FP32 stage asks for the fused round (it still falls back to
@@ -132,6 +132,7 @@ Layout layout(int m, int n, const svd_opts &o) {
     L.off_y32 = take(NN * f);
     L.off_v32 = take(o.switch_method >= 2 ? NN * f : 0);   // V_low for switch methods 2 and 3
     L.off_y16 = take(o.half_sweeps > 0 && o.half_storage ? NN * 2 : 0);   // BF16 Y (half_storage)
+    L.off_ydiag = take(o.diagnostics == 2 ? NN * d : 0);     // copy of Y for the switch study
     L.off_xt = take(nn * f);
     L.off_ulow = take(NN * d);
     L.off_bm = take(nn * d);
@@ -325,6 +326,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     if (o.capture != 0 && o.capture != 1) return -12;
     if (o.half_sweeps < 0 || o.half_stop_off < 0.0) return -12;
     if (o.half_storage != 0 && o.half_storage != 1) return -12;
+    if (o.diagnostics < 0 || o.diagnostics > 2) return -12;
     const bool cap = o.capture != 0;
     // the stream-ordered mode has no host-side clock, and Algorithm 3's
     // route (no triangular factor for V) needs the branch known on the host
@@ -620,6 +622,9 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
     int n_y2 = 0, sweeps_y2 = 0;
     // (the safeguard picks Y2 on the host: not in the stream-ordered mode)
     const bool y2check = o.y2_safeguard && branch == SVD_BRANCH_LOW && n >= 2 && !cap;
+    if (o.diagnostics == 2)
+        MPJ_CHECK(hipMemcpyAsync(w + L.off_ydiag, Y, (size_t)N * N * sizeof(double),
+                                 hipMemcpyDeviceToDevice, s));
     if (o.diagnostics && !y2check) {
         // how far the columns of Y are from orthogonal when the FP64 sweeps start
         normalize_cols64(s, n, n, Y, N, Ulow, N);
@@ -796,6 +801,11 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
 }
 
 } // namespace
+
+extern "C" size_t svd_diag_y_offset(int m, int n, const svd_opts *op) {
+    if (!op || op->diagnostics != 2 || m < 0 || n <= 0 || n > m) return 0;
+    return layout(m, n, *op).off_ydiag;
+}
 
 extern "C" size_t svd_workspace_size(int m, int n, const svd_opts *op) {
     if (m < 0 || n < 0 || n > m) return 0;
