@@ -124,6 +124,8 @@ constexpr int QR_RC = 256;   // rows per workgroup in the panel kernels
 struct QRScratch {
     double *part;   // 2 * max_groups * QR_NB
     double *head;   // 2 * QR_NB
+    unsigned long long *tpart;   // one-launch panel: tagged sums, 2 * 2 * max_groups * QR_NB words
+    unsigned long long *thead;   // and the tagged head row, 2 * 2 * QR_NB words
     double *vtv;    // max_groups * QR_NB * QR_NB
     double *vb;     // m * QR_NB     (explicit unit-lower block of reflectors)
     double *vbo;    // m * QR_NBO    (the same for an outer block)

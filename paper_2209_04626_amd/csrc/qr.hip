@@ -160,15 +160,57 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_step(int j, int mp, int nb, in
 // The whole panel in one launch (at most QR_COOP_MAXG workgroups, all
 // resident at once): thread t of workgroup g keeps row g*QR_RC + t of the
 // panel in registers for all nb columns.  For column j every workgroup
-// reduces its rows' products a_ij a_ik (i > j) in LDS, publishes the sums
-// (and workgroup 0 the head row j), then waits until every workgroup has
-// published step j; all workgroups add the sums in the same order, so they
-// build the same reflector, and apply it to their rows.  The sums, the head
-// row and the flags (raised to base + j + 1) go through device-coherent
-// stores and loads; waiting is a bounded poll.  A wait that runs out poisons
-// tau[j] with NaN instead of hanging.
+// reduces its rows' products a_ij a_ik (i > j) in LDS and publishes the sums
+// (and workgroup 0 the head row j); every workgroup then reads all of them,
+// adds them in the same order, so that all build the same reflector, and
+// applies it to its rows.
+//
+// Each published FP64 value travels as two 64-bit words, (tag << 32) | half,
+// written and read with device-coherent (relaxed, agent-scope) atomics.  A
+// 64-bit atomic is seen whole or not at all, so a reader that finds the
+// column's tag (base + j + 1) in both words has the value: no flag, no
+// store-completion wait, one memory round trip per column.  Reading is a
+// bounded poll; a wait that runs out poisons tau[j] with NaN instead of
+// hanging.  Tags are unique within one factorisation (the words are cleared
+// before each one), and a workgroup cannot overwrite a buffer of column j + 2
+// before every workgroup has read column j (it first needs their column
+// j + 1 values).
 constexpr int QR_COOP_MAXG = 256;
 constexpr int QR_COOP_SPIN = 1 << 22;
+
+__device__ __forceinline__ void tag_store(unsigned long long *p, double v, unsigned tag) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long t = (unsigned long long)tag << 32;
+    coh_store(p, t | (b & 0xffffffffull));
+    coh_store(p + 1, t | (b >> 32));
+}
+
+// Up to K tagged values at once, those whose bit is set in `mask` (all
+// loads of a pass in flight together); false if the bounded poll ran out
+// (spin < 0: give up at once when there is anything to wait for).
+template <int K>
+__device__ __forceinline__ bool tag_load(const unsigned long long *const (&p)[K], unsigned mask,
+                                         unsigned tag, int spin, double (&v)[K]) {
+    if (mask == 0) return true;
+    if (spin < 0) return false;
+    int it = 0;
+    for (;;) {
+        unsigned long long w0[K], w1[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (mask & (1u << i)) { w0[i] = coh_load(p[i]); w1[i] = coh_load(p[i] + 1); }
+        bool ok = true;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (mask & (1u << i)) {
+                ok = ok && (unsigned)(w0[i] >> 32) == tag && (unsigned)(w1[i] >> 32) == tag;
+                v[i] = __longlong_as_double((long long)((w1[i] << 32) | (w0[i] & 0xffffffffull)));
+            }
+        if (ok) return true;
+        if (++it > spin) return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
 
 struct CoopShared {
     double red[QR_RC * (QR_NB + 1)];
@@ -181,8 +223,8 @@ struct CoopShared {
 // row stays in registers).
 template <int J>
 __device__ __forceinline__ void coop_column(double (&a)[QR_NB], CoopShared &sh, int mp, int nb,
-                                            double *part, double *head, double *tau, int *flags,
-                                            int base, int spin) {
+                                            unsigned long long *tpart, unsigned long long *thead,
+                                            double *tau, int base, int spin) {
     if (J >= nb) return;
     constexpr int GR = QR_RC / QR_NB;
     const int G = gridDim.x;
@@ -203,41 +245,58 @@ __device__ __forceinline__ void coop_column(double (&a)[QR_NB], CoopShared &sh, 
         sh.s8[q * QR_NB + k] = sacc;
     }
     __syncthreads();
-    double *po = part + (size_t)(J & 1) * G * QR_NB;
-    double *ho = head + (J & 1) * QR_NB;
-    if (t < QR_NB) {
-        double sacc = 0.0;
+    // 2. publish this workgroup's sums and (workgroup 0) the head row, tagged;
+    // every thread of column k keeps this workgroup's own sum for step 3
+    const unsigned tag = (unsigned)(base + J + 1);
+    unsigned long long *po = tpart + (size_t)(J & 1) * G * QR_NB * 2;
+    unsigned long long *ho = thead + (size_t)(J & 1) * QR_NB * 2;
+    double own = 0.0;
+    {
+        const int k = t % QR_NB;
 #pragma unroll
-        for (int q = 0; q < GR; ++q) sacc += sh.s8[q * QR_NB + t];
-        coh_store(po + (size_t)g * QR_NB + t, sacc);
+        for (int q = 0; q < GR; ++q) own += sh.s8[q * QR_NB + k];
     }
+    if (t < QR_NB) tag_store(po + ((size_t)g * QR_NB + t) * 2, own, tag);
+    // (the head row goes out from 32 threads after the barrier: one thread
+    // issuing its 64 stores held every other workgroup back)
     if (g == 0 && t == J) {
 #pragma unroll
-        for (int k = 0; k < QR_NB; ++k) coh_store(ho + k, a[k]);
-    }
-    // 2. publish (stores complete, then the flag), then wait for every
-    // workgroup's column J
-    publish_fence();
-    __syncthreads();
-    if (t == 0) coh_store(flags + g, base + J + 1);
-    // (a workgroup's own flag needs no wait; spin < 0 gives up on every
-    // other workgroup at once, a test hook for the time-out path)
-    if (t < G && t != g) {
-        int it = 0;
-        while (spin < 0 || coh_load(flags + t) < base + J + 1) {
-            if (spin < 0 || ++it > spin) { sh.bad = 1; break; }
-            __builtin_amdgcn_s_sleep(1);
-        }
+        for (int k = 0; k < QR_NB; ++k) sh.H[k] = a[k];
     }
     __syncthreads();
-    // 3. sums over workgroups in a fixed order, and the head row
+    if (g == 0 && t < QR_NB) tag_store(ho + 2 * t, sh.H[t], tag);
+    // 3. every workgroup's sums of column J, added in workgroup order (the
+    // own one from registers), and the head row; up to four values per pass
+    // with their loads in flight together
     {
-        const double *pi = part + (size_t)(J & 1) * G * QR_NB;
         const int k = t % QR_NB, q0 = t / QR_NB;
         double sacc = 0.0;
-        for (int q = q0; q < G; q += GR) sacc += coh_load(pi + (size_t)q * QR_NB + k);
+        bool ok = true;
+        for (int qb = q0; qb < G; qb += 4 * GR) {
+            const unsigned long long *pp[4];
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            unsigned mask = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int q = qb + i * GR;
+                pp[i] = po + ((size_t)(q < G ? q : 0) * QR_NB + k) * 2;
+                if (q < G && q != g) mask |= 1u << i;
+            }
+            ok = ok && tag_load<4>(pp, mask, tag, spin, v);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int q = qb + i * GR;
+                if (q < G) sacc += q == g ? own : v[i];
+            }
+        }
         sh.s8[q0 * QR_NB + k] = sacc;
-        if (t < QR_NB) sh.H[t] = coh_load(head + (J & 1) * QR_NB + t);
+        if (g != 0 && t < QR_NB) {
+            const unsigned long long *hp[1] = {ho + 2 * t};
+            double hv[1] = {0.0};
+            ok = ok && tag_load<1>(hp, 1u, tag, spin, hv);
+            sh.H[t] = hv[0];
+        }
+        if (!ok) sh.bad = 1;
     }
     __syncthreads();
     if (t < QR_NB) {
@@ -268,10 +327,10 @@ __device__ __forceinline__ void coop_column(double (&a)[QR_NB], CoopShared &sh, 
 
 template <int... J>
 __device__ __forceinline__ void coop_columns(std::integer_sequence<int, J...>, double (&a)[QR_NB],
-                                             CoopShared &sh, int mp, int nb, double *part,
-                                             double *head, double *tau, int *flags, int base,
-                                             int spin) {
-    (coop_column<J>(a, sh, mp, nb, part, head, tau, flags, base, spin), ...);
+                                             CoopShared &sh, int mp, int nb,
+                                             unsigned long long *tpart, unsigned long long *thead,
+                                             double *tau, int base, int spin) {
+    (coop_column<J>(a, sh, mp, nb, tpart, thead, tau, base, spin), ...);
 }
 
 // After the last column: G = V^T V of the panel, each workgroup's rows on
@@ -282,7 +341,8 @@ __device__ __forceinline__ void coop_columns(std::integer_sequence<int, J...>, d
 // solves column j of the inverse of diag(1/tau) + striu(G)).  No workgroup
 // waits for workgroup 0, so this adds one wait, not a round trip.
 __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P, int ld,
-                                                      double *part, double *head, double *tau,
+                                                      unsigned long long *tpart,
+                                                      unsigned long long *thead, double *tau,
                                                       int *flags, int base, double *Vb,
                                                       double *Gpart, double *T, int ldt, int *err,
                                                       int spin) {
@@ -293,8 +353,8 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
 #pragma unroll
     for (int k = 0; k < QR_NB; ++k) a[k] = (live && k < nb) ? P[(size_t)k * ld + i] : 0.0;
     if (threadIdx.x == 0) sh.bad = 0;
-    coop_columns(std::make_integer_sequence<int, QR_NB>{}, a, sh, mp, nb, part, head, tau, flags,
-                 base, spin);
+    coop_columns(std::make_integer_sequence<int, QR_NB>{}, a, sh, mp, nb, tpart, thead, tau, base,
+                 spin);
 #pragma unroll
     for (int k = 0; k < QR_NB; ++k)
         if (live && k < nb) P[(size_t)k * ld + i] = a[k];
@@ -368,9 +428,13 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
     }
 }
 
-__global__ void qr_flags_zero(int n, int *flags) {
+// Clears the one-launch panel's flags and tagged words before a factorisation.
+__global__ void qr_flags_zero(int n, int *flags, int nt, unsigned long long *tp, int nh,
+                              unsigned long long *th) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < n) flags[e] = 0;
+    if (e < nt) tp[e] = 0ull;
+    if (e < nh) th[e] = 0ull;
 }
 
 // T (nb x nb upper, zeros below, ld ldt) of the compact-WY form
@@ -432,7 +496,8 @@ size_t qr_scratch_doubles(int m, int ncols_max, size_t *split_elems) {
     const int G = cdiv(m, QR_RC);
     const size_t se = (size_t)8 * QR_NBO * (size_t)ncols_max;
     if (split_elems) *split_elems = se;
-    return (size_t)2 * G * QR_NB + 2 * QR_NB + (size_t)G * QR_NB * QR_NB + (size_t)m * QR_NB +
+    return (size_t)2 * G * QR_NB + 2 * QR_NB + (size_t)4 * G * QR_NB + 4 * QR_NB +
+           (size_t)G * QR_NB * QR_NB + (size_t)m * QR_NB +
            (size_t)m * QR_NBO + (size_t)QR_NBO * QR_NBO + (size_t)QR_NB * QR_NB +
            2 * (size_t)QR_NBO * ncols_max + se + (size_t)(G + 63) / 2 + 128;
 }
@@ -444,6 +509,8 @@ void qr_scratch_carve(QRScratch &q, double *base, int m, int ncols_max) {
     double *p = base;
     q.part = p; p += (size_t)2 * G * QR_NB;
     q.head = p; p += 2 * QR_NB;
+    q.tpart = (unsigned long long *)p; p += (size_t)4 * G * QR_NB;
+    q.thead = (unsigned long long *)p; p += 4 * QR_NB;
     q.vtv = p; p += (size_t)G * QR_NB * QR_NB;
     q.vb = p; p += (size_t)m * QR_NB;
     q.vbo = p; p += (size_t)m * QR_NBO;
@@ -498,7 +565,7 @@ static void panel_factor(hipStream_t s, int mp, int nb, double *P, int ld, doubl
         // algorithmic work: the panel read and written once, 2 mp nb^2 flops
         if (q.kc) q.kc->begin(s, 7, 2.0 * mp * nb * sizeof(double), 2.0 * mp * nb * nb);
         // the panel, its explicit V and its T in one launch
-        hipLaunchKernelGGL(qr_panel_coop, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.part, q.head,
+        hipLaunchKernelGGL(qr_panel_coop, dim3(G), dim3(QR_RC), 0, s, mp, nb, P, ld, q.tpart, q.thead,
                            tau, q.flags, panel * 64, q.vb, q.vtv, T, ldt, q.err,
                            q.spin == 0 ? QR_COOP_SPIN : q.spin);
         if (q.kc) q.kc->end(s);
@@ -535,8 +602,11 @@ static void apply_block(hipStream_t s, bool transT, int mp, int nb, const double
 void qr_factor(hipStream_t s, int m, int n, double *A, int lda, double *tau, double *Tall,
                QRScratch &q) {
     const int gmax = cdiv(m, QR_RC);
-    if (gmax <= QR_COOP_MAXG)
-        hipLaunchKernelGGL(qr_flags_zero, dim3(cdiv(gmax, 256)), dim3(256), 0, s, gmax, q.flags);
+    if (gmax <= QR_COOP_MAXG) {
+        const int nt = 4 * gmax * QR_NB;   // tagged sums of both column parities
+        hipLaunchKernelGGL(qr_flags_zero, dim3(cdiv(nt, 256)), dim3(256), 0, s, gmax, q.flags, nt,
+                           q.tpart, 4 * QR_NB, q.thead);
+    }
     int panel = 0;
     for (int c0o = 0, ob = 0; c0o < n; c0o += QR_NBO, ++ob) {
         const int nbo = min(QR_NBO, n - c0o);
