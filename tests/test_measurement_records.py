@@ -37,7 +37,8 @@ def test_traffic_records_exist_and_name_their_sources():
         for src in sources:
             assert os.path.exists(os.path.join(ROOT, src)), (kernel, src)
         # the command that produced the record is part of the record
-        text = open(path).read()
+        with open(path) as fh:
+            text = fh.read()
         assert "rocprofv3 --pmc FETCH_SIZE" in text and "rocprofv3 --pmc WRITE_SIZE" in text, kernel
 
 
