@@ -95,3 +95,26 @@ def test_autograd_function_large_matrices(lib):
         ref = (U[b].detach().cpu().numpy() * gs[b]) @ V[b].detach().cpu().numpy().T
         assert np.allclose(A.grad[b].cpu().numpy(), ref, atol=1e-12)
         assert np.allclose(S[b].detach().cpu().numpy(), np.linspace(4.0, 0.5, 24), rtol=1e-13)
+
+
+@pytest.mark.parametrize("gap", [1e-6, 1e-13, 0.0])
+def test_backward_near_degenerate_guard(lib, gap):
+    """Two singular values a relative gap apart (1e-6: the guard inactive;
+    1e-13: s_j^2 - s_i^2 of the order of the guard's eta = 1e-12 s_1^2; 0: an
+    exact pair), the kernel against the FP64 formula on the GPU's own forward
+    outputs, with the guard in both, at the gradient gate."""
+    import torch
+    print(f"case backward near-degenerate gap={gap}", flush=True)
+    rng = np.random.default_rng(21)
+    m, n = 40, 12
+    s = np.linspace(2.0, 0.4, n)
+    s[1] = s[0] * (1.0 - gap)
+    A = testmats.compose(testmats.haar(rng, m, n), s, testmats.haar(rng, n, n))
+    U, S, V, _ = lib.svd(torch.from_numpy(A).cuda(), "mixed")
+    gU, gS, gV = rng.standard_normal((m, n)), rng.standard_normal(n), rng.standard_normal((n, n))
+    gA = lib.svd_backward(U[None], S[None], V[None], torch.from_numpy(gU).cuda()[None],
+                          torch.from_numpy(gS).cuda()[None], torch.from_numpy(gV).cuda()[None])
+    gA = gA[0].cpu().numpy()
+    ref = oracle.svd_backward_ref(U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy(), gU, gS, gV)
+    assert np.all(np.isfinite(gA))
+    assert np.linalg.norm(gA - ref) <= 1e-8 * np.linalg.norm(ref), (np.linalg.norm(gA - ref), np.linalg.norm(ref))

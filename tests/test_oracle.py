@@ -390,6 +390,50 @@ def test_adjoint_matches_high_precision_derivative():
     assert abs(float(d) - np.sum(gA * E)) <= 1e-10 * max(1.0, abs(float(d)))
 
 
+def test_adjoint_square_diagonal_by_hand():
+    """A = diag(d), d distinct, positive and descending: U = V = I and S = d
+    (the sign rule keeps the identity).  First-order perturbation of the SVD
+    at a diagonal matrix (differentiate A = U S V^T with U^T dU and V^T dV
+    antisymmetric): dS_i = E_ii, (U^T dU)_ij = (s_j E_ij + s_i E_ji) /
+    (s_j^2 - s_i^2), (V^T dV)_ij = (s_i E_ij + s_j E_ji) / (s_j^2 - s_i^2).
+    Collecting the coefficient of E_ij in <gU, dU> + <gs, dS> + <gV, dV>:
+    gA_ii = gs_i and, for i != j,
+    gA_ij = (s_j (gU_ij - gU_ji) + s_i (gV_ij - gV_ji)) / (s_j^2 - s_i^2)."""
+    rng = np.random.default_rng(4)
+    n = 5
+    d = np.array([3.0, 2.0, 1.25, 0.75, 0.5])
+    A = np.diag(d)
+    U, S, V, _ = oracle.svd(A)
+    assert np.array_equal(U, np.eye(n)) and np.array_equal(V, np.eye(n)) and np.array_equal(S, d)
+    gU, gs, gV = rng.standard_normal((n, n)), rng.standard_normal(n), rng.standard_normal((n, n))
+    gA = oracle.svd_backward_ref(U, S, V, gU, gs, gV)
+    hand = np.diag(gs).astype(np.float64)
+    for i in range(n):
+        for j in range(n):
+            if i != j:
+                hand[i, j] = (d[j] * (gU[i, j] - gU[j, i]) + d[i] * (gV[i, j] - gV[j, i])) / (d[j] ** 2 - d[i] ** 2)
+    assert np.allclose(gA, hand, rtol=1e-12, atol=1e-14), np.max(np.abs(gA - hand))
+
+
+def test_adjoint_degenerate_pair_with_gauge_invariant_cotangents():
+    """sigma_1 = sigma_2 exactly: U and V are defined only up to a rotation
+    of that pair, and a loss through U M and V N with M, N symmetric does not
+    see the rotation (U^T gU - gU^T U = M - M^T = 0).  Its gradient is
+    U diag(gs) V^T; the guard on 1 / (s_j^2 - s_i^2) must give that instead
+    of 0 * inf."""
+    rng = np.random.default_rng(6)
+    n = 6
+    s = np.array([2.0, 2.0, 1.5, 1.0, 0.6, 0.3])
+    A = testmats.compose(testmats.haar(rng, n, n), s, testmats.haar(rng, n, n))
+    U, S, V, _ = oracle.svd(A)
+    M = rng.standard_normal((n, n)); M = M + M.T
+    N = rng.standard_normal((n, n)); N = N + N.T
+    gs = rng.standard_normal(n)
+    gA = oracle.svd_backward_ref(U, S, V, U @ M, gs, V @ N)
+    assert np.all(np.isfinite(gA))
+    assert np.allclose(gA, (U * gs) @ V.T, atol=1e-12)
+
+
 def test_adjoint_central_differences_on_c5_shape():
     data = testmats.config_c5(batch=2, ndir=4)
     for b in range(2):
