@@ -40,7 +40,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-CLOCK_EVERY = 8                # sampled clocking of the dominant Jacobi class
+CLOCK_EVERY = 8                # sampled clocking of the dominant kernel class
 FP64_PEAK_TF = 78.6            # dense FP64 (vector and MFMA)
 FP32_PEAK_TF = 157.3           # dense FP32 (vector and MFMA)
 
@@ -417,7 +417,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-survey", action="store_true",
                     help="skip the per-class clocked SVDs (no kernels table, no roofline)")
-    ap.add_argument("--cpu-sample-n", type=int, default=1024)
+    ap.add_argument("--cpu-sample-n", type=int, default=2048)
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the other workloads (1024^2 graded, 8192 x 2048, batch, adjoint)")
     ap.add_argument("--cpu-full", action="store_true",
@@ -480,9 +480,9 @@ def main() -> int:
     # events on the library's stream (the pivot pass as one interval per
     # pass); K plain SVDs without events
     opts_mixed.kernel_timing = 1 if dom_class == 6 else (100 + dom_class if dom_class is not None else 0)
-    # a Jacobi class (or the fused FP32 round) is clocked on every
-    # CLOCK_EVERY-th launch (a uniform sample over rounds and sweeps) so that
-    # its events barely touch the step
+    # the class is clocked on every CLOCK_EVERY-th launch (a uniform sample
+    # over rounds and sweeps, or over the panels of each QR) so that its
+    # events barely touch the step
     opts_mixed.kernel_timing_every = CLOCK_EVERY
     opts_plain.kernel_timing = 0
     infos, infos_p = [], []
@@ -595,8 +595,12 @@ def main() -> int:
             "traffic": None if traffic is None else round(traffic),
             "kernel": name, "avg_us": round(avg_s * 1e6, 2), "launches": calls,
             "bytes_per_launch": round(bytes_per_launch),
-            "measured": "timed region" + (f", every {CLOCK_EVERY}th launch" if c < 6 or c == 9 else ""),
+            "measured": "timed region" + (f", every {CLOCK_EVERY}th launch" if c != 6 else ""),
         })
+        if name == "qr_panel":
+            # a chain of 32 dependent column steps, each ending in one
+            # cross-workgroup exchange: the launch time per column step
+            roofline["latency"] = {"steps_per_launch": 32, "us_per_step": round(avg_s * 1e6 / 32, 2)}
 
     line = {
         "metric": "n=4096 SVD time: mixed vs plain FP64 Jacobi, same GPU, sigma rel err <=1e-13",

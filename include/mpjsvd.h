@@ -162,9 +162,10 @@ typedef struct {
                               costs one FP64 Gram product; 0: off */
     double tol_y2;         /* 0 -> 64 sqrt(n) 2^-24 */
     int kernel_timing_every; /* with kernel_timing >= 2: clock only every
-                              k-th launch of a Jacobi kernel class (a sample
-                              that keeps the events' cost out of the rest of
-                              the launches); 0 or 1 = every launch */
+                              k-th launch of each kernel class (the first
+                              launch always; a sample that keeps the events'
+                              cost out of the rest of the launches); 0 or 1 =
+                              every launch */
     int wait_polls;        /* polls of each bounded cross-workgroup wait
                               (one-launch pivot pass, Householder panel)
                               before it gives up: 0 = default (2^22);

@@ -46,7 +46,7 @@ struct KernelClock {
     }
     void begin(hipStream_t s, int c, double b, double f = 0.0) {
         if (!on) return;
-        skipping = only >= 0 && c != only;
+        skipping = (only >= 0 && c != only) || (seen[c]++ % every != 0);
         if (skipping) return;
         if (!grow(c, b, f)) return;
         cls[used / 2] = c;
