@@ -355,20 +355,16 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
     if (threadIdx.x == 0) sh.bad = 0;
     coop_columns(std::make_integer_sequence<int, QR_NB>{}, a, sh, mp, nb, tpart, thead, tau, base,
                  spin);
-#pragma unroll
-    for (int k = 0; k < QR_NB; ++k)
-        if (live && k < nb) P[(size_t)k * ld + i] = a[k];
-    // the explicit unit lower trapezoidal V of the panel (ld mp), also into
-    // LDS (rows past mp and columns past nb are zero)
+    // the explicit unit lower trapezoidal V of the panel into LDS (rows past
+    // mp and columns past nb are zero); the factored panel and V go out to
+    // memory after the V^T V partial has been published, so that the
+    // store-completion wait before the flag covers the partial alone
     __syncthreads();
     {
         double *vr = sh.red + threadIdx.x * (QR_NB + 1);
 #pragma unroll
-        for (int k = 0; k < QR_NB; ++k) {
-            const double v = (live && k < nb) ? (i > k ? a[k] : (i == k ? 1.0 : 0.0)) : 0.0;
-            if (live && k < nb) Vb[(size_t)k * mp + i] = v;
-            vr[k] = v;
-        }
+        for (int k = 0; k < QR_NB; ++k)
+            vr[k] = (live && k < nb) ? (i > k ? a[k] : (i == k ? 1.0 : 0.0)) : 0.0;
     }
     __syncthreads();
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = blockIdx.x, G = gridDim.x;
@@ -387,10 +383,24 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
     publish_fence();
     __syncthreads();
     if (t == 0) coh_store(flags + g, base + QR_NB + 1);
+    // the factored panel and V (workgroup 0: after the sum of the V^T V
+    // partials, before T)
+    auto write_back = [&]() {
+#pragma unroll
+        for (int k = 0; k < QR_NB; ++k) {
+            if (live && k < nb) {
+                P[(size_t)k * ld + i] = a[k];
+                Vb[(size_t)k * mp + i] = i > k ? a[k] : (i == k ? 1.0 : 0.0);
+            }
+        }
+    };
     // a wait that ran out leaves this panel's factors invalid: report it in
     // the caller's error word (read back with the run's status)
     if (t == 0 && sh.bad && err) *err = 1;
-    if (g != 0) return;
+    if (g != 0) {
+        write_back();
+        return;
+    }
     if (t < G && t != 0) {
         int it = 0;
         while (spin < 0 || coh_load(flags + t) < base + QR_NB + 1) {
@@ -401,14 +411,37 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
     __syncthreads();
     if (t == 0 && sh.bad && err) *err = 1;
     double *Gs = sh.red;   // G (ld QR_NB), the rows of V are no longer needed
-    for (int e = t; e < QR_NB * QR_NB; e += QR_RC) {
-        double sacc = 0.0;
-        for (int q = 0; q < G; ++q) sacc += coh_load(Gpart + (size_t)q * QR_NB * QR_NB + e);
-        Gs[e] = sacc;
+    {
+        // the four entries of this thread, the loads of eight partials at a
+        // time in flight together, added in workgroup order
+        constexpr int EPT = QR_NB * QR_NB / QR_RC;
+        constexpr int QB = 8;
+        double sacc[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) sacc[u] = 0.0;
+        for (int q0 = 0; q0 < G; q0 += QB) {
+            double v[QB][EPT];
+#pragma unroll
+            for (int q = 0; q < QB; ++q)
+#pragma unroll
+                for (int u = 0; u < EPT; ++u)
+                    v[q][u] = q0 + q < G ? coh_load(Gpart + (size_t)(q0 + q) * QR_NB * QR_NB + t + u * QR_RC)
+                                         : 0.0;
+#pragma unroll
+            for (int q = 0; q < QB; ++q)
+#pragma unroll
+                for (int u = 0; u < EPT; ++u)
+                    if (q0 + q < G) sacc[u] += v[q][u];
+        }
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) Gs[t + u * QR_RC] = sacc[u];
     }
     __syncthreads();
+    // rows written back (their stores drain while T is solved)
+    write_back();
     if (t < QR_NB) {
         const int j = t;
+        const double poison = sh.bad ? __builtin_nan("") : 0.0;
         double c[QR_NB];
 #pragma unroll
         for (int r = 0; r < QR_NB; ++r) c[r] = (r == j && j < nb) ? sh.tv[r] : 0.0;
@@ -422,7 +455,6 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
             }
             if (r < j) c[r] = -(r < nb ? sh.tv[r] : 0.0) * (s0 + s1);
         }
-        const double poison = sh.bad ? __builtin_nan("") : 0.0;
 #pragma unroll
         for (int r = 0; r < QR_NB; ++r) T[(size_t)j * ldt + r] = (j < nb ? c[r] : 0.0) + poison;
     }
