@@ -384,7 +384,7 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
     __syncthreads();
     if (t == 0) coh_store(flags + g, base + QR_NB + 1);
     // the factored panel and V (workgroup 0: after the sum of the V^T V
-    // partials, before T)
+    // partials, its first wavefront after T)
     auto write_back = [&]() {
 #pragma unroll
         for (int k = 0; k < QR_NB; ++k) {
@@ -437,8 +437,8 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
         for (int u = 0; u < EPT; ++u) Gs[t + u * QR_RC] = sacc[u];
     }
     __syncthreads();
-    // rows written back (their stores drain while T is solved)
-    write_back();
+    // the other wavefronts write their rows back while the first solves for T
+    if (t >= 64) write_back();
     if (t < QR_NB) {
         const int j = t;
         const double poison = sh.bad ? __builtin_nan("") : 0.0;
@@ -458,6 +458,7 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
 #pragma unroll
         for (int r = 0; r < QR_NB; ++r) T[(size_t)j * ldt + r] = (j < nb ? c[r] : 0.0) + poison;
     }
+    if (t < 64) write_back();
 }
 
 // Clears the one-launch panel's flags and tagged words before a factorisation.
