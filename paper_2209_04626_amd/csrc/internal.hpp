@@ -126,6 +126,9 @@ struct QRScratch {
     double *head;   // 2 * QR_NB
     unsigned long long *tpart;   // one-launch panel: tagged sums, 2 * 2 * max_groups * QR_NB words
     unsigned long long *thead;   // and the tagged head row, 2 * 2 * QR_NB words
+    unsigned long long *tw1 = nullptr;   // one-launch in-block update: tagged partials
+    unsigned long long *tw2 = nullptr;   // and the tagged entries of V^T C (right after tw1)
+    int tw_words = 0;                    // words of both
     double *vtv;    // max_groups * QR_NB * QR_NB
     double *vb;     // m * QR_NB     (explicit unit-lower block of reflectors)
     double *vbo;    // m * QR_NBO    (the same for an outer block)

@@ -461,13 +461,168 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
     if (t < 64) write_back();
 }
 
-// Clears the one-launch panel's flags and tagged words before a factorisation.
+// ---------------------------------------------------------------- in-block update
+// C (mp x ncol) <- (I - V T^T V^T) C for a factored panel (V: mp x nb, ld ldv,
+// explicit unit lower trapezoidal; T: nb x nb upper, ld ldt; nb <= 32,
+// ncol <= 96), in one launch instead of the four of apply_block (split-K
+// V^T C, its reduction, T^T W, C - V W).  Workgroup g holds rows 64g .. 64g+63
+// of V and C in LDS and forms its partial P_g = V_g^T C_g on the matrix
+// cores; the partials go out as tagged words (two per value, as in the
+// panel), workgroup g sums a slice of the 32 ncol entries over all
+// workgroups in workgroup order (four threads per entry, each a quarter of
+// the workgroups, then the four quarters in order) and publishes the slice;
+// every workgroup then reads all of W = V^T C, forms T^T W and updates its
+// rows.  Needs every workgroup resident at once; the waits are bounded and
+// one that runs out sets *err.
+constexpr int QA_RB = 64;          // rows per workgroup
+constexpr int QA_NC = 96;          // most columns of C
+constexpr int QA_LDV = QR_NB + 1, QA_LDC = QA_NC + 1;
+
+__global__ __launch_bounds__(256) void qr_apply_coop(int mp, int nb, const double *__restrict__ V, int ldv,
+                                                     const double *__restrict__ T, int ldt, int ncol,
+                                                     double *__restrict__ C, int ldc,
+                                                     unsigned long long *tw1, unsigned long long *tw2,
+                                                     unsigned tag, int spin, int *err) {
+    __shared__ double Vs[QA_RB * QA_LDV];
+    __shared__ double Cs[QA_RB * QA_LDC];
+    __shared__ double Ws[QR_NB * QA_LDC];     // W = V^T C, then T^T W
+    __shared__ double Ts[QR_NB * QA_LDV];
+    __shared__ double red[256];
+    __shared__ int bad;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int g = blockIdx.x, G = gridDim.x;
+    const int r0 = g * QA_RB;
+    if (t == 0) bad = 0;
+    // rows of V (columns past nb zero) and of C (columns past ncol zero), T
+    for (int e = t; e < QA_RB * QR_NB; e += 256) {
+        const int i = e % QA_RB, k = e / QA_RB;
+        Vs[i * QA_LDV + k] = (r0 + i < mp && k < nb) ? V[(size_t)k * ldv + r0 + i] : 0.0;
+    }
+    for (int e = t; e < QA_RB * QA_NC; e += 256) {
+        const int i = e % QA_RB, c = e / QA_RB;
+        Cs[i * QA_LDC + c] = (r0 + i < mp && c < ncol) ? C[(size_t)c * ldc + r0 + i] : 0.0;
+    }
+    for (int e = t; e < QR_NB * QR_NB; e += 256) {
+        const int i = e % QR_NB, k = e / QR_NB;
+        Ts[i * QA_LDV + k] = (i < nb && k < nb) ? T[(size_t)k * ldt + i] : 0.0;
+    }
+    __syncthreads();
+    const int nct = cdiv(ncol, 16);   // 16-column tiles of C
+    // 1. P_g = V_g^T C_g (32 x ncol), 2 x nct tiles over the four wavefronts
+    for (int tile = w; tile < 2 * nct; tile += 4) {
+        const int ti = tile & 1, tj = tile >> 1;
+        dbl4 acc = dbl4{0, 0, 0, 0};
+#pragma unroll
+        for (int s4 = 0; s4 < QA_RB; s4 += 4) {
+            const int k = s4 + lane / 16;
+            acc = mfma16(Vs[k * QA_LDV + 16 * ti + lane % 16], Cs[k * QA_LDC + 16 * tj + lane % 16], acc);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = 16 * ti + mfma_row<double>(lane, e), c = 16 * tj + lane % 16;
+            if (c < ncol) tag_store(tw1 + ((size_t)g * QR_NB * QA_NC + r * QA_NC + c) * 2, acc[e], tag);
+        }
+    }
+    // 2. this workgroup's slice of the 32 ncol entries of W, summed over the
+    // workgroups: 64 entries a pass, four threads per entry
+    const int E = QR_NB * ncol;
+    const int S = cdiv(E, G);
+    const int Gq = cdiv(G, 4);
+    for (int e0 = 0; e0 < S; e0 += 64) {
+        const int el = e0 + (t >> 2), h = t & 3;
+        const int e = g * S + el;
+        double part = 0.0;
+        if (el < S && e < E) {
+            const int r = e / ncol, c = e % ncol;
+            for (int qb = h * Gq; qb < min(G, (h + 1) * Gq); qb += 8) {
+                const unsigned long long *pp[8];
+                double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                unsigned mask = 0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int q = qb + u;
+                    const bool ok = q < min(G, (h + 1) * Gq);
+                    pp[u] = tw1 + ((size_t)(ok ? q : 0) * QR_NB * QA_NC + r * QA_NC + c) * 2;
+                    if (ok) mask |= 1u << u;
+                }
+                if (!tag_load<8>(pp, mask, tag, spin, v)) bad = 1;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (mask & (1u << u)) part += v[u];
+            }
+        }
+        red[t] = part;
+        __syncthreads();
+        if (h == 0 && el < S && e < E) {
+            const double sum = ((red[t] + red[t + 1]) + red[t + 2]) + red[t + 3];
+            tag_store(tw2 + (size_t)e * 2, sum, tag);
+        }
+        __syncthreads();
+    }
+    // 3. all of W (four entries a pass per thread), then T^T W
+    for (int e0 = t; e0 < E; e0 += 4 * 256) {
+        const unsigned long long *pp[4];
+        double v[4] = {0, 0, 0, 0};
+        unsigned mask = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * 256;
+            pp[u] = tw2 + (size_t)(e < E ? e : 0) * 2;
+            if (e < E) mask |= 1u << u;
+        }
+        if (!tag_load<4>(pp, mask, tag, spin, v)) bad = 1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * 256;
+            if (e < E) Ws[(e / ncol) * QA_LDC + e % ncol] = v[u];
+        }
+    }
+    __syncthreads();
+    double tw[QR_NB * QA_NC / 256];   // (T^T W)(i, c) for this thread's entries
+#pragma unroll
+    for (int u = 0; u < QR_NB * QA_NC / 256; ++u) {
+        const int e = t + u * 256, i = e / QA_NC, c = e % QA_NC;
+        double sacc = 0.0;
+        if (c < ncol) {
+#pragma unroll
+            for (int k = 0; k < QR_NB; ++k) sacc = fma(Ts[k * QA_LDV + i], Ws[k * QA_LDC + c], sacc);
+        }
+        tw[u] = sacc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < QR_NB * QA_NC / 256; ++u) {
+        const int e = t + u * 256, i = e / QA_NC, c = e % QA_NC;
+        Ws[i * QA_LDC + c] = c < ncol ? tw[u] : 0.0;
+    }
+    __syncthreads();
+    // 4. C_g <- C_g - V_g (T^T W): 4 x nct tiles over the wavefronts
+    for (int tile = w; tile < 4 * nct; tile += 4) {
+        const int ri = tile & 3, tj = tile >> 2;
+        dbl4 acc = dbl4{0, 0, 0, 0};
+#pragma unroll
+        for (int s4 = 0; s4 < QR_NB; s4 += 4) {
+            const int k = s4 + lane / 16;
+            acc = mfma16(Vs[(16 * ri + lane % 16) * QA_LDV + k], Ws[k * QA_LDC + 16 * tj + lane % 16], acc);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = 16 * ri + mfma_row<double>(lane, e), c = 16 * tj + lane % 16;
+            if (r0 + i < mp && c < ncol) C[(size_t)c * ldc + r0 + i] = Cs[i * QA_LDC + c] - acc[e];
+        }
+    }
+    if (t == 0 && bad && err) *err = 1;
+}
+
+// Clears the one-launch panel's flags and tagged words, and those of the
+// one-launch in-block update, before a factorisation.
 __global__ void qr_flags_zero(int n, int *flags, int nt, unsigned long long *tp, int nh,
-                              unsigned long long *th) {
+                              unsigned long long *th, int na, unsigned long long *ta) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < n) flags[e] = 0;
     if (e < nt) tp[e] = 0ull;
     if (e < nh) th[e] = 0ull;
+    if (e < na) ta[e] = 0ull;
 }
 
 // T (nb x nb upper, zeros below, ld ldt) of the compact-WY form
@@ -529,7 +684,9 @@ size_t qr_scratch_doubles(int m, int ncols_max, size_t *split_elems) {
     const int G = cdiv(m, QR_RC);
     const size_t se = (size_t)8 * QR_NBO * (size_t)ncols_max;
     if (split_elems) *split_elems = se;
-    return (size_t)2 * G * QR_NB + 2 * QR_NB + (size_t)4 * G * QR_NB + 4 * QR_NB +
+    const int GA = cdiv(m, QA_RB);
+    const size_t ta = GA <= 256 ? (size_t)2 * (GA + 1) * QR_NB * QA_NC : 0;   // in-block update words
+    return (size_t)2 * G * QR_NB + 2 * QR_NB + (size_t)4 * G * QR_NB + 4 * QR_NB + ta +
            (size_t)G * QR_NB * QR_NB + (size_t)m * QR_NB +
            (size_t)m * QR_NBO + (size_t)QR_NBO * QR_NBO + (size_t)QR_NB * QR_NB +
            2 * (size_t)QR_NBO * ncols_max + se + (size_t)(G + 63) / 2 + 128;
@@ -544,6 +701,17 @@ void qr_scratch_carve(QRScratch &q, double *base, int m, int ncols_max) {
     q.head = p; p += 2 * QR_NB;
     q.tpart = (unsigned long long *)p; p += (size_t)4 * G * QR_NB;
     q.thead = (unsigned long long *)p; p += 4 * QR_NB;
+    {
+        const int GA = cdiv(m, QA_RB);
+        if (GA <= 256) {
+            q.tw1 = (unsigned long long *)p; p += (size_t)2 * GA * QR_NB * QA_NC;
+            q.tw2 = (unsigned long long *)p; p += (size_t)2 * QR_NB * QA_NC;
+            q.tw_words = 2 * (GA + 1) * QR_NB * QA_NC;
+        } else {
+            q.tw1 = q.tw2 = nullptr;
+            q.tw_words = 0;
+        }
+    }
     q.vtv = p; p += (size_t)G * QR_NB * QR_NB;
     q.vb = p; p += (size_t)m * QR_NB;
     q.vbo = p; p += (size_t)m * QR_NBO;
@@ -585,6 +753,43 @@ static int coop_capacity() {
     c = ncu * per_cu;
     cap[dev].store(c, std::memory_order_relaxed);
     return c;
+}
+
+// Workgroups of qr_apply_coop that the current device holds at once; cached.
+static int apply_capacity() {
+    static std::atomic<int> cap[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    int c = cap[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+    int ncu = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)qr_apply_coop, 256, 0) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    c = ncu * per_cu;
+    cap[dev].store(c, std::memory_order_relaxed);
+    return c;
+}
+
+// The in-block update C <- (I - V T^T V^T) C of a panel in one launch, when
+// its row blocks (8 to 256 of them) all fit on the device; false otherwise
+// (nothing launched, the caller takes apply_block).
+static bool apply_inblock(hipStream_t s, int mp, int nb, const double *T, int ldt, int ncol, double *C,
+                          int ldc, const double *vb, QRScratch &q, unsigned tag) {
+    const int G = cdiv(mp, QA_RB);
+    if (!q.tw1 || G < 8 || G > 256 || ncol > QA_NC || nb > QR_NB || G > apply_capacity()) return false;
+    if (q.kc) q.kc->begin(s, 8, (2.0 * mp * ncol + (double)mp * nb) * sizeof(double),
+                          4.0 * mp * nb * ncol + 2.0 * nb * nb * ncol);
+    hipLaunchKernelGGL(qr_apply_coop, dim3(G), dim3(256), 0, s, mp, nb, vb, mp, T, ldt, ncol, C, ldc,
+                       q.tw1, q.tw2, tag, q.spin == 0 ? QR_COOP_SPIN : q.spin, q.err);
+    if (q.kc) q.kc->end(s);
+    return true;
 }
 
 static void panel_factor(hipStream_t s, int mp, int nb, double *P, int ld, double *tau,
@@ -637,8 +842,9 @@ void qr_factor(hipStream_t s, int m, int n, double *A, int lda, double *tau, dou
     const int gmax = cdiv(m, QR_RC);
     if (gmax <= QR_COOP_MAXG) {
         const int nt = 4 * gmax * QR_NB;   // tagged sums of both column parities
-        hipLaunchKernelGGL(qr_flags_zero, dim3(cdiv(nt, 256)), dim3(256), 0, s, gmax, q.flags, nt,
-                           q.tpart, 4 * QR_NB, q.thead);
+        const int na = q.tw1 ? q.tw_words : 0;       // tw2 sits after the carve's tw1, not the call's
+        hipLaunchKernelGGL(qr_flags_zero, dim3(cdiv(nt > na ? nt : na, 256)), dim3(256), 0, s, gmax,
+                           q.flags, nt, q.tpart, 4 * QR_NB, q.thead, na, q.tw1);
     }
     int panel = 0;
     for (int c0o = 0, ob = 0; c0o < n; c0o += QR_NBO, ++ob) {
@@ -653,7 +859,8 @@ void qr_factor(hipStream_t s, int m, int n, double *A, int lda, double *tau, dou
             double *Tp = To + (size_t)(c0 - c0o) * QR_NBO + (c0 - c0o);
             panel_factor(s, mp, nb, P, lda, tau + c0, Tp, QR_NBO, q, panel);
             const int nin = c0o + nbo - c0 - nb;   // the rest of the outer block
-            if (nin > 0)
+            if (nin > 0 && !apply_inblock(s, mp, nb, Tp, QR_NBO, nin, P + (size_t)nb * lda, lda, q.vb, q,
+                                          (unsigned)(panel * 64 + 48)))
                 apply_block(s, true, mp, nb, Tp, QR_NBO, nin, P + (size_t)nb * lda, lda, q.vb, q);
         }
         double *Po = A + (size_t)c0o * lda + c0o;
