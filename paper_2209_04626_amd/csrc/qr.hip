@@ -471,12 +471,15 @@ __global__ __launch_bounds__(QR_RC) void qr_panel_coop(int mp, int nb, double *P
 // panel), workgroup g sums a slice of the 32 ncol entries over all
 // workgroups in workgroup order (four threads per entry, each a quarter of
 // the workgroups, then the four quarters in order) and publishes the slice;
-// every workgroup then reads all of W = V^T C, forms T^T W and updates its
-// rows.  Needs every workgroup resident at once; the waits are bounded and
-// one that runs out sets *err.
+// every workgroup then reads all of W = V^T C, forms T^T W on the matrix
+// cores and updates its rows.  Each of the two exchanges is one pass of loads
+// with all of a thread's words in flight.  Needs every workgroup resident at
+// once; the waits are bounded and one that runs out sets *err.
 constexpr int QA_RB = 64;          // rows per workgroup
 constexpr int QA_NC = 96;          // most columns of C
 constexpr int QA_LDV = QR_NB + 1, QA_LDC = QA_NC + 1;
+constexpr int QA_KW = QR_NB * QA_NC / 256;             // words of W per thread
+constexpr int QA_K = (QR_NB * QA_NC + 255) / 256 + 1;  // slice words per thread: S G <= 32 QA_NC + G
 
 __global__ __launch_bounds__(256) void qr_apply_coop(int mp, int nb, const double *__restrict__ V, int ldv,
                                                      const double *__restrict__ T, int ldt, int ncol,
@@ -487,6 +490,7 @@ __global__ __launch_bounds__(256) void qr_apply_coop(int mp, int nb, const doubl
     __shared__ double Cs[QA_RB * QA_LDC];
     __shared__ double Ws[QR_NB * QA_LDC];     // W = V^T C, then T^T W
     __shared__ double Ts[QR_NB * QA_LDV];
+    __shared__ double Ps[256 * QA_K];         // the slice's words of every workgroup
     __shared__ double red[256];
     __shared__ int bad;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -506,6 +510,7 @@ __global__ __launch_bounds__(256) void qr_apply_coop(int mp, int nb, const doubl
         const int i = e % QR_NB, k = e / QR_NB;
         Ts[i * QA_LDV + k] = (i < nb && k < nb) ? T[(size_t)k * ldt + i] : 0.0;
     }
+    for (int e = t; e < QR_NB * QA_LDC; e += 256) Ws[e] = 0.0;   // columns past ncol stay zero
     __syncthreads();
     const int nct = cdiv(ncol, 16);   // 16-column tiles of C
     // 1. P_g = V_g^T C_g (32 x ncol), 2 x nct tiles over the four wavefronts
@@ -524,76 +529,95 @@ __global__ __launch_bounds__(256) void qr_apply_coop(int mp, int nb, const doubl
         }
     }
     // 2. this workgroup's slice of the 32 ncol entries of W, summed over the
-    // workgroups: 64 entries a pass, four threads per entry
+    // workgroups.  Every (workgroup, entry) word of the slice is loaded in
+    // one pass (entries fastest, so the loads of a wavefront are contiguous),
+    // kept in LDS, then four threads per entry sum a quarter of the
+    // workgroups each and the four quarters are added in order.
     const int E = QR_NB * ncol;
     const int S = cdiv(E, G);
-    const int Gq = cdiv(G, 4);
-    for (int e0 = 0; e0 < S; e0 += 64) {
-        const int el = e0 + (t >> 2), h = t & 3;
-        const int e = g * S + el;
-        double part = 0.0;
-        if (el < S && e < E) {
-            const int r = e / ncol, c = e % ncol;
-            for (int qb = h * Gq; qb < min(G, (h + 1) * Gq); qb += 8) {
-                const unsigned long long *pp[8];
-                double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                unsigned mask = 0;
+    const int e_lo = g * S;
+    const int SL = min(S, E - e_lo);   // entries of this slice (none past E)
+    {
+        const unsigned long long *pp[QA_K];
+        double v[QA_K];
+        unsigned mask = 0;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int q = qb + u;
-                    const bool ok = q < min(G, (h + 1) * Gq);
-                    pp[u] = tw1 + ((size_t)(ok ? q : 0) * QR_NB * QA_NC + r * QA_NC + c) * 2;
-                    if (ok) mask |= 1u << u;
-                }
-                if (!tag_load<8>(pp, mask, tag, spin, v)) bad = 1;
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (mask & (1u << u)) part += v[u];
-            }
+        for (int u = 0; u < QA_K; ++u) {
+            const int i = t + 256 * u, q = i / S, el = i - q * S;
+            const bool ok = q < G && el < SL;
+            const int e = ok ? e_lo + el : 0, r = e / ncol, c = e - r * ncol;
+            pp[u] = tw1 + ((size_t)(ok ? q : 0) * QR_NB * QA_NC + r * QA_NC + c) * 2;
+            if (ok) mask |= 1u << u;
+            v[u] = 0.0;
         }
+        if (!tag_load<QA_K>(pp, mask, tag, spin, v)) bad = 1;
+#pragma unroll
+        for (int u = 0; u < QA_K; ++u)
+            if (mask & (1u << u)) Ps[t + 256 * u] = v[u];
+    }
+    __syncthreads();
+    const int Gq = cdiv(G, 4);
+    for (int e0 = 0; e0 < SL; e0 += 64) {
+        const int el = e0 + (t >> 2), h = t & 3;
+        double part = 0.0;
+        if (el < SL)
+            for (int q = h * Gq; q < min(G, (h + 1) * Gq); ++q) part += Ps[q * S + el];
         red[t] = part;
         __syncthreads();
-        if (h == 0 && el < S && e < E) {
+        if (h == 0 && el < SL) {
             const double sum = ((red[t] + red[t + 1]) + red[t + 2]) + red[t + 3];
-            tag_store(tw2 + (size_t)e * 2, sum, tag);
+            tag_store(tw2 + (size_t)(e_lo + el) * 2, sum, tag);
         }
         __syncthreads();
     }
-    // 3. all of W (four entries a pass per thread), then T^T W
-    for (int e0 = t; e0 < E; e0 += 4 * 256) {
-        const unsigned long long *pp[4];
-        double v[4] = {0, 0, 0, 0};
+    // 3. all of W in one pass, then T^T W on the matrix cores
+    {
+        const unsigned long long *pp[QA_KW];
+        double v[QA_KW];
         unsigned mask = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = e0 + u * 256;
+        for (int u = 0; u < QA_KW; ++u) {
+            const int e = t + 256 * u;
             pp[u] = tw2 + (size_t)(e < E ? e : 0) * 2;
             if (e < E) mask |= 1u << u;
+            v[u] = 0.0;
         }
-        if (!tag_load<4>(pp, mask, tag, spin, v)) bad = 1;
+        if (!tag_load<QA_KW>(pp, mask, tag, spin, v)) bad = 1;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = e0 + u * 256;
+        for (int u = 0; u < QA_KW; ++u) {
+            const int e = t + 256 * u;
             if (e < E) Ws[(e / ncol) * QA_LDC + e % ncol] = v[u];
         }
     }
     __syncthreads();
-    double tw[QR_NB * QA_NC / 256];   // (T^T W)(i, c) for this thread's entries
+    {
+        constexpr int TPW = (2 * (QA_NC / 16) + 3) / 4;   // tiles of T^T W per wavefront
+        dbl4 acc[TPW];
 #pragma unroll
-    for (int u = 0; u < QR_NB * QA_NC / 256; ++u) {
-        const int e = t + u * 256, i = e / QA_NC, c = e % QA_NC;
-        double sacc = 0.0;
-        if (c < ncol) {
+        for (int u = 0; u < TPW; ++u) {
+            const int tile = w + 4 * u, ti = tile & 1, tj = tile >> 1;
+            acc[u] = dbl4{0, 0, 0, 0};
+            if (tile < 2 * nct) {
 #pragma unroll
-            for (int k = 0; k < QR_NB; ++k) sacc = fma(Ts[k * QA_LDV + i], Ws[k * QA_LDC + c], sacc);
+                for (int s4 = 0; s4 < QR_NB; s4 += 4) {
+                    const int k = s4 + lane / 16;
+                    acc[u] = mfma16(Ts[k * QA_LDV + 16 * ti + lane % 16], Ws[k * QA_LDC + 16 * tj + lane % 16],
+                                    acc[u]);
+                }
+            }
         }
-        tw[u] = sacc;
-    }
-    __syncthreads();
+        __syncthreads();
 #pragma unroll
-    for (int u = 0; u < QR_NB * QA_NC / 256; ++u) {
-        const int e = t + u * 256, i = e / QA_NC, c = e % QA_NC;
-        Ws[i * QA_LDC + c] = c < ncol ? tw[u] : 0.0;
+        for (int u = 0; u < TPW; ++u) {
+            const int tile = w + 4 * u, ti = tile & 1, tj = tile >> 1;
+            if (tile < 2 * nct) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int i = 16 * ti + mfma_row<double>(lane, e), c = 16 * tj + lane % 16;
+                    Ws[i * QA_LDC + c] = acc[u][e];
+                }
+            }
+        }
     }
     __syncthreads();
     // 4. C_g <- C_g - V_g (T^T W): 4 x nct tiles over the wavefronts
