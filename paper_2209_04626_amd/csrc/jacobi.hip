@@ -262,7 +262,7 @@ __device__ __forceinline__ bool jac_rot_test(double al, double be, double ga, do
 
 template <typename T, int B2, int NT, int NTW, bool CROSS>
 __device__ __forceinline__ float inner_rounds_t(T (*G)[B2 * (B2 + 1)], T *W, int *ired, double eps2,
-                                                int max_inner) {
+                                                int max_inner, unsigned rmask) {
     constexpr int LD = B2 + 1;
     constexpr int H = B2 / 2;
     constexpr int M = B2 - 1;
@@ -272,6 +272,7 @@ __device__ __forceinline__ float inner_rounds_t(T (*G)[B2 * (B2 + 1)], T *W, int
     constexpr int NRS = sizeof(T) == 4 ? 1 : 2;
     static_assert(CG * H == NTW && GPT * CG == H && RPT * CG == B2, "tiling");
     static_assert(64 % H == 0 && NTW % 64 == 0 && NTW <= NT, "every wavefront holds every pair index");
+    static_assert((H & (H - 1)) == 0, "cross rounds index the second block modulo H");
     const int tid = threadIdx.x;
     // threads from NTW on (whole wavefronts) only keep step with the barriers
     const bool work = NTW == NT || tid < NTW;
@@ -307,6 +308,15 @@ __device__ __forceinline__ float inner_rounds_t(T (*G)[B2 * (B2 + 1)], T *W, int
     for (int sw = 0; sw < max_inner; ++sw) {
         int rotated = 0;
         for (int rd = 0; rd < nround; ++rd) {
+          if constexpr (CROSS) {
+            // a round none of whose pairs needed a rotation when the block
+            // was tested is left out of the first cycle (rmask is the same
+            // in every thread, so the barriers still match)
+            if (sw == 0 && !((rmask >> rd) & 1u)) continue;
+            ay = H + ((a + rd) & (H - 1));
+#pragma unroll
+            for (int k = 0; k < GPT; ++k) cy[k] = H + ((c0 + k + rd) & (H - 1));
+          }
           if (work) {
             const T *g = G[cur];
             T *gn = G[cur ^ 1];
@@ -337,6 +347,14 @@ __device__ __forceinline__ float inner_rounds_t(T (*G)[B2 * (B2 + 1)], T *W, int
                 smax = fmaxf(smax, (float)fabs(sa));
             }
             const T c1 = (T)ca, s1 = (T)sa;
+            // the rotations of this thread's pairs c, from their lanes (all
+            // in flight while W is updated)
+            T cc2[GPT], ss2[GPT];
+#pragma unroll
+            for (int k = 0; k < GPT; ++k) {
+                cc2[k] = __shfl(c1, c0 + k, 64);
+                ss2[k] = __shfl(s1, c0 + k, 64);
+            }
             // W <- W J on the column pair (p, q): x_p' = c x_p - s x_q, x_q' = s x_p + c x_q
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
@@ -348,7 +366,7 @@ __device__ __forceinline__ float inner_rounds_t(T (*G)[B2 * (B2 + 1)], T *W, int
             // G <- J^T G J on the groups: rows (p, q) by pair a, columns (r, s) by pair c
 #pragma unroll
             for (int k = 0; k < GPT; ++k) {
-                const T c2 = __shfl(c1, c0 + k, 64), s2 = __shfl(s1, c0 + k, 64);
+                const T c2 = cc2[k], s2 = ss2[k];
                 const T h00 = c1 * blk[k][0] - s1 * blk[k][2], h01 = c1 * blk[k][1] - s1 * blk[k][3];
                 const T h10 = s1 * blk[k][0] + c1 * blk[k][2], h11 = s1 * blk[k][1] + c1 * blk[k][3];
                 T o00 = c2 * h00 - s2 * h01, o01 = s2 * h00 + c2 * h01;
@@ -370,12 +388,7 @@ __device__ __forceinline__ float inner_rounds_t(T (*G)[B2 * (B2 + 1)], T *W, int
           }
             __syncthreads();
             cur ^= 1;
-            if constexpr (CROSS) {
-                // next round: the second block's partner advances by one (mod b)
-                ay = ay + 1 == B2 ? H : ay + 1;
-#pragma unroll
-                for (int k = 0; k < GPT; ++k) cy[k] = cy[k] + 1 == B2 ? H : cy[k] + 1;
-            } else {
+            if constexpr (!CROSS) {
                 // next round: every schedule position advances by one (mod
                 // 2b-1), except the fixed partner 2b-1 of pair 0
                 ax = ax + 1 == M ? 0 : ax + 1;
@@ -408,7 +421,11 @@ __device__ __forceinline__ float inner_rounds_t(T (*G)[B2 * (B2 + 1)], T *W, int
 // (rd - k) mod (2b-1); pair 0 joins rd and 2b-1); 2b - 1 rounds reach every
 // pair of the 2b columns.  With cross set, only the b^2 pairs between the two
 // blocks are rotated: round rd joins column k of the first block with column
-// (k + rd) mod b of the second, b rounds.  Thread (a, g) computes the rotation
+// (k + rd) mod b of the second, b rounds, and round rd is left out of the
+// first cycle when bit rd of rmask is clear (the caller clears the rounds none
+// of whose pairs needed a rotation when the block was tested; a pair of such
+// a round that rotations of earlier rounds push over the threshold waits for
+// the next sweep, which tests it on a fresh Gram block).  Thread (a, g) computes the rotation
 // of pair a from the current G and owns the 2x2 groups {p_a, q_a} x {p_c, q_c}
 // of G for its GPT pairs c (the groups tile G) and RPT rows of W's column
 // pair a.  Pair c's rotation comes from the lane of the same wavefront whose
@@ -422,9 +439,9 @@ __device__ __forceinline__ float inner_rounds_t(T (*G)[B2 * (B2 + 1)], T *W, int
 // registers).
 template <typename T, int B2, int NT, int NTW = NT>
 __device__ __forceinline__ float inner_rounds(T (*G)[B2 * (B2 + 1)], T *W, int *ired, double eps2,
-                                              int max_inner, int cross) {
-    return cross ? inner_rounds_t<T, B2, NT, NTW, true>(G, W, ired, eps2, max_inner)
-                 : inner_rounds_t<T, B2, NT, NTW, false>(G, W, ired, eps2, max_inner);
+                                              int max_inner, int cross, unsigned rmask) {
+    return cross ? inner_rounds_t<T, B2, NT, NTW, true>(G, W, ired, eps2, max_inner, rmask)
+                 : inner_rounds_t<T, B2, NT, NTW, false>(G, W, ired, eps2, max_inner, rmask);
 }
 
 // Inner solve of one block pair.  G and the accumulated W are held in the
@@ -528,6 +545,8 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
 
     // 2. does any pair of the block need a rotation?  Also the largest
     // |g_pq| / sqrt(g_pp g_qq) of the block, kept per sweep as a diagnostic.
+    // With cross set, `need` holds the cross rounds (bit (q - p) mod b for
+    // the pair p < b <= q) that have a pair to rotate.
     int need = 0;
     float offmax = 0.f;
 #pragma unroll
@@ -536,7 +555,10 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
         if (uok[k] && p < q) {
             const double g = (double)G[0][p * LD + q];
             const double pq = (double)G[0][p * LD + p] * (double)G[0][q * LD + q];
-            if (g * g > eps2 * pq && pq > 0.0 && (!cross || (p < H && q >= H))) need = 1;
+            if (g * g > eps2 * pq && pq > 0.0) {
+                if (!cross) need = 1;
+                else if (p < H && q >= H) need |= (int)(1u << ((q - H - p) & (H - 1)));
+            }
             if (pq > 0.0) offmax = fmaxf(offmax, (float)(fabs(g) / sqrt(pq)));
         }
     }
@@ -548,6 +570,7 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
     offmax = wave_max(offmax);
     if ((tid & 63) == 0) wmx[tid >> 6] = offmax;
     need = block_or<NT>(need, ired);
+    const unsigned rmask = cross ? (unsigned)need : ~0u;
     if (tid == 0) {
         float m = 0.f;
 #pragma unroll
@@ -560,7 +583,7 @@ __global__ __launch_bounds__(NT) void jac_inner(int nchunk, const T *__restrict_
     if (!need) return;
 
     // 3. cyclic rounds of disjoint rotations on G, accumulating W = prod J
-    float smax = inner_rounds<T, B2, NT>(G, W, ired, eps2, max_inner, cross);
+    float smax = inner_rounds<T, B2, NT>(G, W, ired, eps2, max_inner, cross, rmask);
 
     smax = wave_max(smax);
     if ((tid & 63) == 0) wsm[tid >> 6] = smax;
@@ -949,6 +972,8 @@ __global__ __launch_bounds__(NT) void jac_round_f32(int N, int nblk, int r, void
     // taken once)
     const double eps2 = eps * eps;
     static_assert(NT % B2 == 0, "test layout");
+    // (with cross set, `need` holds the cross rounds that have a pair to
+    // rotate, as in jac_inner)
     int need = 0;
     double offsq = 0.0;
     {
@@ -957,7 +982,10 @@ __global__ __launch_bounds__(NT) void jac_round_f32(int N, int nblk, int r, void
         for (int p = tid / B2; p < q; p += NT / B2) {
             const double g = (double)sm.in.G[0][p * LD + q];
             const double pq = (double)sm.in.G[0][p * LD + p] * gqq;
-            if (g * g > eps2 * pq && pq > 0.0 && (!cross || (p < H && q >= H))) need = 1;
+            if (g * g > eps2 * pq && pq > 0.0) {
+                if (!cross) need = 1;
+                else if (p < H && q >= H) need |= (int)(1u << ((q - H - p) & (H - 1)));
+            }
             if (pq > 0.0) offsq = fmax(offsq, g * g * __builtin_amdgcn_rcp(pq));
         }
     }
@@ -965,6 +993,7 @@ __global__ __launch_bounds__(NT) void jac_round_f32(int N, int nblk, int r, void
     offmax = wave_max(offmax);
     if (lane == 0) wmx[w] = offmax;
     need = block_or<NT>(need, ired);
+    const unsigned rmask = cross ? (unsigned)need : ~0u;
     if (part == 0 && tid == 0) {
         float m = 0.f;
 #pragma unroll
@@ -976,7 +1005,7 @@ __global__ __launch_bounds__(NT) void jac_round_f32(int N, int nblk, int r, void
     if (!need) return;   // nothing rotates: Y keeps this slot's columns
 
     // 6. rotations
-    float smax = inner_rounds<float, B2, NT>(sm.in.G, sm.in.W, ired, eps2, max_inner, cross);
+    float smax = inner_rounds<float, B2, NT>(sm.in.G, sm.in.W, ired, eps2, max_inner, cross, rmask);
     smax = wave_max(smax);
     if (lane == 0) wsm[w] = smax;
     __syncthreads();
