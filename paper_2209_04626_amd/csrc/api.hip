@@ -641,9 +641,7 @@ int run_svd(bool mixed, int m, int n, const double *A, int lda, double *S, doubl
         int *idx = (int *)(w + L.off_idx);
         float *dev = (float *)(idx + n);
         normalize_cols64(s, n, n, Y, N, Ulow, N);
-        gemm<double>(s, true, false, n, n, n, 1.0, Ulow, N, Ulow, N, 0.0, VX, n, q.split,
-                     q.split_elems, jw.kc);
-        colmax_offdiag(s, n, VX, n, dev);
+        gram_colmax_offdiag64(s, n, Ulow, N, dev);
         std::vector<float> hdev(n);
         if (read_back(s, hdev.data(), dev, (size_t)n * sizeof(float))) return SVD_ERR_HIP;
         float dmax = 0.f;

@@ -15,7 +15,9 @@ namespace mpj {
 
 constexpr int GBN = 64, GBK = 32;
 
-enum { EPI_STORE = 0, EPI_PART = 1, EPI_MAXDEV = 2 };
+// EPI_MAXDEV and EPI_COLMAX take C = A^T A (a Gram matrix, symmetric): only
+// the tiles on or above the block diagonal are formed.
+enum { EPI_STORE = 0, EPI_PART = 1, EPI_MAXDEV = 2, EPI_COLMAX = 3 };
 
 // BM x 64 output tile per 256-thread workgroup (BM = 64: 2 x 2 wavefronts of
 // 32 x 32; BM = 32, for the 32-row products of the blocked Householder
@@ -42,6 +44,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w / WN, wn = w % WN;
     const int i0 = blockIdx.x * BM, j0 = blockIdx.y * GBN;
+    if ((EPI == EPI_MAXDEV || EPI == EPI_COLMAX) && i0 > j0) return;   // the mirror tile covers it
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(K, kbeg + kchunk);
     typedef typename acc4<T>::type V4;
@@ -139,18 +142,41 @@ __global__ __launch_bounds__(256) void gemm_kernel(
                     Cs[wn * 16 * TJ + tj * 16 + lane % 16][wm * 32 + ti * 16 + mfma_row<T>(lane, r)] =
                         acc[ti][tj][r];
         __syncthreads();
+        if constexpr (EPI == EPI_COLMAX) {
+            // largest off-diagonal |c_ij| of each column j (and, through the
+            // symmetry, of each row i) of the tile, into maxdev[] (zeroed
+            // beforehand; non-negative floats order as their bit patterns).
+            // A NaN entry is passed over, as fmaxf does.
+            if (tid < 2 * GBN) {
+                const bool colw = tid < GBN;
+                const int x = tid % GBN;
+                const int gx = colw ? j0 + x : i0 + x;
+                float m = 0.f;
+                if (gx < (colw ? N : M)) {
+                    for (int y = 0; y < GBN; ++y) {
+                        const int gi = colw ? i0 + y : gx, gj = colw ? gx : j0 + y;
+                        if (gi < M && gj < N && gi != gj) {
+                            const float d = (float)fabs(alpha * (colw ? Cs[x][y] : Cs[y][x]));
+                            m = fmaxf(m, d);
+                        }
+                    }
+                    atomicMax((unsigned int *)maxdev + gx, __float_as_uint(m));
+                }
+            }
+        } else {
 #pragma unroll
-        for (int q = 0; q < BM * GBN / 256; ++q) {
-            const int e = tid + 256 * q;
-            const int i = e % BM, j = e / BM;
-            const int gi = i0 + i, gj = j0 + j;
-            if (gi < M && gj < N) {
-                const T v = alpha * Cs[j][i];
-                if (EPI == EPI_STORE) {
-                    T *c = C + (size_t)gj * ldc + gi;
-                    *c = (beta == T(0)) ? v : v + beta * (*c);
-                } else {
-                    part[(size_t)blockIdx.z * M * N + (size_t)gj * M + gi] = v;
+            for (int q = 0; q < BM * GBN / 256; ++q) {
+                const int e = tid + 256 * q;
+                const int i = e % BM, j = e / BM;
+                const int gi = i0 + i, gj = j0 + j;
+                if (gi < M && gj < N) {
+                    const T v = alpha * Cs[j][i];
+                    if (EPI == EPI_STORE) {
+                        T *c = C + (size_t)gj * ldc + gi;
+                        *c = (beta == T(0)) ? v : v + beta * (*c);
+                    } else {
+                        part[(size_t)blockIdx.z * M * N + (size_t)gj * M + gi] = v;
+                    }
                 }
             }
         }
@@ -256,6 +282,21 @@ void gemm_orth_maxdev(hipStream_t s, int n, const float *X, int ldx, float *maxd
     hipLaunchKernelGGL((gemm_kernel<float, true, false, EPI_MAXDEV, 64>), dim3(t, t, 1), dim3(256), 0, s,
                        n, n, n, 1.0f, X, ldx, X, ldx, 0.0f, (float *)nullptr, n, cdiv(n, GBK) * GBK,
                        (float *)nullptr, maxdev);
+}
+
+// Largest off-diagonal |c_ij| of each column of C = X^T X (n x n, FP64
+// columns), into dev[0 .. n-1] (FP32), without storing C.
+__global__ void k_zero_f32(int n, float *p) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = 0.f;
+}
+void gram_colmax_offdiag64(hipStream_t s, int n, const double *X, int ldx, float *dev) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero_f32, dim3(cdiv(n, 256)), dim3(256), 0, s, n, dev);
+    const int t = cdiv(n, 64);
+    hipLaunchKernelGGL((gemm_kernel<double, true, false, EPI_COLMAX, 64>), dim3(t, t, 1), dim3(256), 0,
+                       s, n, n, n, 1.0, X, ldx, X, ldx, 0.0, (double *)nullptr, n, cdiv(n, GBK) * GBK,
+                       (double *)nullptr, dev);
 }
 
 // The same for FP64 columns (the deviation is formed in FP64, its maximum

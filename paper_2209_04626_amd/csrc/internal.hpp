@@ -241,7 +241,7 @@ int jacobi_sweeps_cols(hipStream_t s, int N, int ncols, int b, T *Y, T *V, doubl
                        int maxsweep, int max_inner, JacobiWork &jw, int *conv);
 void scatter_cols(hipStream_t s, int rows, int n, const double *D, int ldd, const int *idx, double *A,
                   int lda);
-void colmax_offdiag(hipStream_t s, int n, const double *C, int ldc, float *dev);
+void gram_colmax_offdiag64(hipStream_t s, int n, const double *X, int ldx, float *dev);
 
 // ---------------------------------------------------------------- misc
 void copy_scan(hipStream_t s, int m, int n, const double *A, int lda,

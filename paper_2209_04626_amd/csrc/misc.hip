@@ -427,20 +427,4 @@ void scatter_cols(hipStream_t s, int rows, int n, const double *D, int ldd, cons
                        A, lda);
 }
 
-// dev[j] = max_{i != j} |C(i, j)|   (one wavefront per column)
-__global__ __launch_bounds__(256) void k_colmax_offdiag(int n, const double *C, int ldc, float *dev) {
-    const int lane = threadIdx.x & 63;
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (j >= n) return;
-    float m = 0.f;
-    for (int i = lane; i < n; i += 64)
-        if (i != j) m = fmaxf(m, (float)fabs(C[(size_t)j * ldc + i]));
-    m = wave_max(m);
-    if (lane == 0) dev[j] = m;
-}
-void colmax_offdiag(hipStream_t s, int n, const double *C, int ldc, float *dev) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_colmax_offdiag, dim3(cdiv(n, 4)), dim3(256), 0, s, n, C, ldc, dev);
-}
-
 } // namespace mpj
