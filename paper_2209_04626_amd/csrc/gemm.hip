@@ -8,6 +8,8 @@
 // staged through LDS in slices of 32 with the next slice prefetched into
 // registers.  Split-K writes partial products to scratch and a second kernel
 // sums them in a fixed order (deterministic).
+#include <type_traits>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -192,6 +194,116 @@ __global__ __launch_bounds__(256) void gemm_kernel(
     }
 }
 
+// FP64 products with a large output (C = alpha op(A) op(B) + beta C): a
+// 128 x 128 tile per 256-thread workgroup, 2 x 2 wavefronts of 64 x 64 (4 x 4
+// MFMA tiles each), so that each value staged in LDS feeds four times the
+// products of the 64 x 64 kernel.  K advances in slices of 16, double-buffered
+// in LDS: the next slice is loaded into registers while the matrix cores work
+// on the current one, then written to the other buffer (one barrier per
+// slice).  The operands go into the MFMA swapped (it forms the tile of C^T =
+// op(B)^T op(A)^T), which leaves lane l of each 16 x 16 tile holding rows
+// l % 16 of four columns of C: reads and writes of C cover 128 contiguous
+// bytes of a column per 16 lanes, with no staging.
+constexpr int G2M = 128, G2K = 16, G2LD = G2M + 1;
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256, 2) void gemm128_kernel(int M, int N, int K, double alpha,
+                                                         const double *__restrict__ A, int lda,
+                                                         const double *__restrict__ B, int ldb,
+                                                         double beta, double *C, int ldc) {
+    __shared__ double As[2][G2K][G2LD];
+    __shared__ double Bs[2][G2K][G2LD];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    const int i0 = blockIdx.x * G2M, j0 = blockIdx.y * G2M;
+    constexpr int PL = G2M * G2K / 256;      // values of each operand per thread and slice
+    double ra[PL], rb[PL];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < PL; ++u) {
+            int i, k;
+            if (!TA) { i = tid % G2M; k = tid / G2M + 2 * u; } else { k = tid % G2K; i = tid / G2K + 16 * u; }
+            const int gi = i0 + i, gk = k0 + k;
+            ra[u] = (gi < M && gk < K) ? (TA ? A[(size_t)gi * lda + gk] : A[(size_t)gk * lda + gi]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < PL; ++u) {
+            int j, k;
+            if (TB) { j = tid % G2M; k = tid / G2M + 2 * u; } else { k = tid % G2K; j = tid / G2K + 16 * u; }
+            const int gj = j0 + j, gk = k0 + k;
+            rb[u] = (gj < N && gk < K) ? (TB ? B[(size_t)gk * ldb + gj] : B[(size_t)gj * ldb + gk]) : 0.0;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < PL; ++u) {
+            int i, k;
+            if (!TA) { i = tid % G2M; k = tid / G2M + 2 * u; } else { k = tid % G2K; i = tid / G2K + 16 * u; }
+            As[buf][k][i] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < PL; ++u) {
+            int j, k;
+            if (TB) { j = tid % G2M; k = tid / G2M + 2 * u; } else { k = tid % G2K; j = tid / G2K + 16 * u; }
+            Bs[buf][k][j] = rb[u];
+        }
+    };
+    dbl4 acc[4][4];   // [tile along i][tile along j]
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = dbl4{0, 0, 0, 0};
+    const int ns = cdiv(K, G2K);
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int sl = 0; sl < ns; ++sl) {
+        const int cur = sl & 1;
+        if (sl + 1 < ns) load((sl + 1) * G2K);
+#pragma unroll
+        for (int kk = 0; kk < G2K; kk += 4) {
+            double xa[4], xb[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                xa[t] = As[cur][kk + lane / 16][wm * 64 + 16 * t + lane % 16];
+                xb[t] = Bs[cur][kk + lane / 16][wn * 64 + 16 * t + lane % 16];
+            }
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = mfma16(xb[tj], xa[ti], acc[ti][tj]);
+        }
+        if (sl + 1 < ns) store(cur ^ 1);
+        __syncthreads();
+    }
+    // lane l, element r of tile (ti, tj): C(i0 + 64 wm + 16 ti + l % 16, j0 + 64 wn + 16 tj + l / 16 + 4 r)
+    const int gi_l = i0 + wm * 64 + lane % 16;
+    const bool beta0 = beta == 0.0;
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti) {
+        const int gi = gi_l + 16 * ti;
+        double cv[4][4];
+        if (!beta0) {
+#pragma unroll
+            for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gj = j0 + wn * 64 + 16 * tj + lane / 16 + 4 * r;
+                    cv[tj][r] = (gi < M && gj < N) ? C[(size_t)gj * ldc + gi] : 0.0;
+                }
+        }
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gj = j0 + wn * 64 + 16 * tj + lane / 16 + 4 * r;
+                if (gi < M && gj < N) {
+                    const double v = alpha * acc[ti][tj][r];
+                    C[(size_t)gj * ldc + gi] = beta0 ? v : v + beta * cv[tj][r];
+                }
+            }
+    }
+}
+
 // C = sum_z part[z] + beta C, summed in z order.
 template <typename T>
 __global__ __launch_bounds__(256) void splitk_reduce(int M, int N, int nz,
@@ -229,6 +341,14 @@ static void gemm_launch_bm(hipStream_t s, int M, int N, int K, T alpha, const T 
     }
     int kchunk = cdiv(cdiv(K, nz), GBK) * GBK;
     nz = cdiv(K, kchunk);
+    if constexpr (std::is_same<T, double>::value && BM == 64) {
+        // enough 128 x 128 tiles to give every compute unit one
+        if (nz == 1 && (long long)cdiv(M, G2M) * cdiv(N, G2M) >= 240) {
+            hipLaunchKernelGGL((gemm128_kernel<TA, TB>), dim3(cdiv(M, G2M), cdiv(N, G2M)), dim3(256), 0, s,
+                               M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+            return;
+        }
+    }
     if (nz == 1) {
         hipLaunchKernelGGL((gemm_kernel<T, TA, TB, EPI_STORE, BM>), dim3(tm, tn, 1), dim3(256), 0, s,
                            M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, (T *)nullptr,
