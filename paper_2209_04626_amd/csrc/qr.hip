@@ -497,18 +497,41 @@ __global__ __launch_bounds__(256) void qr_apply_coop(int mp, int nb, const doubl
     const int g = blockIdx.x, G = gridDim.x;
     const int r0 = g * QA_RB;
     if (t == 0) bad = 0;
-    // rows of V (columns past nb zero) and of C (columns past ncol zero), T
-    for (int e = t; e < QA_RB * QR_NB; e += 256) {
-        const int i = e % QA_RB, k = e / QA_RB;
-        Vs[i * QA_LDV + k] = (r0 + i < mp && k < nb) ? V[(size_t)k * ldv + r0 + i] : 0.0;
-    }
-    for (int e = t; e < QA_RB * QA_NC; e += 256) {
-        const int i = e % QA_RB, c = e / QA_RB;
-        Cs[i * QA_LDC + c] = (r0 + i < mp && c < ncol) ? C[(size_t)c * ldc + r0 + i] : 0.0;
-    }
-    for (int e = t; e < QR_NB * QR_NB; e += 256) {
-        const int i = e % QR_NB, k = e / QR_NB;
-        Ts[i * QA_LDV + k] = (i < nb && k < nb) ? T[(size_t)k * ldt + i] : 0.0;
+    // rows of V (columns past nb zero) and of C (columns past ncol zero), T:
+    // every load of a thread in flight together, then the LDS stores
+    {
+        constexpr int NV = QA_RB * QR_NB / 256, NC = QA_RB * QA_NC / 256, NT = QR_NB * QR_NB / 256;
+        double rv[NV], rc[NC], rt[NT];
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+            const int e = t + 256 * u, i = e % QA_RB, k = e / QA_RB;
+            rv[u] = (r0 + i < mp && k < nb) ? V[(size_t)k * ldv + r0 + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NC; ++u) {
+            const int e = t + 256 * u, i = e % QA_RB, c = e / QA_RB;
+            rc[u] = (r0 + i < mp && c < ncol) ? C[(size_t)c * ldc + r0 + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int e = t + 256 * u, i = e % QR_NB, k = e / QR_NB;
+            rt[u] = (i < nb && k < nb) ? T[(size_t)k * ldt + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+            const int e = t + 256 * u;
+            Vs[(e % QA_RB) * QA_LDV + e / QA_RB] = rv[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NC; ++u) {
+            const int e = t + 256 * u;
+            Cs[(e % QA_RB) * QA_LDC + e / QA_RB] = rc[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int e = t + 256 * u;
+            Ts[(e % QR_NB) * QA_LDV + e / QR_NB] = rt[u];
+        }
     }
     for (int e = t; e < QR_NB * QA_LDC; e += 256) Ws[e] = 0.0;   // columns past ncol stay zero
     __syncthreads();
