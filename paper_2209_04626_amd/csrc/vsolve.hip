@@ -19,33 +19,48 @@ constexpr int TRSM_NB = 64;   // rows per diagonal block
 // triangular diagonal block L_kk (kb <= TB): one lane per right-hand side
 // column, the column in registers, the block in LDS (read as broadcasts).
 // Column-oriented forward substitution: after z_l is final, every later z_i
-// takes z_i - L_il z_l, so each lane has TB - l independent updates in flight.
+// takes z_i - L_il z_l, so each lane has TB - l independent updates in flight;
+// z_l itself is scaled by 1 / l_ll, formed once per block.  The block of B
+// goes through LDS so that its loads and stores run along the columns (lane =
+// row), every load of a lane in flight together.
 template <int TB>
 __global__ __launch_bounds__(64) void k_trsm_diag(int kb, int nrhs, const double *L, int ldl,
                                                   double *B, int ldb) {
+    static_assert(TB == 64, "one lane per row of the block");
     __shared__ double Ls[TB][TB];
-    const int t = threadIdx.x;
-    for (int l = 0; l < TB; ++l)
-        for (int i = t; i < TB; i += 64)
-            Ls[i][l] = (i < kb && l < kb && l <= i) ? L[(size_t)l * ldl + i] : 0.0;
+    __shared__ double Bs[TB][TB + 1];    // [column][row]
+    __shared__ double rinv[TB];
+    const int t = threadIdx.x, c0 = blockIdx.x * 64;
+    {
+        double v[TB];
+#pragma unroll
+        for (int l = 0; l < TB; ++l) v[l] = (t < kb && l < kb && l <= t) ? L[(size_t)l * ldl + t] : 0.0;
+#pragma unroll
+        for (int l = 0; l < TB; ++l) Ls[t][l] = v[l];
+        rinv[t] = t < kb ? 1.0 / Ls[t][t] : 0.0;   // this lane stored the row
+#pragma unroll
+        for (int j = 0; j < TB; ++j) v[j] = (t < kb && c0 + j < nrhs) ? B[(size_t)(c0 + j) * ldb + t] : 0.0;
+#pragma unroll
+        for (int j = 0; j < TB; ++j) Bs[j][t] = v[j];
+    }
     __syncthreads();
-    const int c = blockIdx.x * 64 + t;
-    if (c >= nrhs) return;
-    double *b = B + (size_t)c * ldb;
     double z[TB];
 #pragma unroll
-    for (int i = 0; i < TB; ++i) z[i] = i < kb ? b[i] : 0.0;
+    for (int i = 0; i < TB; ++i) z[i] = Bs[t][i];
 #pragma unroll
     for (int l = 0; l < TB; ++l) {
         if (l < kb) {
-            z[l] = z[l] / Ls[l][l];
+            z[l] *= rinv[l];
 #pragma unroll
             for (int i = l + 1; i < TB; ++i) z[i] = fma(-Ls[i][l], z[l], z[i]);
         }
     }
 #pragma unroll
-    for (int i = 0; i < TB; ++i)
-        if (i < kb) b[i] = z[i];
+    for (int i = 0; i < TB; ++i) Bs[t][i] = z[i];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < TB; ++j)
+        if (t < kb && c0 + j < nrhs) B[(size_t)(c0 + j) * ldb + t] = Bs[j][t];
 }
 
 // B (n x nrhs, ld ldb) <- L^{-1} B for lower triangular L (n x n, ld ldl):
