@@ -316,16 +316,23 @@ void normalize_f32_to_f64(hipStream_t s, int rows, int cols, const float *Y, int
 }
 
 // rank_j = #{i : s_i > s_j} + #{i < j : s_i == s_j}: a stable descending order.
-__global__ void k_rank(int n, const double *sig, int *rank) {
+// The values are read through LDS, 2048 at a time, by every workgroup.
+__global__ __launch_bounds__(256) void k_rank(int n, const double *sig, int *rank) {
+    __shared__ double sh[2048];
     const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    const double sj = sig[j];
+    const double sj = j < n ? sig[j] : 0.0;
     int r = 0;
-    for (int i = 0; i < n; ++i) {
-        const double si = sig[i];
-        r += (si > sj) || (si == sj && i < j);
+    for (int i0 = 0; i0 < n; i0 += 2048) {
+        const int m = min(2048, n - i0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < m; e += 256) sh[e] = sig[i0 + e];
+        __syncthreads();
+        for (int e = 0; e < m; ++e) {
+            const double si = sh[e];
+            r += (si > sj) || (si == sj && i0 + e < j);
+        }
     }
-    rank[j] = r;
+    if (j < n) rank[j] = r;
 }
 
 // Column j of Y / V goes to column rank_j of U_X / V_X (n x n, ld n).
