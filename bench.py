@@ -74,8 +74,6 @@ def algorithmic_flops(n: int, info: dict, mixed: bool, m: int | None = None) -> 
 TRAFFIC = {
     "qrcp": ("qrcp_persist_f32_n4096_traffic.md",
              ["paper_2209_04626_amd/csrc/qrcp.hip", "paper_2209_04626_amd/csrc/common.hpp"]),
-    "jac_update<f32>": ("jac_update_f32_n4096_traffic.md",
-                        ["paper_2209_04626_amd/csrc/jacobi.hip", "paper_2209_04626_amd/csrc/common.hpp"]),
     "qr_panel": ("qr_panel_coop_n4096_traffic.md",
                  ["paper_2209_04626_amd/csrc/qr.hip", "paper_2209_04626_amd/csrc/common.hpp"]),
     "jac_round<f32>": ("jac_round_f32_n4096_traffic.md",
