@@ -316,7 +316,8 @@ void normalize_f32_to_f64(hipStream_t s, int rows, int cols, const float *Y, int
 }
 
 // rank_j = #{i : s_i > s_j} + #{i < j : s_i == s_j}: a stable descending order.
-// The values are read through LDS, 2048 at a time, by every workgroup.
+// The values are read through LDS, 2048 at a time, by every workgroup (the
+// reads are broadcasts: every thread of a wavefront reads the same value).
 __global__ __launch_bounds__(256) void k_rank(int n, const double *sig, int *rank) {
     __shared__ double sh[2048];
     const int j = blockIdx.x * 256 + threadIdx.x;
@@ -327,7 +328,15 @@ __global__ __launch_bounds__(256) void k_rank(int n, const double *sig, int *ran
         __syncthreads();
         for (int e = threadIdx.x; e < m; e += 256) sh[e] = sig[i0 + e];
         __syncthreads();
-        for (int e = 0; e < m; ++e) {
+        int e = 0;
+        for (; e + 8 <= m; e += 8) {   // eight reads in flight
+            double si[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) si[u] = sh[e + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) r += (si[u] > sj) || (si[u] == sj && i0 + e + u < j);
+        }
+        for (; e < m; ++e) {
             const double si = sh[e];
             r += (si > sj) || (si == sj && i0 + e < j);
         }
