@@ -188,6 +188,33 @@ def test_gram_chunks_not_multiple_of_256(lib):
         assert rel < 1e-11, (mode, rel)
 
 
+def test_tall_ragged_large(lib):
+    """5000 x 2100: a tall QR whose panels, in-block updates and 128 x 128
+    GEMM tiles all end in partial tiles (5000 and 2100 are not multiples of
+    64 or 128), the fused FP32 round on a padded 2112-column Y, and the
+    switch's product on ragged tiles.  sigma geometric in [1e-3, 1] stands in
+    for the oracle's, as in the n = 4160 case."""
+    import torch
+    m, n = 5000, 2100
+    print(f"case tall m={m} n={n}", flush=True)
+    rng = np.random.default_rng(5021)
+    s = testmats.sigma_geometric(n, 3.0)
+    A = testmats.compose(testmats.haar(rng, m, n), s, testmats.haar(rng, n, n))
+    At = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    eye = torch.eye(n, dtype=torch.float64, device="cuda")
+    for mode in ("mixed", "plain"):
+        U, S, V, info = lib.svd(At, mode, branch=1 if mode == "mixed" else 0, fused_rounds=1)
+        torch.cuda.synchronize()
+        assert info["status"] == 0, info
+        orth_u = torch.linalg.norm(U.t() @ U - eye).item()
+        orth_v = torch.linalg.norm(V.t() @ V - eye).item()
+        res = (torch.linalg.norm(At - (U * S) @ V.t()) / torch.linalg.norm(At)).item()
+        rel = np.max(np.abs(S.cpu().numpy() - s) / s)
+        print(mode, {"orth_u": orth_u, "orth_v": orth_v, "res": res, "rel": rel}, flush=True)
+        assert orth_u <= 1e-13 * n and orth_v <= 1e-13 * n and res <= 1e-14 * n, (mode, orth_u, orth_v, res)
+        assert rel < 1e-11, (mode, rel)
+
+
 def graded(m, n, seed, e=8.0, d=4.0):
     """A = B diag(10^w), w ~ U(-d, 0): badly scaled columns over a B with
     log-uniform sigma (the A = B D family)."""
